@@ -1,0 +1,139 @@
+"""FP64 CPU oracle for the Cholesky-vector particle-particle ladder.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library imports this package: only
+the test-suite, the smoke check and the CPU-baseline leg of the benchmark may
+call it.  It shares no code with the HIP path.
+
+What it computes (arXiv 2310.04559):
+
+* eq. (cholesky): the four-index integral is factorised through one set of
+  Cholesky vectors, ``V[a,c,b,d] = (ac|bd) = sum_x L[x,a,c] L[x,b,d]``.
+* eq. (vfunction): the ladder term of the doubles vector function,
+  ``R[i,j,a,b] += sum_{c,d} V[a,c,b,d] t[i,j,c,d]``.
+* The adjoint of that term for ``Loss = sum_{ijab} lam[i,j,a,b] R[i,j,a,b]``:
+  ``dt[i,j,c,d] = sum_{a,b} lam[i,j,a,b] V[a,c,b,d]``;
+  with ``W[a,b,c,d] = sum_{i,j} lam[i,j,a,b] t[i,j,c,d]``,
+  ``dL[x,p,q] = sum_{b,d} W[p,b,q,d] L[x,b,d] + sum_{a,c} W[a,p,c,q] L[x,a,c]``
+  (entrywise gradient: each array entry of L is an independent variable).
+
+Algorithm: the paper's loop over one virtual index (Sec. "Pythonic
+implementations of the CC vector function", the tensordot variant that keeps
+intermediates at v^3): for each ``a`` the slice ``V[a,:,:,:]`` is built from
+the Cholesky vectors and contracted with the amplitudes.  Each step is one
+library matrix product in float64; there is no further blocking or fusion.
+
+Layouts: ``L[x][p][q]`` (the virtual-virtual block), ``t, R, lam[i][j][a][b]``,
+all float64 C-contiguous.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_loss",
+           "reduce_dot", "eri_slice", "nominal_flops_forward", "nominal_flops_backward"]
+
+
+def _check(L, t):
+    L = np.asarray(L, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    if L.ndim != 3 or L.shape[1] != L.shape[2]:
+        raise ValueError("L must be [P][v][v]")
+    if t.ndim != 4 or t.shape[0] != t.shape[1] or t.shape[2] != t.shape[3]:
+        raise ValueError("t must be [o][o][v][v]")
+    if t.shape[2] != L.shape[1]:
+        raise ValueError("L and t disagree on v")
+    return L, t
+
+
+def eri_slice(L: np.ndarray, a: int) -> np.ndarray:
+    """``V[a, c, b, d]`` for one fixed ``a``, returned as ``[b][c][d]``
+    (eq. cholesky restricted to one virtual index)."""
+    P, v, _ = L.shape
+    # [c][(b,d)] = sum_x L[x,a,c] * L[x,b,d]
+    Vc_bd = L[:, a, :].T @ L.reshape(P, v * v)
+    return Vc_bd.reshape(v, v, v).transpose(1, 0, 2)
+
+
+def ladder_forward(L, t, R=None, a_begin: int = 0, a_end=None) -> np.ndarray:
+    """``R[i,j,a,b] += sum_{c,d} (ac|bd) t[i,j,c,d]`` (eq. vfunction).
+
+    ``R`` is accumulated in place when given, else a zero array is made.
+    ``[a_begin, a_end)`` restricts the loop over ``a`` (a bounded sample)."""
+    L, t = _check(L, t)
+    P, v, _ = L.shape
+    o = t.shape[0]
+    if R is None:
+        R = np.zeros((o, o, v, v))
+    a_end = v if a_end is None else a_end
+    T = t.reshape(o * o, v * v)                       # [(i,j)][(c,d)]
+    for a in range(a_begin, a_end):
+        Va = eri_slice(L, a)                          # [b][c][d]
+        # R[(i,j), a, b] += sum_{(c,d)} T[(i,j),(c,d)] * Va[b,(c,d)]
+        R[:, :, a, :] += (T @ Va.reshape(v, v * v).T).reshape(o, o, v)
+    return R
+
+
+def ladder_backward(L, t, lam):
+    """Entrywise gradients ``(dL, dt)`` of ``sum lam * R`` with R the ladder
+    term; one pass over ``a`` as in the forward, V[a] rebuilt, not stored."""
+    L, t = _check(L, t)
+    lam = np.asarray(lam, dtype=np.float64)
+    P, v, _ = L.shape
+    o = t.shape[0]
+    if lam.shape != t.shape:
+        raise ValueError("lam must match t")
+    T = t.reshape(o * o, v * v)
+    Lf = L.reshape(P, v * v)
+    dt = np.zeros((o * o, v * v))
+    dL = np.zeros((P, v, v))
+    for a in range(v):
+        Va = eri_slice(L, a)                          # [b][c][d]
+        lam_a = lam[:, :, a, :].reshape(o * o, v)     # [(i,j)][b]
+        # dt[(i,j),(c,d)] += sum_b lam[i,j,a,b] V[a,c,b,d]
+        dt += lam_a @ Va.reshape(v, v * v)
+        # W[a,b,(c,d)] = sum_{(i,j)} lam[i,j,a,b] t[i,j,c,d]
+        Wa = (lam_a.T @ T).reshape(v, v, v)          # [b][c][d]
+        Wa_cbd = Wa.transpose(1, 0, 2).reshape(v, v * v)   # [c][(b,d)]
+        # first term: dL[x,a,c] += sum_{b,d} L[x,b,d] W[a,b,c,d]
+        dL[:, a, :] += Lf @ Wa_cbd.T
+        # second term: dL[x,b,d] += sum_c L[x,a,c] W[a,b,c,d]
+        dL += (L[:, a, :] @ Wa_cbd).reshape(P, v, v)
+    return dL, dt.reshape(o, o, v, v)
+
+
+def ladder_pairs(L, t, pairs) -> np.ndarray:
+    """``R[:, :, a, b]`` of the ladder term for each ``(a, b)`` in ``pairs``,
+    one at a time from the definition: ``V[a,:,b,:]`` from eq. cholesky, then
+    the (c,d) sum of eq. vfunction.  Returns ``[len(pairs)][o][o]``."""
+    L, t = _check(L, t)
+    P, v, _ = L.shape
+    o = t.shape[0]
+    T = t.reshape(o * o, v * v)
+    out = np.empty((len(pairs), o, o))
+    for k, (a, b) in enumerate(pairs):
+        Vab = L[:, a, :].T @ L[:, b, :]               # [c][d]
+        out[k] = (T @ Vab.reshape(v * v)).reshape(o, o)
+    return out
+
+
+def ladder_loss(lam, R) -> float:
+    """``sum_{ijab} lam[i,j,a,b] R[i,j,a,b]``."""
+    return float(np.dot(np.ravel(lam), np.ravel(R)))
+
+
+def reduce_dot(x, y):
+    """``(sum x*y, sum y*y)`` in float64."""
+    xf = np.ravel(np.asarray(x, dtype=np.float64))
+    yf = np.ravel(np.asarray(y, dtype=np.float64))
+    return float(np.dot(xf, yf)), float(np.dot(yf, yf))
+
+
+def nominal_flops_forward(o: int, v: int, P: int) -> float:
+    """Factorised cost of one forward: 2 P v^4 (integral slices) + 2 o^2 v^4
+    (amplitude contraction)."""
+    return 2.0 * (P + o * o) * float(v) ** 4
+
+
+def nominal_flops_backward(o: int, v: int, P: int) -> float:
+    """Rebuild (2Pv^4) + dt (2o^2v^4) + W (2o^2v^4) + two dL terms (2Pv^4 each)."""
+    return (6.0 * P + 4.0 * o * o) * float(v) ** 4

@@ -1,0 +1,327 @@
+"""Pins for the FP64 oracle, independent of the oracle's own code path.
+
+Each test fixes the oracle against something the paper or mathematics settles:
+exact integer brute force, closed forms, symmetries the paper states for real
+orbitals, invariants of the quadratic loss, and the paper's printed table of
+problem sizes.  All run on the CPU.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_04559_amd.inputs import (CONFIGS, integer_inputs, make_inputs, paper_shape,
+                                         random_general, seed_for)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel_fro(x, ref):
+    return float(np.linalg.norm(np.ravel(x - ref)) / np.linalg.norm(np.ravel(ref)))
+
+
+# ---------------------------------------------------------------------------
+# exact brute force in Python integers (definitions of eq. cholesky/vfunction)
+# ---------------------------------------------------------------------------
+
+def _int_ladder(L, t):
+    P, v = len(L), len(L[0])
+    o = len(t)
+    R = [[[[0] * v for _ in range(v)] for _ in range(o)] for _ in range(o)]
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        s = 0
+        for c, d in itertools.product(range(v), range(v)):
+            V = sum(L[x][a][c] * L[x][b][d] for x in range(P))
+            s += V * t[i][j][c][d]
+        R[i][j][a][b] = s
+    return R
+
+
+def _int_loss(L, t, lam):
+    R = _int_ladder(L, t)
+    o, v = len(t), len(L[0])
+    return sum(lam[i][j][a][b] * R[i][j][a][b]
+               for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)))
+
+
+def _to_int(x):
+    return np.asarray(x).astype(np.int64).tolist()
+
+
+@pytest.mark.parametrize("o,v,P,seed", [(2, 3, 2, 11), (3, 4, 3, 12), (1, 5, 1, 13)])
+def test_forward_equals_integer_bruteforce(o, v, P, seed):
+    L, t = integer_inputs(o, v, P, seed)
+    exact = np.array(_int_ladder(_to_int(L), _to_int(t)), dtype=np.float64)
+    got = oracle.ladder_forward(L, t)
+    assert np.array_equal(got, exact)  # every partial sum is a small integer: exact
+
+
+def test_backward_equals_exact_differences():
+    # Loss is linear in t and quadratic in L: integer central differences with
+    # step 1 give the exact entrywise gradient.
+    o, v, P = 2, 3, 2
+    L, t = integer_inputs(o, v, P, 21)
+    lam = np.random.default_rng(22).integers(-2, 3, size=(o, o, v, v)).astype(np.float64)
+    Li, ti, lami = _to_int(L), _to_int(t), _to_int(lam)
+    dL_ref = np.zeros((P, v, v))
+    for x, p, q in itertools.product(range(P), range(v), range(v)):
+        Lp = [[row[:] for row in m] for m in Li]
+        Lm = [[row[:] for row in m] for m in Li]
+        Lp[x][p][q] += 1
+        Lm[x][p][q] -= 1
+        diff = _int_loss(Lp, ti, lami) - _int_loss(Lm, ti, lami)
+        assert diff % 2 == 0
+        dL_ref[x, p, q] = diff // 2
+    dt_ref = np.zeros((o, o, v, v))
+    base = _int_loss(Li, ti, lami)
+    for i, j, c, d in itertools.product(range(o), range(o), range(v), range(v)):
+        tp = [[[row[:] for row in m] for m in blk] for blk in ti]
+        tp[i][j][c][d] += 1
+        dt_ref[i, j, c, d] = _int_loss(Li, tp, lami) - base
+    dL, dt = oracle.ladder_backward(L, t, lam)
+    assert np.array_equal(dL, dL_ref)
+    assert np.array_equal(dt, dt_ref)
+
+
+# ---------------------------------------------------------------------------
+# closed forms
+# ---------------------------------------------------------------------------
+
+def test_single_vector_closed_form():
+    # P = 1: V[a,c,b,d] = l[a,c] l[b,d], so R[i,j] = l @ t[i,j] @ l^T.
+    rng = np.random.default_rng(31)
+    o, v = 3, 7
+    ell = rng.standard_normal((v, v))           # deliberately non-symmetric
+    t = rng.standard_normal((o, o, v, v))
+    got = oracle.ladder_forward(ell[None], t)
+    ref = np.empty_like(t)
+    for i in range(o):
+        for j in range(o):
+            ref[i, j] = ell @ t[i, j] @ ell.T
+    assert rel_fro(got, ref) < 1e-14
+
+
+def test_identity_vector_returns_t():
+    rng = np.random.default_rng(32)
+    o, v = 3, 6
+    t = rng.standard_normal((o, o, v, v))
+    got = oracle.ladder_forward(np.eye(v)[None], t)
+    assert np.array_equal(got, t)
+
+
+def test_rank_one_amplitudes_closed_form():
+    # t[i,j,c,d] = alpha[i,j] u[c] w[d]  ->  R[i,j,a,b] = alpha[i,j] sum_x (L_x u)[a] (L_x w)[b]
+    rng = np.random.default_rng(33)
+    o, v, P = 2, 6, 5
+    L = rng.standard_normal((P, v, v))
+    alpha = rng.standard_normal((o, o))
+    u, w = rng.standard_normal(v), rng.standard_normal(v)
+    t = alpha[:, :, None, None] * u[None, None, :, None] * w[None, None, None, :]
+    M = sum(np.outer(L[x] @ u, L[x] @ w) for x in range(P))
+    ref = alpha[:, :, None, None] * M[None, None]
+    assert rel_fro(oracle.ladder_forward(L, t), ref) < 1e-14
+
+
+def test_explicit_eri_of_all_orbitals_c1():
+    # The c1 workload evaluated through an explicitly stored four-index integral:
+    # the generator's full L over n = o+v orbitals is rebuilt, the n^4 tensor is
+    # formed, and its virtual block is contracted one (i,j,a,b) at a time.
+    o, v, P = CONFIGS["c1"]
+    inp = make_inputs(o, v, P, seed_for("c1"))
+    rng = np.random.default_rng(seed_for("c1"))
+    n = o + v
+    X = rng.standard_normal((P, n, n))
+    Lfull = np.triu(X) + np.transpose(np.triu(X, 1), (0, 2, 1))
+    Lfull *= (np.exp(-np.arange(P) / 25.0) / np.sqrt(n))[:, None, None]
+    assert np.array_equal(Lfull[:, o:, o:], inp.L_vv)
+    eri = np.einsum("xpq,xrs->pqrs", Lfull, Lfull)          # (pq|rs), n^4
+    vv = eri[o:, o:, o:, o:]                                  # (ac|bd) as [a][c][b][d]
+    ref = np.empty((o, o, v, v))
+    for a in range(v):
+        for b in range(v):
+            ref[:, :, a, b] = np.tensordot(inp.t, vv[a, :, b, :], axes=([2, 3], [0, 1]))
+    assert rel_fro(oracle.ladder_forward(inp.L_vv, inp.t), ref) < 1e-13
+
+
+def test_papers_one_shot_formulation_c1():
+    # The paper's one-shot form keeps amplitudes as t[i,c,j,d] and writes
+    # t_new[i,a,j,b] (Sec. "einsum and opt_einsum").
+    o, v, P = CONFIGS["c1"]
+    inp = make_inputs(o, v, P, seed_for("c1"))
+    t_paper = inp.t.transpose(0, 2, 1, 3)
+    out_paper = np.einsum("xac,xbd,icjd->iajb", inp.L_vv, inp.L_vv, t_paper, optimize=True)
+    got = oracle.ladder_forward(inp.L_vv, inp.t)
+    assert rel_fro(got, out_paper.transpose(0, 2, 1, 3)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# symmetries and invariants
+# ---------------------------------------------------------------------------
+
+def test_integral_permutational_symmetry():
+    # Real orbitals: (ac|bd) = (ca|db) = (bd|ac) when every Cholesky vector is symmetric.
+    inp = make_inputs(3, 9, 20, 41)
+    v = inp.v
+    V = np.stack([oracle.eri_slice(inp.L_vv, a) for a in range(v)])  # [a][b][c][d]
+    Vacbd = V.transpose(0, 2, 1, 3)
+    assert np.max(np.abs(Vacbd - Vacbd.transpose(1, 0, 3, 2))) < 1e-15
+    assert np.max(np.abs(Vacbd - Vacbd.transpose(2, 3, 0, 1))) < 1e-15
+
+
+def test_pair_symmetry_of_result():
+    inp = make_inputs(4, 10, 30, 42)
+    tscale = np.max(np.abs(inp.t))
+    assert np.max(np.abs(inp.t - inp.t.transpose(1, 0, 3, 2))) <= 1e-15 * tscale
+    R = oracle.ladder_forward(inp.L_vv, inp.t)
+    scale = np.max(np.abs(R))
+    assert np.max(np.abs(R - R.transpose(1, 0, 3, 2))) <= 1e-14 * scale
+
+
+def test_linearity_and_homogeneity():
+    L, t, lam = random_general(3, 7, 6, 43)
+    R1 = oracle.ladder_forward(L, t)
+    R2 = oracle.ladder_forward(L, lam)
+    assert rel_fro(oracle.ladder_forward(L, 2.0 * t - 3.0 * lam), 2.0 * R1 - 3.0 * R2) < 1e-14
+    assert rel_fro(oracle.ladder_forward(1.5 * L, t), 2.25 * R1) < 1e-14
+
+
+def test_accumulates_and_range_split():
+    L, t, _ = random_general(3, 8, 5, 44)
+    R0 = np.random.default_rng(45).standard_normal(t.shape)
+    full = oracle.ladder_forward(L, t)
+    acc = oracle.ladder_forward(L, t, R=R0.copy())
+    assert rel_fro(acc, R0 + full) < 1e-14
+    part = oracle.ladder_forward(L, t, a_begin=0, a_end=3)
+    part = oracle.ladder_forward(L, t, R=part, a_begin=3)
+    assert np.array_equal(part, full)
+    head = oracle.ladder_forward(L, t, a_end=3)
+    assert np.all(head[:, :, 3:, :] == 0)
+
+
+def test_pairs_match_forward():
+    L, t, _ = random_general(3, 9, 7, 46)
+    full = oracle.ladder_forward(L, t)
+    pairs = [(0, 0), (8, 1), (4, 4), (2, 7)]
+    got = oracle.ladder_pairs(L, t, pairs)
+    for k, (a, b) in enumerate(pairs):
+        assert rel_fro(got[k], full[:, :, a, b]) < 1e-14
+
+
+def test_mp2_identity_of_generator():
+    # sum t*(ia|jb) equals sum (ia|jb)^2 / D with D built independently.
+    inp = make_inputs(6, 30, 90, 47)
+    e_o, e_v = inp.e_occ, inp.e_vir
+    lhs = float(np.sum(inp.t * inp.ovov))
+    rhs = 0.0
+    for i in range(inp.o):
+        for j in range(inp.o):
+            D = e_o[i] + e_o[j] - e_v[:, None] - e_v[None, :]
+            assert np.all(D < -0.8 + 1e-12)
+            rhs += float(np.sum(inp.ovov[i, j] ** 2 / D))
+    assert abs(lhs - rhs) <= 1e-13 * abs(rhs)
+    # the generator's (ia|jb) is the ov block of the same symmetric Cholesky vectors
+    gscale = np.max(np.abs(inp.ovov))
+    assert np.max(np.abs(inp.ovov - inp.ovov.transpose(1, 0, 3, 2))) <= 1e-15 * gscale
+
+
+def test_generator_structure():
+    inp = make_inputs(3, 8, 40, 48, with_lambda=True)
+    assert np.array_equal(inp.L_vv, inp.L_vv.transpose(0, 2, 1))
+    # exp(-x/25) decay of the Cholesky vectors
+    norms = np.linalg.norm(inp.L_vv.reshape(40, -1), axis=1)
+    assert norms[39] < norms[0] * np.exp(-39 / 25.0) * 4
+    assert np.array_equal(inp.lam, inp.lam.transpose(1, 0, 3, 2))
+    assert np.all(np.diff(inp.e_occ) >= 0) and np.all(np.diff(inp.e_vir) >= 0)
+    again = make_inputs(3, 8, 40, 48, with_lambda=True)
+    assert np.array_equal(again.t, inp.t) and np.array_equal(again.lam, inp.lam)
+
+
+# ---------------------------------------------------------------------------
+# adjoint invariants
+# ---------------------------------------------------------------------------
+
+def test_euler_identities_and_self_adjointness():
+    # Loss is homogeneous of degree 1 in t and 2 in L:
+    #   <dt, t> = Loss,  <dL, L> = 2 Loss.
+    inp = make_inputs(4, 12, 40, 51, with_lambda=True)
+    L, t, lam = inp.L_vv, inp.t, inp.lam
+    R = oracle.ladder_forward(L, t)
+    loss = oracle.ladder_loss(lam, R)
+    dL, dt = oracle.ladder_backward(L, t, lam)
+    assert abs(np.sum(dt * t) - loss) <= 1e-13 * abs(loss)
+    assert abs(np.sum(dL * L) - 2 * loss) <= 1e-13 * abs(loss)
+    # symmetric Cholesky vectors make the ladder self-adjoint: dt = Ladder(lam)
+    assert rel_fro(dt, oracle.ladder_forward(L, lam)) < 1e-13
+
+
+def test_general_gradient_unsymmetric_inputs():
+    # Euler identities hold for any L, t, lam; the two dL terms differ here.
+    L, t, lam = random_general(3, 8, 6, 52)
+    R = oracle.ladder_forward(L, t)
+    loss = oracle.ladder_loss(lam, R)
+    dL, dt = oracle.ladder_backward(L, t, lam)
+    assert abs(np.sum(dt * t) - loss) <= 1e-13 * abs(loss)
+    assert abs(np.sum(dL * L) - 2 * loss) <= 1e-13 * abs(loss)
+
+
+def test_gradient_central_differences():
+    # Quadratic in L and linear in t: central differences have no truncation
+    # error, only rounding of order u*|Loss|/h.
+    inp = make_inputs(4, 12, 40, 53, with_lambda=True)
+    L, t, lam = inp.L_vv, inp.t, inp.lam
+    dL, dt = oracle.ladder_backward(L, t, lam)
+
+    def loss_of(Lx, tx):
+        return oracle.ladder_loss(lam, oracle.ladder_forward(Lx, tx))
+
+    rng = np.random.default_rng(54)
+    h = 1e-6
+    gmax_L, gmax_t = np.max(np.abs(dL)), np.max(np.abs(dt))
+    for _ in range(10):
+        x, p, q = int(rng.integers(0, 40)), int(rng.integers(0, 12)), int(rng.integers(0, 12))
+        Lp, Lm = L.copy(), L.copy()
+        Lp[x, p, q] += h
+        Lm[x, p, q] -= h
+        fd = (loss_of(Lp, t) - loss_of(Lm, t)) / (2 * h)
+        assert abs(fd - dL[x, p, q]) <= 1e-6 * abs(dL[x, p, q]) + 1e-8 * gmax_L
+        idx = tuple(int(rng.integers(0, s)) for s in t.shape)
+        tp, tm = t.copy(), t.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        fd = (loss_of(L, tp) - loss_of(L, tm)) / (2 * h)
+        assert abs(fd - dt[idx]) <= 1e-6 * abs(dt[idx]) + 1e-8 * gmax_t
+    # directional derivatives with h = 1: exact for the quadratic dependence on
+    # L and the linear dependence on t (taken separately; jointly it is cubic)
+    base = abs(loss_of(L, t))
+    dirL = rng.standard_normal(L.shape) * 1e-2
+    fd = (loss_of(L + dirL, t) - loss_of(L - dirL, t)) / 2.0
+    an = np.sum(dL * dirL)
+    assert abs(fd - an) <= 1e-13 * (abs(an) + base)
+    dirt = rng.standard_normal(t.shape) * 1e-3
+    fd = (loss_of(L, t + dirt) - loss_of(L, t - dirt)) / 2.0
+    an = np.sum(dt * dirt)
+    assert abs(fd - an) <= 1e-13 * (abs(an) + base)
+
+
+# ---------------------------------------------------------------------------
+# paper-printed values
+# ---------------------------------------------------------------------------
+
+def test_paper_problem_size_table():
+    rows = [list(map(int, line.split())) for line in open(os.path.join(GOLDEN, "tbl_timing.txt"))
+            if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for K, n_ladder, n_o3v in rows:
+        o, v, x = paper_shape(K)
+        assert o * o * v * v == n_ladder
+        assert o ** 3 * v == n_o3v
+        assert x == 5 * K
+
+
+def test_reduce_and_flops():
+    x = np.arange(10.0)
+    y = np.ones(10) * 2
+    assert oracle.reduce_dot(x, y) == (90.0, 40.0)
+    assert oracle.nominal_flops_forward(40, 360, 1200) == pytest.approx(94.06e12, rel=1e-3)
