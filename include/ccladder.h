@@ -1,0 +1,120 @@
+/*
+ * ccladder.h -- C ABI of the MI355X (gfx950) particle-particle ladder library.
+ *
+ * The library evaluates the bottleneck term of the Cholesky-vector CCD/CCSD
+ * doubles vector function of arXiv 2310.04559:
+ *
+ *   (ac|bd) = V[a,c,b,d] = sum_x L[x,a,c] L[x,b,d]          (eq. cholesky)
+ *   R[i,j,a,b] += sum_{c,d} V[a,c,b,d] t[i,j,c,d]           (eq. vfunction)
+ *
+ * The four-index integral is never stored whole: it is rebuilt in blocks of
+ * the first virtual index a (the paper's loop over one virtual index,
+ * Sec. "tensordot", generalised to blocks sized to device memory as in
+ * Sec. "CuPy and batch-wise computations").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Tensor pointers are DEVICE pointers to float64, C-contiguous:
+ *     L   [P][v][v]      virtual-virtual block of the Cholesky vectors
+ *     t   [o][o][v][v]   t[i][j][c][d]
+ *     R   [o][o][v][v]   R[i][j][a][b]
+ *   The caller owns all of them; the library never frees caller memory.
+ * - Results are ACCUMULATED (+=) into R, dL and dt; zero them for the bare term.
+ * - Calls enqueue work on `stream` (NULL = the legacy default stream) and
+ *   return without a host synchronisation.  Kernel faults surface at the
+ *   caller's next synchronisation of that stream.
+ * - Return value: 0 on success, else one of the negative CC_LADDER_E* codes.
+ *   Nothing throws across the ABI.  On an error return no kernel has been
+ *   enqueued and the outputs are untouched.
+ * - Internal scratch: taken from opts->workspace when given, otherwise
+ *   allocated with hipMallocAsync on `stream` and released with hipFreeAsync
+ *   on the same stream before return.
+ */
+#ifndef CCLADDER_H
+#define CCLADDER_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define CC_LADDER_OK            0
+#define CC_LADDER_EINVAL       -1   /* bad dimension, null/aliased pointer, unknown precision or option */
+#define CC_LADDER_ENOMEM       -2   /* not even a one-virtual block fits the budget / workspace too small */
+#define CC_LADDER_ENODEV       -3   /* no gfx950 device is current */
+#define CC_LADDER_EHIP         -4   /* a HIP runtime call failed */
+#define CC_LADDER_EUNSUPPORTED -5   /* valid request this build does not implement */
+
+/* Arithmetic of the two contractions.  Sources and results are always float64. */
+typedef enum {
+  CC_LADDER_FP64 = 0,        /* float64 MFMA throughout */
+  CC_LADDER_FP32 = 1,        /* float32 operands and MFMA, float32 partial sums drained to float64 */
+  CC_LADDER_SPLIT_BF16 = 2   /* operands cut into bf16 slices on shared per-row exponents; slice
+                                products on bf16 MFMA, exact float32 chunks drained to float64 */
+} cc_ladder_precision;
+
+/* Optional controls; a zero-initialised struct (or NULL) selects everything automatically. */
+typedef struct {
+  int    a_block;          /* virtuals per integral block; 0 = largest that fits hbm_budget */
+  int    split_slices;     /* SPLIT_BF16 slice count s in [2, 6]; 0 = 4.  Products kept: p+q <= s+1 */
+  int    k_chunk;          /* FP32 drain interval along the contracted index (multiple of 64); 0 = 512 */
+  int    reserved;         /* must be 0 */
+  size_t hbm_budget;       /* bytes the library may use for scratch; 0 = half the free device memory */
+  void*  workspace;        /* caller scratch (device, 256-byte aligned) or NULL */
+  size_t workspace_bytes;  /* its size; the plan must fit in it */
+} cc_ladder_opts;
+
+/*
+ * Ladder term (eq. vfunction with eq. cholesky):
+ *   R[i][j][a][b] += sum_{c,d} ( sum_x L[x][a][c] L[x][b][d] ) t[i][j][c][d]
+ * o, v, P > 0.  R must not overlap L or t.
+ */
+int cc_ladder_residual(int o, int v, int P,
+                       const double* L, const double* t, double* R,
+                       int precision, hipStream_t stream, const cc_ladder_opts* opts);
+
+/*
+ * Adjoint of the ladder term for Loss = sum lam[i][j][a][b] R[i][j][a][b]
+ * (lam = dLoss/dR, any values, pair symmetry not assumed):
+ *   dt[i][j][c][d] += sum_{a,b} lam[i][j][a][b] V[a,c,b,d]
+ *   dL[x][p][q]    += sum_{b,d} W[p,b,q,d] L[x][b][d] + sum_{a,c} W[a,p,c,q] L[x][a][c]
+ *   with W[a,b,c,d] = sum_{i,j} lam[i][j][a][b] t[i][j][c][d].
+ * dL is the entrywise gradient (each entry of L independent).  Integral
+ * blocks are rebuilt, not stored.  dL/dt must not overlap any input.
+ */
+int cc_ladder_backward(int o, int v, int P,
+                       const double* L, const double* t, const double* lam,
+                       double* dL, double* dt,
+                       int precision, hipStream_t stream, const cc_ladder_opts* opts);
+
+/*
+ * float64 reductions over n = o*o*v*v entries, as used for the energy-like
+ * functional and norms of the vector function:
+ *   out_dev[0] = sum x*y,  out_dev[1] = sum y*y        (out_dev: device, 2 doubles)
+ * Deterministic for a given device and size.
+ */
+int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out_dev,
+                     hipStream_t stream);
+
+/*
+ * Host-only planner query (needs no device): the scratch bytes and the
+ * integral block (virtuals per block) that cc_ladder_residual (backward = 0)
+ * or cc_ladder_backward (backward = 1) would use under `hbm_budget` bytes
+ * (0 = no limit, i.e. the whole virtual range in one block).  `opts` may be
+ * NULL; its a_block and split_slices are honoured, its budget fields are not.
+ */
+int cc_ladder_workspace_query(int o, int v, int P, int precision, int backward,
+                              size_t hbm_budget, const cc_ladder_opts* opts,
+                              size_t* bytes, int* a_block);
+
+/* Static description of an error code (never NULL). */
+const char* cc_ladder_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCLADDER_H */

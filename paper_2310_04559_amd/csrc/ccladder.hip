@@ -1,0 +1,406 @@
+// C ABI of the MI355X ladder library: argument checks, planning, scratch,
+// and the stream-ordered schedule of the MFMA kernels.
+//
+// Forward (eq. cholesky + eq. vfunction), per block A of first virtuals:
+//   build    V_A[a][b][c][d] = sum_x L[x][a][c] L[x][b][d]     GEMM M=(a,c) N=(b,d) K=x
+//   contract R[(ij)][(a b)] += sum_(cd) t[(ij)][(cd)] V_A[(ab)][(cd)]   GEMM M=ij N=(a,b) K=(c,d)
+// Adjoint, per block, with V_A rebuilt:
+//   dt[(ij)][(cd)] += sum_(a in A, b) lam[(ij)][(ab)] V_A[(ab)][(cd)]
+//   W'_A[a][c][b][d] = sum_(ij) lam[(ij)][(ab)] t[(ij)][(cd)]
+//   dL[x][(a c)]  += sum_(bd) L[x][(bd)] W'_A[(ac)][(bd)]          (a in A)
+//   dL[x][(b d)]  += sum_(a in A, c) L[x][(ac)] W'_A[(ac)][(bd)]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "ccladder.h"
+#include "gemm.hpp"
+#include "plan.h"
+#include "split.hpp"
+
+namespace ccl {
+namespace {
+
+#define CCL_HIP(expr)                                  \
+  do {                                                 \
+    if ((expr) != hipSuccess) return CC_LADDER_EHIP;   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device checks
+// ---------------------------------------------------------------------------
+
+std::mutex g_dev_mu;
+int g_dev_ok[64];  // 0 unknown, 1 gfx950, -1 other
+
+int check_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return CC_LADDER_ENODEV;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CC_LADDER_ENODEV;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (g_dev_ok[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return CC_LADDER_ENODEV;
+    g_dev_ok[dev] = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+  }
+  return g_dev_ok[dev] == 1 ? CC_LADDER_OK : CC_LADDER_ENODEV;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bbytes && y < x + abytes;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM launch
+// ---------------------------------------------------------------------------
+
+template <class T>
+bool vec_ok(const T* p, long long ld) {
+  constexpr int per16 = 16 / sizeof(T);
+  return (reinterpret_cast<uintptr_t>(p) % 16) == 0 && (ld % per16) == 0;
+}
+
+template <class Tr, int LA, int LB, int EPI>
+int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
+                void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
+                hipStream_t stream) {
+  if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
+  GemmArgs<typename Tr::T> g;
+  g.A = A; g.lda = lda;
+  g.B = B; g.ldb = ldb;
+  g.C = C; g.ldc = ldc;
+  g.M = M; g.N = N; g.K = K;
+  g.v = v;
+  g.tiles_m = (M + kBM - 1) / kBM;
+  g.tiles_n = (N + kBN - 1) / kBN;
+  const long long tiles = (long long)g.tiles_m * g.tiles_n;
+  if (tiles > 0x7fffffffLL) return CC_LADDER_EINVAL;
+  // Bands of up to 16 tile rows: co-resident tiles of one XCD then share
+  // both their row panels and a few column panels.
+  g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
+  g.drain_steps = drain_steps > 0 ? drain_steps : 1;
+  const dim3 grid(static_cast<unsigned>(tiles)), block(kThreads);
+  if (vec_ok(A, lda) && vec_ok(B, ldb))
+    hipLaunchKernelGGL((gemm_kernel<Tr, LA, LB, EPI, true>), grid, block, 0, stream, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<Tr, LA, LB, EPI, false>), grid, block, 0, stream, g);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// operand preparation and reductions
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void to_f32_kernel(const double* __restrict__ x,
+                                                     float* __restrict__ y, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    y[i] = static_cast<float>(x[i]);  // round to nearest even
+}
+
+int to_f32(const double* x, float* y, size_t n, hipStream_t s) {
+  if (!n) return CC_LADDER_OK;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(to_f32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x, y,
+                     static_cast<long long>(n));
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+constexpr int kRedBlocks = 1024;
+
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const double* __restrict__ x,
+                                                             const double* __restrict__ y,
+                                                             long long n, double* part) {
+  double sxy = 0.0, syy = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double yi = y[i];
+    sxy = fma(x[i], yi, sxy);
+    syy = fma(yi, yi, syy);
+  }
+  __shared__ double s1[256], s2[256];
+  s1[threadIdx.x] = sxy;
+  s2[threadIdx.x] = syy;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restrict__ part, int nb,
+                                                           double* out) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  __shared__ double s1[256], s2[256];
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s1[0];
+    out[1] = s2[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// scratch
+// ---------------------------------------------------------------------------
+
+struct Scratch {
+  char* base = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  ~Scratch() {
+    if (owned && base) (void)hipFreeAsync(base, stream);
+  }
+};
+
+size_t default_budget() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0;
+  const size_t half = free_b / 2;
+  const size_t cap = static_cast<size_t>(64) << 30;
+  return half < cap ? half : cap;
+}
+
+int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream_t stream,
+                     const cc_ladder_opts* opts, Plan* plan, Scratch* ws) {
+  size_t budget;
+  if (opts && opts->workspace)
+    budget = opts->workspace_bytes;
+  else if (opts && opts->hbm_budget)
+    budget = opts->hbm_budget;
+  else
+    budget = default_budget();
+  if (!budget) return CC_LADDER_EHIP;
+  int rc = make_plan(o, v, P, precision, backward, budget, opts, plan);
+  if (rc) return rc;
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < plan->bytes) return CC_LADDER_ENOMEM;
+    ws->base = static_cast<char*>(opts->workspace);
+    return CC_LADDER_OK;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipMallocAsync(&p, plan->bytes ? plan->bytes : 256, stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? CC_LADDER_ENOMEM : CC_LADDER_EHIP;
+  }
+  ws->base = static_cast<char*>(p);
+  ws->owned = true;
+  ws->stream = stream;
+  return CC_LADDER_OK;
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+
+template <class Tr>
+int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t, double* R,
+                   typename Tr::T* V, hipStream_t s) {
+  const int o = pl.o, v = pl.v, P = pl.P;
+  const long long v2 = (long long)v * v;
+  const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  for (int a0 = 0; a0 < v; a0 += pl.n_a) {
+    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+    // V_A[a][b][c][d]: rows (a,c) of L's block, columns (b,d) of L, K = x
+    int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + (long long)a0 * v, v2, L, v2, V, 0, na * v,
+                                               static_cast<int>(v2), P, v, drain, s);
+    if (rc) return rc;
+    // R[(ij)][a0*v + (a,b)] += t[(ij)][(cd)] . V_A[(ab)][(cd)]
+    rc = launch_gemm<Tr, KC, KC, EPI_ACC>(t, v2, V, v2, R + (long long)a0 * v, v2, o * o, na * v,
+                                          static_cast<int>(v2), v, drain, s);
+    if (rc) return rc;
+  }
+  return CC_LADDER_OK;
+}
+
+template <class Tr>
+int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t,
+                    const typename Tr::T* lam, double* dL, double* dt, typename Tr::T* V,
+                    typename Tr::T* W, hipStream_t s) {
+  const int o = pl.o, v = pl.v, P = pl.P;
+  const long long v2 = (long long)v * v;
+  const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  for (int a0 = 0; a0 < v; a0 += pl.n_a) {
+    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+    const long long off = (long long)a0 * v;
+    int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + off, v2, L, v2, V, 0, na * v,
+                                               static_cast<int>(v2), P, v, drain, s);
+    if (rc) return rc;
+    // dt[(ij)][(cd)] += lam[(ij)][a0*v + (ab)] . V_A[(ab)][(cd)]
+    rc = launch_gemm<Tr, KC, RC, EPI_ACC>(lam + off, v2, V, v2, dt, v2, o * o,
+                                          static_cast<int>(v2), na * v, v, drain, s);
+    if (rc) return rc;
+    // W'_A[a][c][b][d] = sum_(ij) lam[(ij)][a0*v + (ab)] t[(ij)][(cd)]
+    rc = launch_gemm<Tr, RC, RC, EPI_PERM>(lam + off, v2, t, v2, W, 0, na * v,
+                                           static_cast<int>(v2), o * o, v, drain, s);
+    if (rc) return rc;
+    // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]
+    rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
+                                          static_cast<int>(v2), v, drain, s);
+    if (rc) return rc;
+    // dL[x][(bd)] += L[x][a0*v + (ac)] . W'_A[(ac)][(bd)]
+    rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
+                                          na * v, v, drain, s);
+    if (rc) return rc;
+  }
+  return CC_LADDER_OK;
+}
+
+}  // namespace
+}  // namespace ccl
+
+using namespace ccl;
+
+extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const double* t,
+                                  double* R, int precision, hipStream_t stream,
+                                  const cc_ladder_opts* opts) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  if (!L || !t || !R) return CC_LADDER_EINVAL;
+  const size_t nt = (size_t)o * o * v * v * sizeof(double);
+  const size_t nL = (size_t)P * v * v * sizeof(double);
+  if (overlaps(R, nt, t, nt) || overlaps(R, nt, L, nL)) return CC_LADDER_EINVAL;
+  rc = check_device();
+  if (rc) return rc;
+  Plan pl;
+  Scratch ws;
+  rc = plan_and_scratch(o, v, P, precision, 0, stream, opts, &pl, &ws);
+  if (rc) return rc;
+  char* base = ws.base;
+  switch (precision) {
+    case CC_LADDER_FP64:
+      return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V), stream);
+    case CC_LADDER_FP32: {
+      float* L32 = reinterpret_cast<float*>(base + pl.off_L);
+      float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+      rc = to_f32(L, L32, (size_t)P * v * v, stream);
+      if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
+      if (rc) return rc;
+      return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V),
+                                   stream);
+    }
+    case CC_LADDER_SPLIT_BF16:
+      return split_forward(pl, L, t, R, base, stream);
+    default:
+      return CC_LADDER_EINVAL;
+  }
+}
+
+extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const double* t,
+                                  const double* lam, double* dL, double* dt, int precision,
+                                  hipStream_t stream, const cc_ladder_opts* opts) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  if (!L || !t || !lam || !dL || !dt) return CC_LADDER_EINVAL;
+  const size_t nt = (size_t)o * o * v * v * sizeof(double);
+  const size_t nL = (size_t)P * v * v * sizeof(double);
+  if (overlaps(dt, nt, t, nt) || overlaps(dt, nt, lam, nt) || overlaps(dt, nt, L, nL) ||
+      overlaps(dL, nL, L, nL) || overlaps(dL, nL, t, nt) || overlaps(dL, nL, lam, nt) ||
+      overlaps(dL, nL, dt, nt))
+    return CC_LADDER_EINVAL;
+  if (precision == CC_LADDER_SPLIT_BF16) return CC_LADDER_EUNSUPPORTED;
+  rc = check_device();
+  if (rc) return rc;
+  Plan pl;
+  Scratch ws;
+  rc = plan_and_scratch(o, v, P, precision, 1, stream, opts, &pl, &ws);
+  if (rc) return rc;
+  char* base = ws.base;
+  if (precision == CC_LADDER_FP64) {
+    return backward_blocks<TrF64>(pl, L, t, lam, dL, dt,
+                                  reinterpret_cast<double*>(base + pl.off_V),
+                                  reinterpret_cast<double*>(base + pl.off_W), stream);
+  }
+  float* L32 = reinterpret_cast<float*>(base + pl.off_L);
+  float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+  float* lam32 = reinterpret_cast<float*>(base + pl.off_lam);
+  rc = to_f32(L, L32, (size_t)P * v * v, stream);
+  if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
+  if (!rc) rc = to_f32(lam, lam32, (size_t)o * o * v * v, stream);
+  if (rc) return rc;
+  return backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dt,
+                                reinterpret_cast<float*>(base + pl.off_V),
+                                reinterpret_cast<float*>(base + pl.off_W), stream);
+}
+
+extern "C" int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out_dev,
+                                hipStream_t stream) {
+  if (o <= 0 || v <= 0 || o > 46340 || v > 46340) return CC_LADDER_EINVAL;
+  if (!x || !y || !out_dev) return CC_LADDER_EINVAL;
+  const long long n = (long long)o * o * v * v;
+  if (overlaps(out_dev, 2 * sizeof(double), x, n * sizeof(double)) ||
+      overlaps(out_dev, 2 * sizeof(double), y, n * sizeof(double)))
+    return CC_LADDER_EINVAL;
+  int rc = check_device();
+  if (rc) return rc;
+  const long long want = (n + 255) / 256;
+  const int nb = static_cast<int>(want < kRedBlocks ? want : kRedBlocks);
+  void* part = nullptr;
+  if (hipMallocAsync(&part, 2 * sizeof(double) * nb, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return CC_LADDER_ENOMEM;
+  }
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(nb), dim3(256), 0, stream, x, y, n,
+                     static_cast<double*>(part));
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, stream,
+                     static_cast<const double*>(part), nb, out_dev);
+  const bool ok = hipGetLastError() == hipSuccess;
+  (void)hipFreeAsync(part, stream);
+  return ok ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+extern "C" int cc_ladder_workspace_query(int o, int v, int P, int precision, int backward,
+                                         size_t hbm_budget, const cc_ladder_opts* opts,
+                                         size_t* bytes, int* a_block) {
+  if (!bytes || !a_block) return CC_LADDER_EINVAL;
+  Plan pl;
+  const int rc = make_plan(o, v, P, precision, backward, hbm_budget, opts, &pl);
+  if (rc) return rc;
+  *bytes = pl.bytes;
+  *a_block = pl.n_a;
+  return CC_LADDER_OK;
+}
+
+extern "C" const char* cc_ladder_strerror(int code) {
+  switch (code) {
+    case CC_LADDER_OK: return "success";
+    case CC_LADDER_EINVAL: return "invalid argument (dimension, pointer, aliasing, precision or option)";
+    case CC_LADDER_ENOMEM: return "scratch does not fit the budget or the workspace";
+    case CC_LADDER_ENODEV: return "no gfx950 device is current";
+    case CC_LADDER_EHIP: return "HIP runtime error";
+    case CC_LADDER_EUNSUPPORTED: return "request not supported by this build";
+    default: return "unknown error code";
+  }
+}

@@ -1,0 +1,303 @@
+// MFMA GEMM family for gfx950 (CDNA4) used by every contraction of the ladder
+// term and its adjoint.
+//
+//   C[m][n] (+)= sum_k A(m,k) B(k,n)
+//
+// Operands are addressed through a pointer and a leading dimension in one of
+// two layouts:
+//   KC: the contracted index is contiguous   A(m,k) = A[m*lda + k], B(k,n) = B[n*ldb + k]
+//   RC: the row / column index is contiguous A(m,k) = A[k*lda + m], B(k,n) = B[k*ldb + n]
+// which covers every product of the path without operand copies: the integral
+// build reads the Cholesky vectors [x][(p,q)] directly (RC, K = x), the
+// amplitude contraction reads t and the integral block with K = (c,d)
+// contiguous (KC), and so on.
+//
+// Epilogues:
+//   EPI_ACC : C[m*ldc + n] += acc                         (float64 accumulation)
+//   EPI_PERM: m = (a, x), n = (y, d) with x, d < v:
+//             C[a*v^3 + y*v^2 + x*v + d] = acc            (stores, in the operand type, an
+//                                                          integral-shaped block with its
+//                                                          middle indices swapped)
+//
+// Tiling: 256 threads = 4 wave64s in a 2x2 grid, 128x128 workgroup tile, each
+// wave owns a 64x64 sub-tile = 4x4 MFMA 16x16 blocks.  Global tiles are read
+// 16 bytes per lane into registers one K-step ahead and written into a
+// double-buffered LDS tile, so one barrier per K-step separates the two halves.
+//
+// MFMA operand layout (v_mfma_*_16x16x4): lane l supplies A[l%16][slot l/16]
+// and B[slot l/16][l%16]; the 16x16 result sits as 4 values per lane in
+// column l%16: value r is row 4*(l/16)+r for the float32 instruction and row
+// (l/16)+4*r for the float64 one (measured on gfx950).  A "k-group" of CH*4 consecutive k is read with one
+// 16-byte LDS access per lane and consumed by CH MFMA steps: in step e, slot j
+// carries k = group_base + CH*j + e, for both operands alike.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccl {
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+enum { KC = 0, RC = 1 };
+enum { EPI_ACC = 0, EPI_PERM = 1 };
+
+// float64 operands on v_mfma_f64_16x16x4_f64.
+struct TrF64 {
+  using T = double;
+  using Chunk = f64x2;   // 16 bytes
+  using Acc = f64x4;
+  static constexpr int CH = 2;     // elements per 16-byte chunk = MFMA steps per k-group
+  static constexpr int BK = 16;    // K per LDS stage
+  static constexpr bool kDrain = false;
+  __device__ static inline Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of result value r held by `lane`
+  __device__ static inline int row_of(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// float32 operands on v_mfma_f32_16x16x4_f32; partial sums drained to float64.
+struct TrF32 {
+  using T = float;
+  using Chunk = f32x4;
+  using Acc = f32x4;
+  static constexpr int CH = 4;
+  static constexpr int BK = 32;
+  static constexpr bool kDrain = true;
+  __device__ static inline Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row_of(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <class T>
+struct GemmArgs {
+  const T* A;
+  long long lda;
+  const T* B;
+  long long ldb;
+  void* C;          // EPI_ACC: double; EPI_PERM: T
+  long long ldc;
+  int M, N, K;
+  int v;             // EPI_PERM index split
+  int tiles_m, tiles_n;
+  int group_m;       // tile-order swizzle: rows of tiles walked together
+  int drain_steps;   // K-steps between float32 -> float64 drains (TrF32)
+};
+
+constexpr int kBM = 128, kBN = 128;
+
+template <class Tr, int LAY, int ROWS>
+struct TileIO {
+  using T = typename Tr::T;
+  using Chunk = typename Tr::Chunk;
+  static constexpr int CH = Tr::CH;
+  static constexpr int BK = Tr::BK;
+  static constexpr int PADK = CH;              // KC row pad: 16 bytes
+  static constexpr int PADR = 64 / sizeof(T);  // RC row pad: 64 bytes
+  static constexpr int LD = (LAY == KC) ? (BK + PADK) : (ROWS + PADR);
+  static constexpr int ELEMS = (LAY == KC) ? ROWS * LD : BK * LD;  // one LDS stage
+  static constexpr int NCH = ROWS * BK / CH / kThreads;            // chunks per thread
+  static_assert(NCH * CH * kThreads == ROWS * BK, "tile must split evenly into 16-byte chunks");
+
+  // Chunk c of this thread: its (row, k) origin inside the tile.
+  __device__ static inline void coord(int c, int tid, int& row, int& kk) {
+    const int q = c * kThreads + tid;
+    if (LAY == KC) {
+      row = q / (BK / CH);
+      kk = (q % (BK / CH)) * CH;
+    } else {
+      kk = q / (ROWS / CH);
+      row = (q % (ROWS / CH)) * CH;
+    }
+  }
+
+  template <bool VEC>
+  __device__ static inline void load(Chunk (&r)[NCH], const T* __restrict__ p, long long ld,
+                                     int row0, int nrows, int k0, int K, bool full, int tid) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int row, kk;
+      coord(c, tid, row, kk);
+      const long long off = (LAY == KC) ? (long long)(row0 + row) * ld + (k0 + kk)
+                                        : (long long)(k0 + kk) * ld + (row0 + row);
+      const T* src = p + off;
+      if (VEC && full) {
+        r[c] = *reinterpret_cast<const Chunk*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+          const bool ok = (LAY == KC) ? (row0 + row < nrows && k0 + kk + e < K)
+                                      : (k0 + kk < K && row0 + row + e < nrows);
+          r[c][e] = ok ? src[e] : T(0);
+        }
+      }
+    }
+  }
+
+  __device__ static inline void store(T* s, const Chunk (&r)[NCH], int tid) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int row, kk;
+      coord(c, tid, row, kk);
+      T* dst = (LAY == KC) ? s + row * LD + kk : s + kk * LD + row;
+      *reinterpret_cast<Chunk*>(dst) = r[c];
+    }
+  }
+
+  // Operand values of k-group g for the 16 rows starting at rb: element e feeds MFMA step e.
+  __device__ static inline Chunk frag(const T* s, int rb, int g, int lane) {
+    const int kb = g * (CH * 4) + CH * (lane >> 4);
+    if (LAY == KC) {
+      return *reinterpret_cast<const Chunk*>(s + (rb + (lane & 15)) * LD + kb);
+    } else {
+      Chunk f;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) f[e] = s[(kb + e) * LD + rb + (lane & 15)];
+      return f;
+    }
+  }
+};
+
+// Maps the linear workgroup id to a tile.  Workgroups are handed to the 8 XCDs
+// round-robin; the remap gives each XCD a contiguous range of logical tiles so
+// that co-resident tiles share operand panels in that XCD's L2.  Logical tiles
+// are walked in bands of group_m tile rows.
+__device__ inline void tile_of(int bid, int nwg, int tiles_m, int group_m, int& tm, int& tn) {
+  const int per = nwg / 8, extra = nwg % 8;
+  const int xcd = bid % 8, local = bid / 8;
+  const int id = xcd * per + (xcd < extra ? xcd : extra) + local;
+  const int band = group_m * (nwg / tiles_m);  // tiles in one band (tiles_n tiles per row)
+  const int b = id / band;
+  const int first = b * group_m;
+  const int rows = (tiles_m - first) < group_m ? (tiles_m - first) : group_m;
+  const int in = id - b * band;
+  tm = first + in % rows;
+  tn = in / rows;
+}
+
+template <class Tr, int LA, int LB, int EPI, bool VEC>
+__global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs<typename Tr::T> g) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  using IA = TileIO<Tr, LA, kBM>;
+  using IB = TileIO<Tr, LB, kBN>;
+  constexpr int BK = Tr::BK;
+  constexpr int CH = Tr::CH;
+  constexpr int NG = BK / (CH * 4);  // k-groups per stage
+
+  __shared__ __attribute__((aligned(16))) T sA[2][IA::ELEMS];
+  __shared__ __attribute__((aligned(16))) T sB[2][IB::ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * 64;
+
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  const int m0 = tm * kBM;
+  const int n0 = tn * kBN;
+
+  Acc acc[4][4];
+  f64x4 acc64[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = Acc{0, 0, 0, 0};
+      acc64[i][j] = f64x4{0, 0, 0, 0};
+    }
+
+  const int nk = (g.K + BK - 1) / BK;
+  const bool rows_full = (m0 + kBM <= g.M) && (n0 + kBN <= g.N);
+
+  typename IA::Chunk ra[IA::NCH];
+  typename IB::Chunk rb[IB::NCH];
+
+  {
+    const bool full = rows_full && (BK <= g.K);
+    IA::template load<VEC>(ra, g.A, g.lda, m0, g.M, 0, g.K, full, tid);
+    IB::template load<VEC>(rb, g.B, g.ldb, n0, g.N, 0, g.K, full, tid);
+    IA::store(sA[0], ra, tid);
+    IB::store(sB[0], rb, tid);
+  }
+  __syncthreads();
+
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      const int k1 = (kt + 1) * BK;
+      const bool full = rows_full && (k1 + BK <= g.K);
+      IA::template load<VEC>(ra, g.A, g.lda, m0, g.M, k1, g.K, full, tid);
+      IB::template load<VEC>(rb, g.B, g.ldb, n0, g.N, k1, g.K, full, tid);
+    }
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      typename Tr::Chunk fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = IA::frag(sA[cur], wm + 16 * i, gi, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = IB::frag(sB[cur], wn + 16 * j, gi, lane);
+#pragma unroll
+      for (int e = 0; e < CH; ++e)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][e], fb[j][e], acc[i][j]);
+    }
+    if (Tr::kDrain && ((kt + 1) % g.drain_steps == 0 || kt + 1 == nk)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc64[i][j][r] += static_cast<double>(acc[i][j][r]);
+            acc[i][j][r] = 0;
+          }
+    }
+    if (kt + 1 < nk) {
+      IA::store(sA[cur ^ 1], ra, tid);
+      IB::store(sB[cur ^ 1], rb, tid);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds column lane%16 of each 16x16 block, rows Tr::row_of(lane, r).
+  const int col = lane & 15;
+  const long long v = g.v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn + 16 * j + col;
+    if (n >= g.N) continue;
+    long long ncol = n;
+    if (EPI == EPI_PERM) {
+      const int y = n / g.v, d = n - (n / g.v) * g.v;
+      ncol = (long long)y * v * v + d;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);
+        if (m >= g.M) continue;
+        const double val = Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]);
+        if (EPI == EPI_ACC) {
+          double* dst = static_cast<double*>(g.C) + (long long)m * g.ldc + n;
+          *dst += val;
+        } else {
+          const int a = m / g.v, x = m - (m / g.v) * g.v;
+          static_cast<T*>(g.C)[(long long)a * v * v * v + ncol + (long long)x * v] = static_cast<T>(val);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace ccl

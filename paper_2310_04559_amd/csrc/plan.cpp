@@ -1,0 +1,138 @@
+// Host-only planner: buffer layout and block-size selection.
+#include "plan.h"
+
+#include <cstdint>
+
+namespace ccl {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Appends a buffer of `bytes` at the end of the layout and returns its offset.
+size_t take(size_t* cursor, size_t bytes) {
+  size_t off = *cursor;
+  *cursor = round_up(off + bytes);
+  return off;
+}
+
+}  // namespace
+
+int check_dims(int o, int v, int P) {
+  if (o <= 0 || v <= 0 || P <= 0) return CC_LADDER_EINVAL;
+  // o^2 and v^2 are GEMM extents held in 32-bit ints.
+  if (o > 46340 || v > 46340 || P > (1 << 24)) return CC_LADDER_EINVAL;
+  return CC_LADDER_OK;
+}
+
+int check_precision_opts(int precision, const cc_ladder_opts* opts) {
+  if (precision != CC_LADDER_FP64 && precision != CC_LADDER_FP32 &&
+      precision != CC_LADDER_SPLIT_BF16)
+    return CC_LADDER_EINVAL;
+  if (!opts) return CC_LADDER_OK;
+  if (opts->a_block < 0 || opts->reserved != 0) return CC_LADDER_EINVAL;
+  if (opts->split_slices != 0 && (opts->split_slices < 2 || opts->split_slices > 6))
+    return CC_LADDER_EINVAL;
+  if (opts->k_chunk < 0 || opts->k_chunk % 64 != 0) return CC_LADDER_EINVAL;
+  if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
+    return CC_LADDER_EINVAL;
+  return CC_LADDER_OK;
+}
+
+int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
+                int slices, int k_chunk, Plan* plan) {
+  if (n_a < 1 || n_a > v) return CC_LADDER_EINVAL;
+  Plan p;
+  p.o = o; p.v = v; p.P = P;
+  p.precision = precision;
+  p.backward = backward ? 1 : 0;
+  p.n_a = n_a;
+  p.nblocks = (v + n_a - 1) / n_a;
+  const size_t v2 = static_cast<size_t>(v) * v;
+  const size_t o2 = static_cast<size_t>(o) * o;
+  const size_t blk = static_cast<size_t>(n_a) * v2 * v;  // entries of one integral block
+  size_t cur = 0;
+  switch (precision) {
+    case CC_LADDER_FP64:
+      p.off_V = take(&cur, blk * sizeof(double));
+      if (p.backward) p.off_W = take(&cur, blk * sizeof(double));
+      break;
+    case CC_LADDER_FP32:
+      p.k_chunk = k_chunk ? k_chunk : 512;
+      p.off_L = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
+      p.off_t = take(&cur, o2 * v2 * sizeof(float));
+      if (p.backward) p.off_lam = take(&cur, o2 * v2 * sizeof(float));
+      p.off_V = take(&cur, blk * sizeof(float));
+      if (p.backward) p.off_W = take(&cur, blk * sizeof(float));
+      break;
+    case CC_LADDER_SPLIT_BF16: {
+      p.slices = slices ? slices : 4;
+      const size_t s = static_cast<size_t>(p.slices);
+      // slices are stored with the contracted index padded to a multiple of 64
+      const size_t Pp = (static_cast<size_t>(P) + 63) / 64 * 64;
+      const size_t v2p = (v2 + 63) / 64 * 64;
+      // L is cut twice: along x for the integral build (rows (p,q), K = x)
+      p.off_L = take(&cur, s * v2 * Pp * 2);
+      p.off_Lexp = take(&cur, v2 * sizeof(int));
+      p.off_t = take(&cur, s * o2 * v2p * 2);
+      p.off_texp = take(&cur, o2 * sizeof(int));
+      p.off_V = take(&cur, blk * sizeof(double));
+      p.off_Vs = take(&cur, s * static_cast<size_t>(n_a) * v * v2p * 2);
+      p.off_Vexp = take(&cur, static_cast<size_t>(n_a) * v * sizeof(int));
+      if (p.backward) return CC_LADDER_EUNSUPPORTED;
+      break;
+    }
+    default:
+      return CC_LADDER_EINVAL;
+  }
+  p.bytes = cur;
+  *plan = p;
+  return CC_LADDER_OK;
+}
+
+int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
+              const cc_ladder_opts* opts, Plan* plan) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  const int slices = opts ? opts->split_slices : 0;
+  const int k_chunk = opts ? opts->k_chunk : 0;
+  if (opts && opts->a_block > 0) {
+    const int n_a = opts->a_block < v ? opts->a_block : v;
+    rc = layout_plan(o, v, P, precision, backward, n_a, slices, k_chunk, plan);
+    if (rc) return rc;
+    return (budget && plan->bytes > budget) ? CC_LADDER_ENOMEM : CC_LADDER_OK;
+  }
+  // Largest block that fits: the footprint grows monotonically with n_a.
+  Plan best;
+  rc = layout_plan(o, v, P, precision, backward, 1, slices, k_chunk, &best);
+  if (rc) return rc;
+  if (budget && best.bytes > budget) return CC_LADDER_ENOMEM;
+  int lo = 1, hi = v;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    Plan trial;
+    rc = layout_plan(o, v, P, precision, backward, mid, slices, k_chunk, &trial);
+    if (rc) return rc;
+    if (!budget || trial.bytes <= budget) {
+      lo = mid;
+      best = trial;
+    } else {
+      hi = mid - 1;
+    }
+  }
+  // Equalise the blocks: same block count, smallest n_a that achieves it.
+  const int nb = (v + best.n_a - 1) / best.n_a;
+  const int n_eq = (v + nb - 1) / nb;
+  if (n_eq != best.n_a) {
+    rc = layout_plan(o, v, P, precision, backward, n_eq, slices, k_chunk, &best);
+    if (rc) return rc;
+  }
+  *plan = best;
+  return CC_LADDER_OK;
+}
+
+}  // namespace ccl

@@ -1,0 +1,49 @@
+// Host-side planning of the virtual-index blocking (no device calls).
+//
+// The integral V[a,c,b,d] is rebuilt for a block of n_a first-virtual indices
+// at a time.  Like the paper's batch-wise scheme (Sec. "CuPy and batch-wise
+// computations"), the element counts of every buffer are multiplied by their
+// element sizes and the block is shrunk until everything fits the budget;
+// here the inputs are already resident, so only the scratch is planned.
+#pragma once
+#include <cstddef>
+
+#include "ccladder.h"
+
+namespace ccl {
+
+// Scratch buffers of one call, as byte offsets into a single workspace.
+struct Plan {
+  int o = 0, v = 0, P = 0;
+  int precision = 0;
+  int backward = 0;
+  int n_a = 0;          // virtuals per integral block
+  int nblocks = 0;      // ceil(v / n_a)
+  int slices = 0;       // split-bf16 slice count (0 for the other forms)
+  int k_chunk = 0;      // float32 drain interval along the contracted index
+  // operand copies made once per call (float32 / bf16 slice forms)
+  size_t off_L = 0, off_t = 0, off_lam = 0;
+  size_t off_Lexp = 0, off_texp = 0, off_lamexp = 0;
+  // per-block buffers
+  size_t off_V = 0;     // float64 or float32 integral block [n_a][v][v][v]
+  size_t off_W = 0;     // adjoint block W'[n_a][v][v][v] (backward)
+  size_t off_Vs = 0;    // bf16 slices of the integral block
+  size_t off_Vexp = 0;  // per-row exponents of the integral block
+  size_t off_Ws = 0, off_Wexp = 0;
+  size_t bytes = 0;     // total scratch
+};
+
+// Fills `plan` for a block size of n_a (1 <= n_a <= v).  Returns 0 or CC_LADDER_EINVAL.
+int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
+                int slices, int k_chunk, Plan* plan);
+
+// Picks n_a (honouring opts->a_block when set) so that plan.bytes <= budget
+// (budget 0 = unlimited).  Returns 0, CC_LADDER_EINVAL or CC_LADDER_ENOMEM.
+int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
+              const cc_ladder_opts* opts, Plan* plan);
+
+// Argument checks shared by every entry point (dimensions, precision, options).
+int check_dims(int o, int v, int P);
+int check_precision_opts(int precision, const cc_ladder_opts* opts);
+
+}  // namespace ccl

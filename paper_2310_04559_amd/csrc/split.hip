@@ -1,0 +1,10 @@
+// Split-bf16 form: not built yet.
+#include "split.hpp"
+
+namespace ccl {
+
+int split_forward(const Plan&, const double*, const double*, double*, char*, hipStream_t) {
+  return CC_LADDER_EUNSUPPORTED;
+}
+
+}  // namespace ccl

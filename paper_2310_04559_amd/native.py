@@ -1,0 +1,194 @@
+"""ctypes binding of libccladder.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and takes
+torch tensors (device memory and streams come from PyTorch); all arithmetic
+happens in the library's HIP kernels.  The library is required: when it is
+not built, ``load()`` raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # loaded first so the library binds to the HIP runtime torch uses
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccladder.so")
+
+CC_LADDER_FP64 = 0
+CC_LADDER_FP32 = 1
+CC_LADDER_SPLIT_BF16 = 2
+PRECISIONS = {"fp64": CC_LADDER_FP64, "fp32": CC_LADDER_FP32, "split_bf16": CC_LADDER_SPLIT_BF16}
+
+CC_LADDER_OK = 0
+CC_LADDER_EINVAL = -1
+CC_LADDER_ENOMEM = -2
+CC_LADDER_ENODEV = -3
+CC_LADDER_EHIP = -4
+CC_LADDER_EUNSUPPORTED = -5
+
+EXPORTS = ("cc_ladder_residual", "cc_ladder_backward", "cc_ladder_reduce",
+           "cc_ladder_workspace_query", "cc_ladder_strerror")
+
+
+class CcLadderOpts(ctypes.Structure):
+    _fields_ = [
+        ("a_block", ctypes.c_int),
+        ("split_slices", ctypes.c_int),
+        ("k_chunk", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+        ("hbm_budget", ctypes.c_size_t),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class LadderError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+
+
+_lib = None
+
+
+def load():
+    """Loads the library (once).  Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    i, p, st = ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+    opts_p = ctypes.POINTER(CcLadderOpts)
+    lib.cc_ladder_residual.argtypes = [i, i, i, p, p, p, i, p, opts_p]
+    lib.cc_ladder_residual.restype = i
+    lib.cc_ladder_backward.argtypes = [i, i, i, p, p, p, p, p, i, p, opts_p]
+    lib.cc_ladder_backward.restype = i
+    lib.cc_ladder_reduce.argtypes = [i, i, p, p, p, p]
+    lib.cc_ladder_reduce.restype = i
+    lib.cc_ladder_workspace_query.argtypes = [i, i, i, i, i, st, opts_p,
+                                              ctypes.POINTER(st), ctypes.POINTER(i)]
+    lib.cc_ladder_workspace_query.restype = i
+    lib.cc_ladder_strerror.argtypes = [i]
+    lib.cc_ladder_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().cc_ladder_strerror(int(code)).decode()
+
+
+def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
+              workspace: Optional[torch.Tensor] = None) -> CcLadderOpts:
+    o = CcLadderOpts()
+    o.a_block = int(a_block)
+    o.split_slices = int(split_slices)
+    o.k_chunk = int(k_chunk)
+    o.reserved = 0
+    o.hbm_budget = int(hbm_budget)
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, str):
+        return PRECISIONS[precision]
+    return int(precision)
+
+
+def _dev_f64(x: torch.Tensor, name: str, shape=None) -> int:
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+    return x.data_ptr()
+
+
+def _stream(dev, stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    return s.cuda_stream
+
+
+def _opts_ref(opts):
+    return ctypes.byref(opts) if opts is not None else None
+
+
+def _check(rc: int, where: str):
+    if rc != CC_LADDER_OK:
+        raise LadderError(rc, where)
+
+
+def cc_ladder_residual(L: torch.Tensor, t: torch.Tensor, R: torch.Tensor, precision=0,
+                       stream=None, opts: Optional[CcLadderOpts] = None) -> torch.Tensor:
+    """R[i,j,a,b] += sum_cd (sum_x L[x,a,c] L[x,b,d]) t[i,j,c,d]; returns R."""
+    lib = load()
+    P, v, _ = L.shape
+    o = t.shape[0]
+    pL = _dev_f64(L, "L", (P, v, v))
+    pt = _dev_f64(t, "t", (o, o, v, v))
+    pR = _dev_f64(R, "R", (o, o, v, v))
+    with torch.cuda.device(R.device):
+        rc = lib.cc_ladder_residual(o, v, P, pL, pt, pR, _prec(precision),
+                                    _stream(R.device, stream), _opts_ref(opts))
+    _check(rc, "cc_ladder_residual")
+    return R
+
+
+def cc_ladder_backward(L: torch.Tensor, t: torch.Tensor, lam: torch.Tensor, dL: torch.Tensor,
+                       dt: torch.Tensor, precision=0, stream=None,
+                       opts: Optional[CcLadderOpts] = None):
+    """dL += dLoss/dL and dt += dLoss/dt for Loss = sum lam * R; returns (dL, dt)."""
+    lib = load()
+    P, v, _ = L.shape
+    o = t.shape[0]
+    args = (_dev_f64(L, "L", (P, v, v)), _dev_f64(t, "t", (o, o, v, v)),
+            _dev_f64(lam, "lam", (o, o, v, v)), _dev_f64(dL, "dL", (P, v, v)),
+            _dev_f64(dt, "dt", (o, o, v, v)))
+    with torch.cuda.device(dt.device):
+        rc = lib.cc_ladder_backward(o, v, P, *args, _prec(precision),
+                                    _stream(dt.device, stream), _opts_ref(opts))
+    _check(rc, "cc_ladder_backward")
+    return dL, dt
+
+
+def cc_ladder_reduce(x: torch.Tensor, y: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     stream=None) -> torch.Tensor:
+    """out = [sum x*y, sum y*y] (device float64[2])."""
+    lib = load()
+    if x.dim() != 4 or x.shape[0] != x.shape[1] or x.shape[2] != x.shape[3]:
+        raise ValueError("x must be [o][o][v][v]")
+    o, v = x.shape[0], x.shape[2]
+    px = _dev_f64(x, "x")
+    py = _dev_f64(y, "y", x.shape)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=x.device)
+    pout = _dev_f64(out, "out", (2,))
+    with torch.cuda.device(x.device):
+        rc = lib.cc_ladder_reduce(o, v, px, py, pout, _stream(x.device, stream))
+    _check(rc, "cc_ladder_reduce")
+    return out
+
+
+def cc_ladder_workspace_query(o: int, v: int, P: int, precision=0, backward: bool = False,
+                              hbm_budget: int = 0, opts: Optional[CcLadderOpts] = None):
+    """(scratch bytes, virtuals per block) the planner picks; needs no device."""
+    lib = load()
+    nbytes = ctypes.c_size_t(0)
+    a_block = ctypes.c_int(0)
+    rc = lib.cc_ladder_workspace_query(int(o), int(v), int(P), _prec(precision), int(bool(backward)),
+                                       int(hbm_budget), _opts_ref(opts), ctypes.byref(nbytes),
+                                       ctypes.byref(a_block))
+    _check(rc, "cc_ladder_workspace_query")
+    return nbytes.value, a_block.value
+
+
+def cc_ladder_strerror(code: int) -> str:
+    return strerror(code)

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI: the library loads, exports what the header
+declares, plans blocks and rejects bad arguments without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccladder.h")
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2310_04559_amd import native as nat
+
+    nat.load()
+    return nat
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cc_ladder_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(native):
+    names = declared_functions()
+    assert set(names) == set(native.EXPORTS)
+    lib = native.load()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_opts_struct_layout(native):
+    # int a_block, split_slices, k_chunk, reserved; size_t budget; void* ws; size_t ws_bytes
+    assert ctypes.sizeof(native.CcLadderOpts) == 4 * 4 + 8 * 3
+
+
+def test_strerror(native):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert native.cc_ladder_strerror(code)
+    assert "unknown" in native.cc_ladder_strerror(7)
+
+
+def test_planner_whole_range_without_budget(native):
+    nbytes, n_a = native.cc_ladder_workspace_query(40, 360, 1200, "fp64")
+    assert n_a == 360
+    assert nbytes == 360 ** 4 * 8  # one float64 integral block of all virtuals
+
+
+def test_planner_shrinks_to_budget(native):
+    per_a = 360 ** 3 * 8
+    nbytes, n_a = native.cc_ladder_workspace_query(40, 360, 1200, "fp64", hbm_budget=32 * per_a)
+    assert nbytes <= 32 * per_a
+    # equalised blocks: ceil(360/32) = 12 blocks of 30
+    assert n_a == 30
+    nbytes, n_a = native.cc_ladder_workspace_query(20, 180, 600, "fp64", hbm_budget=32 * 180 ** 3 * 8)
+    assert n_a == 30  # 6 blocks of 30 rather than 5x32 + 20
+
+
+def test_planner_backward_and_fp32_footprints(native):
+    v, o, P = 30, 4, 50
+    b64, n = native.cc_ladder_workspace_query(o, v, P, "fp64", backward=True)
+    assert n == v and b64 >= 2 * v ** 4 * 8
+    b32, n = native.cc_ladder_workspace_query(o, v, P, "fp32")
+    assert n == v and b32 >= (P * v * v + o * o * v * v + v ** 4) * 4
+
+
+def test_planner_explicit_block_and_enomem(native):
+    opts = native.make_opts(a_block=7)
+    nbytes, n_a = native.cc_ladder_workspace_query(5, 20, 75, "fp64", opts=opts)
+    assert n_a == 7 and nbytes >= 7 * 20 ** 3 * 8
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(5, 20, 75, "fp64", hbm_budget=1000)
+    assert e.value.code == native.CC_LADDER_ENOMEM
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(5, 20, 75, "fp64", hbm_budget=3 * 20 ** 3 * 8, opts=opts)
+    assert e.value.code == native.CC_LADDER_ENOMEM
+
+
+@pytest.mark.parametrize("o,v,P,prec", [(0, 4, 4, 0), (2, 0, 4, 0), (2, 4, -1, 0), (2, 4, 4, 3),
+                                        (2, 4, 4, -1), (50000, 4, 4, 0)])
+def test_planner_rejects_bad_arguments(native, o, v, P, prec):
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(o, v, P, prec)
+    assert e.value.code == native.CC_LADDER_EINVAL
+
+
+def test_bad_options_rejected(native):
+    for kw in (dict(split_slices=1), dict(split_slices=9), dict(k_chunk=100), dict(a_block=-2)):
+        with pytest.raises(native.LadderError) as e:
+            native.cc_ladder_workspace_query(3, 8, 10, "fp32", opts=native.make_opts(**kw))
+        assert e.value.code == native.CC_LADDER_EINVAL
+
+
+def test_argument_checks_precede_device_checks(native):
+    lib = native.load()
+    # null pointers and aliasing are rejected on the host, device or not
+    assert lib.cc_ladder_residual(2, 4, 2, None, None, None, 0, None, None) == native.CC_LADDER_EINVAL
+    R = 1 << 20
+    assert lib.cc_ladder_residual(2, 4, 2, 1 << 24, R + 8, R, 0, None, None) == native.CC_LADDER_EINVAL
+    assert lib.cc_ladder_backward(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 1 << 30, 1 << 30, 0, None,
+                                  None) == native.CC_LADDER_EINVAL
+    assert lib.cc_ladder_reduce(2, 4, None, 1 << 20, 1 << 24, None) == native.CC_LADDER_EINVAL
+
+
+def test_no_device_is_reported(native):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = native.load()
+    rc = lib.cc_ladder_residual(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None, None)
+    assert rc == native.CC_LADDER_ENODEV
+    assert lib.cc_ladder_reduce(2, 4, 1 << 24, 1 << 26, 1 << 28, None) == native.CC_LADDER_ENODEV
