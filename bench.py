@@ -1,0 +1,346 @@
+#!/usr/bin/env python3
+"""Throughput of the particle-particle ladder residual on one MI355X.
+
+A step is one pass of the forward hot path over the throughput workload
+(o=40 occupied, v=360 virtual, P=1200 Cholesky vectors; synthetic MP2-like
+amplitudes, see paper_2310_04559_amd/inputs.py): planning, operand
+preparation, integral-block builds, amplitude contractions with float64
+accumulation into R, and the float64 reductions sum t*R and |R|^2.  Inputs
+are resident in HBM before timing starts.  The headline ``value`` is the
+nominal 2(P+o^2)v^4 flops of a step over its time, in TFLOP/s, for the
+float64 form; the float32 and split-bf16 forms are timed the same way and
+reported with their error against the float64 oracle.
+
+Also reported: the dominant kernel's roofline (HIP events recorded around its
+launches through the library's trace hook), the adjoint's throughput on the
+gradient workload (o=30, v=300, P=900), and the oracle timed on the host's
+cores over a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 at rel err"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}  # MI355X dense MFMA
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16"}
+KERNEL_SRC = [os.path.join(ROOT, "paper_2310_04559_amd", "csrc", f)
+              for f in ("gemm.hpp", "ccladder.hip", "split.hip", "split.hpp")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_src_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, form: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is absent or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_c3_{form}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_src_sha256_16") != kernel_src_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class PhaseTimer:
+    """Records a HIP event pair on the call's stream around each traced phase."""
+
+    def __init__(self, native, stream):
+        import torch
+
+        self.torch = torch
+        self.stream = stream
+        self.open = {}
+        self.spans = []  # (phase name, block, start event, end event)
+        self.fn = native.TRACE_FN(self._hook)
+        self.phases = native.PHASES
+
+    def _hook(self, user, phase, block, end, stream):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(self.stream)
+        if not end:
+            self.open[(phase, block)] = ev
+        else:
+            self.spans.append((self.phases[phase], block, self.open.pop((phase, block)), ev))
+
+    def reset(self):
+        self.spans = []
+
+    def summary(self):
+        out = {}
+        for name, _, a, b in self.spans:
+            d = out.setdefault(name, [0.0, 0])
+            d[0] += a.elapsed_time(b)
+            d[1] += 1
+        return {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1]} for k, v in out.items()}
+
+
+def sampled_pairs(v, n, seed):
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    pairs = {(0, 0), (v - 1, v - 1), (0, v - 1), (v - 1, 0)}
+    while len(pairs) < n:
+        pairs.add((int(rng.integers(0, v)), int(rng.integers(0, v))))
+    return sorted(pairs)
+
+
+def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
+    import torch
+
+    prec = native.PRECISIONS[form]
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, prec, hbm_budget=ws_bytes)
+    timer = PhaseTimer(native, stream)
+    opts = native.make_opts(workspace=ws, trace=timer.fn)
+
+    def step():
+        native.cc_ladder_residual(L, t, R, prec, opts=opts)
+        native.cc_ladder_reduce(t, R, out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    timer.reset()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / steps
+    phases = timer.summary()
+    del ws
+    return {"ms_per_step": ms, "wall_s": wall, "a_block": n_a, "workspace_bytes": nbytes,
+            "phases": phases}
+
+
+def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
+    import numpy as np
+    import torch
+
+    R = torch.zeros_like(t)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    native.cc_ladder_residual(L, t, R, native.PRECISIONS[form], opts=native.make_opts(workspace=ws))
+    torch.cuda.synchronize()
+    got = R[:, :, idx_a, idx_b].permute(2, 0, 1).cpu().numpy()
+    del R, ws
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def cpu_baseline(inp, target_s=15.0):
+    """The oracle (NumPy, float64 BLAS) over the first k virtuals of the loop
+    over a, k sized to roughly target_s seconds of host work."""
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([d.get("num_threads", 0) for d in threadpool_info()
+                     if d.get("user_api") == "blas"] or [os.cpu_count()])
+    except Exception:  # threadpoolctl missing: report the visible cores
+        cores = os.cpu_count()
+    o, v, P = inp.o, inp.v, inp.P
+    t0 = time.perf_counter()
+    R = oracle.ladder_forward(inp.L_vv, inp.t, a_begin=0, a_end=1)
+    one = time.perf_counter() - t0
+    k = int(max(1, min(v - 1, target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.ladder_forward(inp.L_vv, inp.t, R=R, a_begin=1, a_end=1 + k)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * (P + o * o) * float(v) ** 3 * k
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle forward over a in [1,{1 + k}) of the o={o},v={v},P={P} workload "
+                      f"({k}/{v} of its flops, {dt:.1f} s)"}
+
+
+def bench_adjoint(native, steps, forms=("fp64", "fp32")):
+    import numpy as np
+    import torch
+
+    from paper_2310_04559_amd.inputs import CONFIGS, make_inputs, seed_for
+
+    o, v, P = CONFIGS["c4"]
+    inp = make_inputs(o, v, P, seed_for("c4"), with_lambda=True, device="cuda")
+    L = torch.from_numpy(inp.L_vv).cuda()
+    t = torch.from_numpy(inp.t).cuda()
+    lam = torch.from_numpy(inp.lam).cuda()
+    del inp
+    flops = (6.0 * P + 4.0 * o * o) * float(v) ** 4
+    res = {"workload": f"o={o},v={v},P={P}", "nominal_tflop": flops / 1e12}
+    ref = None
+    for form in forms:
+        prec = native.PRECISIONS[form]
+        dL = torch.zeros_like(L)
+        dt = torch.zeros_like(t)
+        native.cc_ladder_backward(L, t, lam, dL, dt, prec)  # warm-up, also the result
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (dL.clone(), dt.clone())
+            err = None
+        else:
+            err = max(float(torch.linalg.vector_norm(dL - ref[0]) / torch.linalg.vector_norm(ref[0])),
+                      float(torch.linalg.vector_norm(dt - ref[1]) / torch.linalg.vector_norm(ref[1])))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            native.cc_ladder_backward(L, t, lam, dL, dt, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[form] = {"ms_per_step": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                     "rel_err_vs_fp64_gpu": err}
+        del dL, dt
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--forms", default="fp64,fp32,split_bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = ("bench.py measures one GPU only: the ladder library runs on a single MI355X and "
+               "this build has no multi-GPU path (--gpus must be 1).")
+        print(json.dumps({"error": msg, "n_gpus": args.gpus}), flush=True)
+        log(msg)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2310_04559_amd import native
+    from paper_2310_04559_amd.inputs import CONFIGS, make_inputs, seed_for
+
+    native.load()
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    o, v, P = CONFIGS["c3"]
+    t0 = time.perf_counter()
+    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    log(f"inputs o={o} v={v} P={P} drawn in {time.perf_counter() - t0:.1f} s")
+    L = torch.from_numpy(inp.L_vv).cuda()
+    t = torch.from_numpy(inp.t).cuda()
+    R = torch.zeros_like(t)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    free, _ = torch.cuda.mem_get_info()
+    ws_bytes = int(min(free // 2, 64 << 30))
+    flops = 2.0 * (P + o * o) * float(v) ** 4
+
+    pairs = sampled_pairs(v, 24, 3)
+    ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
+    idx_a = torch.tensor([a for a, _ in pairs], device="cuda")
+    idx_b = torch.tensor([b for _, b in pairs], device="cuda")
+
+    forms = {}
+    for form in [f for f in args.forms.split(",") if f]:
+        try:
+            err = rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes)
+        except native.LadderError as e:
+            forms[form] = {"status": "unsupported", "detail": str(e)}
+            log(f"{form}: {e}")
+            continue
+        r = bench_form(native, form, L, t, R, out, ws_bytes, args.steps, args.warmup, o, v, P)
+        r["tflops"] = flops / (r["ms_per_step"] * 1e-3) / 1e12
+        r["rel_err_vs_oracle"] = err
+        r["tolerance"] = TOL[form]
+        r["within_tolerance"] = err < TOL[form]
+        n_a = r["a_block"]
+        # dominant kernel: the amplitude contraction, 2 o^2 (n_a v) v^2 flops per full-block launch
+        c = r["phases"].get("contract")
+        if c:
+            per_step = c["launches"] / args.steps  # launches of the kernel in one step
+            launch_flops = 2.0 * o * o * float(v) ** 4 / per_step
+            achieved = launch_flops / (c["ms_avg"] * 1e-3) / 1e12
+            r["roofline"] = {"kernel": "contract", "bound": "mfma", "achieved": achieved,
+                             "peak": PEAK_TFLOPS[form], "unit": "TFLOP/s",
+                             "frac": achieved / PEAK_TFLOPS[form],
+                             "traffic": read_traffic("contract", form),
+                             "flops_per_launch": launch_flops}
+        b = r["phases"].get("build")
+        if b:
+            bflops = 2.0 * P * float(v) ** 4 / (b["launches"] / args.steps)
+            r["build_tflops"] = bflops / (b["ms_avg"] * 1e-3) / 1e12
+        forms[form] = r
+        log(f"{form}: {r['ms_per_step']:.1f} ms/step {r['tflops']:.2f} TFLOP/s err {err:.2e} "
+            f"a_block {n_a} phases {json.dumps(r['phases'])}")
+        R.zero_()
+
+    head = forms.get(args.precision)
+    if not head or "ms_per_step" not in head:
+        log(f"headline form {args.precision} did not run")
+        sys.exit(1)
+    line = {
+        "metric": METRIC,
+        "value": head["tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "ladder residual o=40 v=360 P=1200 (MP2-like amplitudes)",
+                   "o": o, "v": v, "P": P, "a_block": head["a_block"],
+                   "nominal_tflop_per_step": flops / 1e12, "precision": args.precision},
+        "roofline": head.get("roofline"),
+        "rel_err_vs_oracle": head["rel_err_vs_oracle"],
+        "forms": {k: {kk: vv for kk, vv in f.items() if kk != "phases"} | (
+            {"phases_ms_avg": {p: d["ms_avg"] for p, d in f["phases"].items()}} if "phases" in f else {})
+                  for k, f in forms.items()},
+    }
+    del L, t, R
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        log("adjoint ...")
+        line["adjoint"] = bench_adjoint(native, max(1, min(args.steps, 2)))
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        line["cpu_baseline"] = cpu_baseline(inp)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -56,15 +56,34 @@ typedef enum {
                                 products on bf16 MFMA, exact float32 chunks drained to float64 */
 } cc_ladder_precision;
 
+/* Kernel phases reported to an optional trace hook. */
+typedef enum {
+  CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam */
+  CC_LADDER_PHASE_BUILD = 1,     /* integral block V_A (eq. cholesky) */
+  CC_LADDER_PHASE_CONTRACT = 2,  /* R += t . V_A (eq. vfunction) */
+  CC_LADDER_PHASE_DT = 3,        /* adjoint: dt += lam . V_A */
+  CC_LADDER_PHASE_W = 4,         /* adjoint: W_A = lam^T t */
+  CC_LADDER_PHASE_DL = 5,        /* adjoint: both dL terms */
+  CC_LADDER_PHASE_SLICE = 6      /* split-bf16: slicing of the integral block */
+} cc_ladder_phase;
+
+/* Called on the host right before (end = 0) and right after (end = 1) the
+ * kernels of one phase of integral block `block` are enqueued on `stream`, so
+ * the caller can record events there.  Must not call back into the library. */
+typedef void (*cc_ladder_trace_fn)(void* user, int phase, int block, int end, hipStream_t stream);
+
 /* Optional controls; a zero-initialised struct (or NULL) selects everything automatically. */
 typedef struct {
   int    a_block;          /* virtuals per integral block; 0 = largest that fits hbm_budget */
   int    split_slices;     /* SPLIT_BF16 slice count s in [2, 6]; 0 = 4.  Products kept: p+q <= s+1 */
   int    k_chunk;          /* FP32 drain interval along the contracted index (multiple of 64); 0 = 512 */
   int    reserved;         /* must be 0 */
-  size_t hbm_budget;       /* bytes the library may use for scratch; 0 = half the free device memory */
+  size_t hbm_budget;       /* bytes the library may use for scratch; 0 = half the free device
+                              memory, at most 64 GiB */
   void*  workspace;        /* caller scratch (device, 256-byte aligned) or NULL */
   size_t workspace_bytes;  /* its size; the plan must fit in it */
+  cc_ladder_trace_fn trace;  /* optional per-phase hook, NULL = none */
+  void*  trace_user;       /* passed back to `trace` */
 } cc_ladder_opts;
 
 /*

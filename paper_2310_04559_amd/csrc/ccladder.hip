@@ -223,19 +223,23 @@ int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream
 
 template <class Tr>
 int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t, double* R,
-                   typename Tr::T* V, hipStream_t s) {
+                   typename Tr::T* V, const Tracer& tr, hipStream_t s) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
-  for (int a0 = 0; a0 < v; a0 += pl.n_a) {
+  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
     const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
     // V_A[a][b][c][d]: rows (a,c) of L's block, columns (b,d) of L, K = x
+    tr(CC_LADDER_PHASE_BUILD, blk, 0);
     int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + (long long)a0 * v, v2, L, v2, V, 0, na * v,
                                                static_cast<int>(v2), P, v, drain, s);
+    tr(CC_LADDER_PHASE_BUILD, blk, 1);
     if (rc) return rc;
     // R[(ij)][a0*v + (a,b)] += t[(ij)][(cd)] . V_A[(ab)][(cd)]
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
     rc = launch_gemm<Tr, KC, KC, EPI_ACC>(t, v2, V, v2, R + (long long)a0 * v, v2, o * o, na * v,
                                           static_cast<int>(v2), v, drain, s);
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
     if (rc) return rc;
   }
   return CC_LADDER_OK;
@@ -244,31 +248,39 @@ int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T
 template <class Tr>
 int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t,
                     const typename Tr::T* lam, double* dL, double* dt, typename Tr::T* V,
-                    typename Tr::T* W, hipStream_t s) {
+                    typename Tr::T* W, const Tracer& tr, hipStream_t s) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
-  for (int a0 = 0; a0 < v; a0 += pl.n_a) {
+  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
     const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
     const long long off = (long long)a0 * v;
+    tr(CC_LADDER_PHASE_BUILD, blk, 0);
     int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + off, v2, L, v2, V, 0, na * v,
                                                static_cast<int>(v2), P, v, drain, s);
+    tr(CC_LADDER_PHASE_BUILD, blk, 1);
     if (rc) return rc;
     // dt[(ij)][(cd)] += lam[(ij)][a0*v + (ab)] . V_A[(ab)][(cd)]
+    tr(CC_LADDER_PHASE_DT, blk, 0);
     rc = launch_gemm<Tr, KC, RC, EPI_ACC>(lam + off, v2, V, v2, dt, v2, o * o,
                                           static_cast<int>(v2), na * v, v, drain, s);
+    tr(CC_LADDER_PHASE_DT, blk, 1);
     if (rc) return rc;
     // W'_A[a][c][b][d] = sum_(ij) lam[(ij)][a0*v + (ab)] t[(ij)][(cd)]
+    tr(CC_LADDER_PHASE_W, blk, 0);
     rc = launch_gemm<Tr, RC, RC, EPI_PERM>(lam + off, v2, t, v2, W, 0, na * v,
                                            static_cast<int>(v2), o * o, v, drain, s);
+    tr(CC_LADDER_PHASE_W, blk, 1);
     if (rc) return rc;
+    tr(CC_LADDER_PHASE_DL, blk, 0);
     // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]
     rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
                                           static_cast<int>(v2), v, drain, s);
-    if (rc) return rc;
     // dL[x][(bd)] += L[x][a0*v + (ac)] . W'_A[(ac)][(bd)]
-    rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
-                                          na * v, v, drain, s);
+    if (!rc)
+      rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
+                                            na * v, v, drain, s);
+    tr(CC_LADDER_PHASE_DL, blk, 1);
     if (rc) return rc;
   }
   return CC_LADDER_OK;
@@ -297,20 +309,24 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
   rc = plan_and_scratch(o, v, P, precision, 0, stream, opts, &pl, &ws);
   if (rc) return rc;
   char* base = ws.base;
+  const Tracer tr(opts, stream);
   switch (precision) {
     case CC_LADDER_FP64:
-      return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V), stream);
+      return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V), tr,
+                                   stream);
     case CC_LADDER_FP32: {
       float* L32 = reinterpret_cast<float*>(base + pl.off_L);
       float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+      tr(CC_LADDER_PHASE_PREP, 0, 0);
       rc = to_f32(L, L32, (size_t)P * v * v, stream);
       if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
+      tr(CC_LADDER_PHASE_PREP, 0, 1);
       if (rc) return rc;
-      return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V),
+      return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V), tr,
                                    stream);
     }
     case CC_LADDER_SPLIT_BF16:
-      return split_forward(pl, L, t, R, base, stream);
+      return split_forward(pl, L, t, R, base, tr, stream);
     default:
       return CC_LADDER_EINVAL;
   }
@@ -338,21 +354,24 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
   rc = plan_and_scratch(o, v, P, precision, 1, stream, opts, &pl, &ws);
   if (rc) return rc;
   char* base = ws.base;
+  const Tracer tr(opts, stream);
   if (precision == CC_LADDER_FP64) {
     return backward_blocks<TrF64>(pl, L, t, lam, dL, dt,
                                   reinterpret_cast<double*>(base + pl.off_V),
-                                  reinterpret_cast<double*>(base + pl.off_W), stream);
+                                  reinterpret_cast<double*>(base + pl.off_W), tr, stream);
   }
   float* L32 = reinterpret_cast<float*>(base + pl.off_L);
   float* t32 = reinterpret_cast<float*>(base + pl.off_t);
   float* lam32 = reinterpret_cast<float*>(base + pl.off_lam);
+  tr(CC_LADDER_PHASE_PREP, 0, 0);
   rc = to_f32(L, L32, (size_t)P * v * v, stream);
   if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
   if (!rc) rc = to_f32(lam, lam32, (size_t)o * o * v * v, stream);
+  tr(CC_LADDER_PHASE_PREP, 0, 1);
   if (rc) return rc;
   return backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dt,
                                 reinterpret_cast<float*>(base + pl.off_V),
-                                reinterpret_cast<float*>(base + pl.off_W), stream);
+                                reinterpret_cast<float*>(base + pl.off_W), tr, stream);
 }
 
 extern "C" int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out_dev,

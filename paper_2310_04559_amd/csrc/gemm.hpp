@@ -53,6 +53,7 @@ struct TrF64 {
   static constexpr int CH = 2;     // elements per 16-byte chunk = MFMA steps per k-group
   static constexpr int BK = 16;    // K per LDS stage
   static constexpr bool kDrain = false;
+  static constexpr int kWaves = 2;  // waves per SIMD the register budget is sized for
   __device__ static inline Acc mfma(double a, double b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -68,6 +69,7 @@ struct TrF32 {
   static constexpr int CH = 4;
   static constexpr int BK = 32;
   static constexpr bool kDrain = true;
+  static constexpr int kWaves = 1;  // float64 drain registers double the accumulator footprint
   __device__ static inline Acc mfma(float a, float b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -116,25 +118,50 @@ struct TileIO {
     }
   }
 
-  template <bool VEC>
-  __device__ static inline void load(Chunk (&r)[NCH], const T* __restrict__ p, long long ld,
-                                     int row0, int nrows, int k0, int K, bool full, int tid) {
+  // Chunk c of a thread sits a fixed, thread-independent distance from its chunk 0:
+  // KC: rows advance by kThreads*CH/BK per chunk; RC: k advances by kThreads*CH/ROWS.
+  static constexpr int kChunkRows = (LAY == KC) ? kThreads * CH / BK : kThreads * CH / ROWS;
+  static_assert((LAY == KC ? BK / CH : ROWS / CH) <= kThreads, "chunk layout");
+
+  // Thread's chunk-0 address at the current K-step; chunks and K-steps are uniform strides.
+  struct Cursor {
+    const T* p;
+    long long cstride;  // elements from chunk c to chunk c+1
+    long long kstep;    // elements between consecutive K-steps
+  };
+
+  __device__ static inline void init(Cursor& cu, const T* __restrict__ base, long long ld, int row0,
+                                     int tid) {
+    int row, kk;
+    coord(0, tid, row, kk);
+    cu.p = base + ((LAY == KC) ? (long long)(row0 + row) * ld + kk
+                               : (long long)kk * ld + (row0 + row));
+    cu.cstride = (long long)kChunkRows * ld;
+    cu.kstep = (LAY == KC) ? BK : (long long)BK * ld;
+  }
+
+  __device__ static inline void advance(Cursor& cu) { cu.p += cu.kstep; }
+
+  // Whole tile in bounds and 16-byte aligned: one vector load per chunk.
+  __device__ static inline void load_full(Chunk (&r)[NCH], const Cursor& cu) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+      r[c] = *reinterpret_cast<const Chunk*>(cu.p + c * cu.cstride);
+  }
+
+  // Any tile: element loads, zero outside [0, nrows) x [0, K).
+  __device__ static inline void load_masked(Chunk (&r)[NCH], const Cursor& cu, int row0, int nrows,
+                                            int k0, int K, int tid) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       int row, kk;
       coord(c, tid, row, kk);
-      const long long off = (LAY == KC) ? (long long)(row0 + row) * ld + (k0 + kk)
-                                        : (long long)(k0 + kk) * ld + (row0 + row);
-      const T* src = p + off;
-      if (VEC && full) {
-        r[c] = *reinterpret_cast<const Chunk*>(src);
-      } else {
+      const T* src = cu.p + c * cu.cstride;
 #pragma unroll
-        for (int e = 0; e < CH; ++e) {
-          const bool ok = (LAY == KC) ? (row0 + row < nrows && k0 + kk + e < K)
-                                      : (k0 + kk < K && row0 + row + e < nrows);
-          r[c][e] = ok ? src[e] : T(0);
-        }
+      for (int e = 0; e < CH; ++e) {
+        const bool ok = (LAY == KC) ? (row0 + row < nrows && k0 + kk + e < K)
+                                    : (k0 + kk < K && row0 + row + e < nrows);
+        r[c][e] = ok ? src[e] : T(0);
       }
     }
   }
@@ -180,15 +207,120 @@ __device__ inline void tile_of(int bid, int nwg, int tiles_m, int group_m, int& 
   tn = in / rows;
 }
 
-template <class Tr, int LA, int LB, int EPI, bool VEC>
-__global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs<typename Tr::T> g) {
-  using T = typename Tr::T;
-  using Acc = typename Tr::Acc;
+// K loop of one tile.  FAST: the tile lies inside M x N and its operands are
+// 16-byte aligned, so every full K-step is one vector load per chunk with no
+// test; only a ragged last K-step is masked.  Otherwise every load is masked.
+template <class Tr, int LA, int LB, bool FAST>
+__device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g, int m0, int n0,
+                                              typename Tr::T* sA0, typename Tr::T* sA1,
+                                              typename Tr::T* sB0, typename Tr::T* sB1,
+                                              typename Tr::Acc (&acc)[4][4],
+                                              f64x4 (&acc64)[4][4]) {
   using IA = TileIO<Tr, LA, kBM>;
   using IB = TileIO<Tr, LB, kBN>;
   constexpr int BK = Tr::BK;
   constexpr int CH = Tr::CH;
   constexpr int NG = BK / (CH * 4);  // k-groups per stage
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * 64;
+  const int nk = (g.K + BK - 1) / BK;
+  const int nkf = FAST ? g.K / BK : 0;  // K-steps loaded without masks
+
+  typename IA::Cursor ca;
+  typename IB::Cursor cb;
+  IA::init(ca, g.A, g.lda, m0, tid);
+  IB::init(cb, g.B, g.ldb, n0, tid);
+  typename IA::Chunk ra[IA::NCH];
+  typename IB::Chunk rb[IB::NCH];
+
+  auto fetch = [&](int kt) {
+    if (kt < nkf) {
+      IA::load_full(ra, ca);
+      IB::load_full(rb, cb);
+    } else {
+      IA::load_masked(ra, ca, m0, g.M, kt * BK, g.K, tid);
+      IB::load_masked(rb, cb, n0, g.N, kt * BK, g.K, tid);
+    }
+    IA::advance(ca);
+    IB::advance(cb);
+  };
+  auto compute = [&](const typename Tr::T* sa, const typename Tr::T* sb) {
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      typename Tr::Chunk fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = IA::frag(sa, wm + 16 * i, gi, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = IB::frag(sb, wn + 16 * j, gi, lane);
+#pragma unroll
+      for (int e = 0; e < CH; ++e)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][e], fb[j][e], acc[i][j]);
+    }
+  };
+  int until_drain = g.drain_steps;
+  auto drain = [&](bool last) {
+    if (!Tr::kDrain) return;
+    if (--until_drain != 0 && !last) return;
+    until_drain = g.drain_steps;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc64[i][j][r] += static_cast<double>(acc[i][j][r]);
+          acc[i][j][r] = 0;
+        }
+  };
+
+  fetch(0);
+  IA::store(sA0, ra, tid);
+  IB::store(sB0, rb, tid);
+  __syncthreads();
+  int kt = 0;
+  // Steady state, two K-steps per trip so the LDS stages stay compile-time.
+  for (; kt + 2 < nkf; kt += 2) {
+    fetch(kt + 1);
+    compute(sA0, sB0);
+    drain(false);
+    IA::store(sA1, ra, tid);
+    IB::store(sB1, rb, tid);
+    __syncthreads();
+    fetch(kt + 2);
+    compute(sA1, sB1);
+    drain(false);
+    IA::store(sA0, ra, tid);
+    IB::store(sB0, rb, tid);
+    __syncthreads();
+  }
+  // Remaining steps (masked loads where needed); stage parity follows kt.
+  for (; kt < nk; ++kt) {
+    typename Tr::T* sa = (kt & 1) ? sA1 : sA0;
+    typename Tr::T* sb = (kt & 1) ? sB1 : sB0;
+    const bool more = kt + 1 < nk;
+    if (more) fetch(kt + 1);
+    compute(sa, sb);
+    drain(!more);
+    if (more) {
+      IA::store((kt & 1) ? sA0 : sA1, ra, tid);
+      IB::store((kt & 1) ? sB0 : sB1, rb, tid);
+    }
+    __syncthreads();
+  }
+}
+
+template <class Tr, int LA, int LB, int EPI, bool VEC>
+__global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typename Tr::T> g) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  using IA = TileIO<Tr, LA, kBM>;
+  using IB = TileIO<Tr, LB, kBN>;
 
   __shared__ __attribute__((aligned(16))) T sA[2][IA::ELEMS];
   __shared__ __attribute__((aligned(16))) T sB[2][IB::ELEMS];
@@ -214,60 +346,11 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs<typename Tr:
       acc64[i][j] = f64x4{0, 0, 0, 0};
     }
 
-  const int nk = (g.K + BK - 1) / BK;
-  const bool rows_full = (m0 + kBM <= g.M) && (n0 + kBN <= g.N);
-
-  typename IA::Chunk ra[IA::NCH];
-  typename IB::Chunk rb[IB::NCH];
-
-  {
-    const bool full = rows_full && (BK <= g.K);
-    IA::template load<VEC>(ra, g.A, g.lda, m0, g.M, 0, g.K, full, tid);
-    IB::template load<VEC>(rb, g.B, g.ldb, n0, g.N, 0, g.K, full, tid);
-    IA::store(sA[0], ra, tid);
-    IB::store(sB[0], rb, tid);
-  }
-  __syncthreads();
-
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      const int k1 = (kt + 1) * BK;
-      const bool full = rows_full && (k1 + BK <= g.K);
-      IA::template load<VEC>(ra, g.A, g.lda, m0, g.M, k1, g.K, full, tid);
-      IB::template load<VEC>(rb, g.B, g.ldb, n0, g.N, k1, g.K, full, tid);
-    }
-#pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-      typename Tr::Chunk fa[4], fb[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) fa[i] = IA::frag(sA[cur], wm + 16 * i, gi, lane);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) fb[j] = IB::frag(sB[cur], wn + 16 * j, gi, lane);
-#pragma unroll
-      for (int e = 0; e < CH; ++e)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][e], fb[j][e], acc[i][j]);
-    }
-    if (Tr::kDrain && ((kt + 1) % g.drain_steps == 0 || kt + 1 == nk)) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            acc64[i][j][r] += static_cast<double>(acc[i][j][r]);
-            acc[i][j][r] = 0;
-          }
-    }
-    if (kt + 1 < nk) {
-      IA::store(sA[cur ^ 1], ra, tid);
-      IB::store(sB[cur ^ 1], rb, tid);
-    }
-    __syncthreads();
-  }
+  const bool interior = (m0 + kBM <= g.M) && (n0 + kBN <= g.N);
+  if (VEC && interior)
+    tile_mainloop<Tr, LA, LB, true>(g, m0, n0, sA[0], sA[1], sB[0], sB[1], acc, acc64);
+  else
+    tile_mainloop<Tr, LA, LB, false>(g, m0, n0, sA[0], sA[1], sB[0], sB[1], acc, acc64);
 
   // Epilogue: lane holds column lane%16 of each 16x16 block, rows Tr::row_of(lane, r).
   const int col = lane & 15;

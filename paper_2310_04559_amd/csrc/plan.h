@@ -42,6 +42,18 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
 int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
               const cc_ladder_opts* opts, Plan* plan);
 
+// Forwards phase boundaries to the caller's optional trace hook.
+struct Tracer {
+  cc_ladder_trace_fn fn = nullptr;
+  void* user = nullptr;
+  hipStream_t stream = nullptr;
+  Tracer(const cc_ladder_opts* o, hipStream_t s)
+      : fn(o ? o->trace : nullptr), user(o ? o->trace_user : nullptr), stream(s) {}
+  void operator()(int phase, int block, int end) const {
+    if (fn) fn(user, phase, block, end, stream);
+  }
+};
+
 // Argument checks shared by every entry point (dimensions, precision, options).
 int check_dims(int o, int v, int P);
 int check_precision_opts(int precision, const cc_ladder_opts* opts);

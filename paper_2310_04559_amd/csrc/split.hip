@@ -3,7 +3,8 @@
 
 namespace ccl {
 
-int split_forward(const Plan&, const double*, const double*, double*, char*, hipStream_t) {
+int split_forward(const Plan&, const double*, const double*, double*, char*, const Tracer&,
+                  hipStream_t) {
   return CC_LADDER_EUNSUPPORTED;
 }
 

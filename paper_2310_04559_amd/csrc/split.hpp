@@ -9,6 +9,6 @@
 namespace ccl {
 
 int split_forward(const Plan& pl, const double* L, const double* t, double* R, char* ws,
-                  hipStream_t stream);
+                  const Tracer& tr, hipStream_t stream);
 
 }  // namespace ccl

@@ -41,7 +41,14 @@ class CcLadderOpts(ctypes.Structure):
         ("hbm_budget", ctypes.c_size_t),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+        ("trace", ctypes.c_void_p),
+        ("trace_user", ctypes.c_void_p),
     ]
+
+
+TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_void_p)
+PHASES = {0: "prep", 1: "build", 2: "contract", 3: "dt", 4: "W", 5: "dL", 6: "slice"}
 
 
 class LadderError(RuntimeError):
@@ -83,7 +90,8 @@ def strerror(code: int) -> str:
 
 
 def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
-              workspace: Optional[torch.Tensor] = None) -> CcLadderOpts:
+              workspace: Optional[torch.Tensor] = None, trace=None) -> CcLadderOpts:
+    """``trace`` is a TRACE_FN (keep a reference to it while the options are in use)."""
     o = CcLadderOpts()
     o.a_block = int(a_block)
     o.split_slices = int(split_slices)
@@ -93,6 +101,9 @@ def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_bud
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if trace is not None:
+        o.trace = ctypes.cast(trace, ctypes.c_void_p)
+        o._trace_ref = trace
     return o
 
 

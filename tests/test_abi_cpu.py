@@ -33,8 +33,9 @@ def test_exports_every_declared_symbol(native):
 
 
 def test_opts_struct_layout(native):
-    # int a_block, split_slices, k_chunk, reserved; size_t budget; void* ws; size_t ws_bytes
-    assert ctypes.sizeof(native.CcLadderOpts) == 4 * 4 + 8 * 3
+    # int a_block, split_slices, k_chunk, reserved; size_t budget; void* ws; size_t ws_bytes;
+    # trace hook and its user pointer
+    assert ctypes.sizeof(native.CcLadderOpts) == 4 * 4 + 8 * 5
 
 
 def test_strerror(native):
