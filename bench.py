@@ -31,9 +31,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 at rel err"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}  # MI355X dense MFMA
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9}
-DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16"}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_bf16_s2": 2500.0,
+               "split_bf16_s3": 2500.0}  # MI355X dense MFMA
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9, "split_bf16_s2": 8 * 2.0 ** -16,
+       "split_bf16_s3": 8 * 2.0 ** -24}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split_bf16_s2": "bf16",
+         "split_bf16_s3": "bf16"}
+# form -> (precision enum name, digit slices); split_bf16 is the 4-slice (10-product) form
+FORMS = {"fp64": ("fp64", 0), "fp32": ("fp32", 0), "split_bf16": ("split_bf16", 4),
+         "split_bf16_s2": ("split_bf16", 2), "split_bf16_s3": ("split_bf16", 3)}
+
+
+def mfma_products(form):
+    """Slice products per nominal product (executed MFMA work multiplier)."""
+    s = FORMS[form][1]
+    return s * (s + 1) // 2 if s else 1
 KERNEL_SRC = [os.path.join(ROOT, "paper_2310_04559_amd", "csrc", f)
               for f in ("gemm.hpp", "ccladder.hip", "split.hip", "split.hpp")]
 
@@ -115,12 +127,14 @@ def sampled_pairs(v, n, seed):
 def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
     import torch
 
-    prec = native.PRECISIONS[form]
+    prec = native.PRECISIONS[FORMS[form][0]]
+    slices = FORMS[form][1]
     stream = torch.cuda.current_stream()
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, prec, hbm_budget=ws_bytes)
+    nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, prec, hbm_budget=ws_bytes,
+                                                   opts=native.make_opts(split_slices=slices))
     timer = PhaseTimer(native, stream)
-    opts = native.make_opts(workspace=ws, trace=timer.fn)
+    opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices)
 
     def step():
         native.cc_ladder_residual(L, t, R, prec, opts=opts)
@@ -151,7 +165,8 @@ def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
 
     R = torch.zeros_like(t)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    native.cc_ladder_residual(L, t, R, native.PRECISIONS[form], opts=native.make_opts(workspace=ws))
+    native.cc_ladder_residual(L, t, R, native.PRECISIONS[FORMS[form][0]],
+                              opts=native.make_opts(workspace=ws, split_slices=FORMS[form][1]))
     torch.cuda.synchronize()
     got = R[:, :, idx_a, idx_b].permute(2, 0, 1).cpu().numpy()
     del R, ws
@@ -229,10 +244,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=list(PEAK_TFLOPS))
-    ap.add_argument("--forms", default="fp64,fp32,split_bf16")
+    ap.add_argument("--precision", default="fp64", choices=list(FORMS))
+    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -254,6 +272,15 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
+        del src, dst
     o, v, P = CONFIGS["c3"]
     t0 = time.perf_counter()
     inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
@@ -290,12 +317,14 @@ def main():
         if c:
             per_step = c["launches"] / args.steps  # launches of the kernel in one step
             launch_flops = 2.0 * o * o * float(v) ** 4 / per_step
-            achieved = launch_flops / (c["ms_avg"] * 1e-3) / 1e12
+            # executed MFMA flops: the split forms run S(S+1)/2 slice products per product
+            achieved = mfma_products(form) * launch_flops / (c["ms_avg"] * 1e-3) / 1e12
             r["roofline"] = {"kernel": "contract", "bound": "mfma", "achieved": achieved,
                              "peak": PEAK_TFLOPS[form], "unit": "TFLOP/s",
                              "frac": achieved / PEAK_TFLOPS[form],
                              "traffic": read_traffic("contract", form),
-                             "flops_per_launch": launch_flops}
+                             "flops_per_launch": mfma_products(form) * launch_flops,
+                             "nominal_tflops": launch_flops / (c["ms_avg"] * 1e-3) / 1e12}
         b = r["phases"].get("build")
         if b:
             bflops = 2.0 * P * float(v) ** 4 / (b["launches"] / args.steps)

@@ -75,9 +75,11 @@ typedef void (*cc_ladder_trace_fn)(void* user, int phase, int block, int end, hi
 /* Optional controls; a zero-initialised struct (or NULL) selects everything automatically. */
 typedef struct {
   int    a_block;          /* virtuals per integral block; 0 = largest that fits hbm_budget */
-  int    split_slices;     /* SPLIT_BF16 slice count s in [2, 6]; 0 = 4.  Products kept: p+q <= s+1 */
+  int    split_slices;     /* SPLIT_BF16 digit slices S in [2, 4]; 0 = 4 */
   int    k_chunk;          /* FP32 drain interval along the contracted index (multiple of 64); 0 = 512 */
-  int    reserved;         /* must be 0 */
+  int    split_depth;      /* SPLIT_BF16 slice products (p,q), 1-based, kept when p+q <= S+depth,
+                              depth in [1, 2]; 0 = 2 for S = 4 (13 products), 1 otherwise
+                              (S = 2: 3 products, S = 3: 6) */
   size_t hbm_budget;       /* bytes the library may use for scratch; 0 = half the free device
                               memory, at most 64 GiB */
   void*  workspace;        /* caller scratch (device, 256-byte aligned) or NULL */

@@ -1,6 +1,8 @@
 // Host-only planner: buffer layout and block-size selection.
 #include "plan.h"
 
+#include "split.hpp"
+
 #include <cstdint>
 
 namespace ccl {
@@ -32,8 +34,8 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
       precision != CC_LADDER_SPLIT_BF16)
     return CC_LADDER_EINVAL;
   if (!opts) return CC_LADDER_OK;
-  if (opts->a_block < 0 || opts->reserved != 0) return CC_LADDER_EINVAL;
-  if (opts->split_slices != 0 && (opts->split_slices < 2 || opts->split_slices > 6))
+  if (opts->a_block < 0 || opts->split_depth < 0 || opts->split_depth > 2) return CC_LADDER_EINVAL;
+  if (opts->split_slices != 0 && (opts->split_slices < 2 || opts->split_slices > 4))
     return CC_LADDER_EINVAL;
   if (opts->k_chunk < 0 || opts->k_chunk % 64 != 0) return CC_LADDER_EINVAL;
   if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
@@ -42,7 +44,7 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
 }
 
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int k_chunk, Plan* plan) {
+                int slices, int depth, int k_chunk, Plan* plan) {
   if (n_a < 1 || n_a > v) return CC_LADDER_EINVAL;
   Plan p;
   p.o = o; p.v = v; p.P = P;
@@ -68,20 +70,21 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       if (p.backward) p.off_W = take(&cur, blk * sizeof(float));
       break;
     case CC_LADDER_SPLIT_BF16: {
-      p.slices = slices ? slices : 4;
-      const size_t s = static_cast<size_t>(p.slices);
-      // slices are stored with the contracted index padded to a multiple of 64
-      const size_t Pp = (static_cast<size_t>(P) + 63) / 64 * 64;
-      const size_t v2p = (v2 + 63) / 64 * 64;
-      // L is cut twice: along x for the integral build (rows (p,q), K = x)
-      p.off_L = take(&cur, s * v2 * Pp * 2);
-      p.off_Lexp = take(&cur, v2 * sizeof(int));
-      p.off_t = take(&cur, s * o2 * v2p * 2);
-      p.off_texp = take(&cur, o2 * sizeof(int));
-      p.off_V = take(&cur, blk * sizeof(double));
-      p.off_Vs = take(&cur, s * static_cast<size_t>(n_a) * v * v2p * 2);
-      p.off_Vexp = take(&cur, static_cast<size_t>(n_a) * v * sizeof(int));
       if (p.backward) return CC_LADDER_EUNSUPPORTED;
+      p.slices = slices ? slices : 4;
+      // automatic depth: the 4-slice form keeps the triangle's next anti-diagonal
+      p.split_depth = depth ? depth : (p.slices == 4 ? 2 : 1);
+      const size_t s = static_cast<size_t>(p.slices);
+      const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
+      const SliceDims dt = slice_dims(static_cast<long long>(o2), static_cast<int>(v2));
+      const SliceDims dV = slice_dims(static_cast<long long>(n_a) * v, static_cast<int>(v2));
+      p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad * 2);
+      p.off_Lexp = take(&cur, static_cast<size_t>(dL.rows_pad) * sizeof(int));
+      p.off_t = take(&cur, s * dt.rows_pad * dt.k_pad * 2);
+      p.off_texp = take(&cur, static_cast<size_t>(dt.rows_pad) * sizeof(int));
+      p.off_V = take(&cur, blk * sizeof(double));
+      p.off_Vs = take(&cur, s * dV.rows_pad * dV.k_pad * 2);
+      p.off_Vexp = take(&cur, static_cast<size_t>(dV.rows_pad) * sizeof(int));
       break;
     }
     default:
@@ -99,23 +102,24 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   rc = check_precision_opts(precision, opts);
   if (rc) return rc;
   const int slices = opts ? opts->split_slices : 0;
+  const int depth = opts ? opts->split_depth : 0;
   const int k_chunk = opts ? opts->k_chunk : 0;
   if (opts && opts->a_block > 0) {
     const int n_a = opts->a_block < v ? opts->a_block : v;
-    rc = layout_plan(o, v, P, precision, backward, n_a, slices, k_chunk, plan);
+    rc = layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, plan);
     if (rc) return rc;
     return (budget && plan->bytes > budget) ? CC_LADDER_ENOMEM : CC_LADDER_OK;
   }
   // Largest block that fits: the footprint grows monotonically with n_a.
   Plan best;
-  rc = layout_plan(o, v, P, precision, backward, 1, slices, k_chunk, &best);
+  rc = layout_plan(o, v, P, precision, backward, 1, slices, depth, k_chunk, &best);
   if (rc) return rc;
   if (budget && best.bytes > budget) return CC_LADDER_ENOMEM;
   int lo = 1, hi = v;
   while (lo < hi) {
     const int mid = lo + (hi - lo + 1) / 2;
     Plan trial;
-    rc = layout_plan(o, v, P, precision, backward, mid, slices, k_chunk, &trial);
+    rc = layout_plan(o, v, P, precision, backward, mid, slices, depth, k_chunk, &trial);
     if (rc) return rc;
     if (!budget || trial.bytes <= budget) {
       lo = mid;
@@ -128,7 +132,7 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   const int nb = (v + best.n_a - 1) / best.n_a;
   const int n_eq = (v + nb - 1) / nb;
   if (n_eq != best.n_a) {
-    rc = layout_plan(o, v, P, precision, backward, n_eq, slices, k_chunk, &best);
+    rc = layout_plan(o, v, P, precision, backward, n_eq, slices, depth, k_chunk, &best);
     if (rc) return rc;
   }
   *plan = best;

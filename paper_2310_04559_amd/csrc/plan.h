@@ -20,6 +20,7 @@ struct Plan {
   int n_a = 0;          // virtuals per integral block
   int nblocks = 0;      // ceil(v / n_a)
   int slices = 0;       // split-bf16 slice count (0 for the other forms)
+  int split_depth = 0;  // split-bf16 anti-diagonals kept beyond the slice triangle (1 or 2)
   int k_chunk = 0;      // float32 drain interval along the contracted index
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;
@@ -35,7 +36,7 @@ struct Plan {
 
 // Fills `plan` for a block size of n_a (1 <= n_a <= v).  Returns 0 or CC_LADDER_EINVAL.
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int k_chunk, Plan* plan);
+                int slices, int depth, int k_chunk, Plan* plan);
 
 // Picks n_a (honouring opts->a_block when set) so that plan.bytes <= budget
 // (budget 0 = unlimited).  Returns 0, CC_LADDER_EINVAL or CC_LADDER_ENOMEM.

@@ -8,6 +8,21 @@
 
 namespace ccl {
 
+// Geometry of a digit buffer [S][rows_pad][k_pad]: rows padded so that every
+// workgroup tile of a product stays inside it, the contracted index to whole
+// 32-deep MFMA steps (zero digits in the padding).
+struct SliceDims {
+  int rows_pad;
+  int k_pad;
+};
+
+inline SliceDims slice_dims(long long rows, int K) {
+  SliceDims d;
+  d.rows_pad = static_cast<int>((rows + 127) / 128 * 128 + 128);
+  d.k_pad = (K + 63) / 64 * 64;
+  return d;
+}
+
 int split_forward(const Plan& pl, const double* L, const double* t, double* R, char* ws,
                   const Tracer& tr, hipStream_t stream);
 

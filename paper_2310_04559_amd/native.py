@@ -37,7 +37,7 @@ class CcLadderOpts(ctypes.Structure):
         ("a_block", ctypes.c_int),
         ("split_slices", ctypes.c_int),
         ("k_chunk", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("split_depth", ctypes.c_int),
         ("hbm_budget", ctypes.c_size_t),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -90,13 +90,14 @@ def strerror(code: int) -> str:
 
 
 def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
-              workspace: Optional[torch.Tensor] = None, trace=None) -> CcLadderOpts:
+              workspace: Optional[torch.Tensor] = None, trace=None,
+              split_depth: int = 0) -> CcLadderOpts:
     """``trace`` is a TRACE_FN (keep a reference to it while the options are in use)."""
     o = CcLadderOpts()
     o.a_block = int(a_block)
     o.split_slices = int(split_slices)
     o.k_chunk = int(k_chunk)
-    o.reserved = 0
+    o.split_depth = int(split_depth)
     o.hbm_budget = int(hbm_budget)
     if workspace is not None:
         o.workspace = workspace.data_ptr()

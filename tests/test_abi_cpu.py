@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(native):
 
 
 def test_opts_struct_layout(native):
-    # int a_block, split_slices, k_chunk, reserved; size_t budget; void* ws; size_t ws_bytes;
+    # int a_block, split_slices, k_chunk, split_depth; size_t budget; void* ws; size_t ws_bytes;
     # trace hook and its user pointer
     assert ctypes.sizeof(native.CcLadderOpts) == 4 * 4 + 8 * 5
 
@@ -68,6 +68,18 @@ def test_planner_backward_and_fp32_footprints(native):
     assert n == v and b32 >= (P * v * v + o * o * v * v + v ** 4) * 4
 
 
+def test_planner_split_footprint(native):
+    # digit buffers: S slices of L (rows v^2, K = P padded to 64), of t and of
+    # one integral block, plus the float64 block itself
+    o, v, P = 4, 30, 50
+    b4, n = native.cc_ladder_workspace_query(o, v, P, "split_bf16")
+    b2, _ = native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(split_slices=2))
+    assert n == v and b4 > b2 >= v ** 4 * 8
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(o, v, P, "split_bf16", backward=True)
+    assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+
+
 def test_planner_explicit_block_and_enomem(native):
     opts = native.make_opts(a_block=7)
     nbytes, n_a = native.cc_ladder_workspace_query(5, 20, 75, "fp64", opts=opts)
@@ -89,7 +101,8 @@ def test_planner_rejects_bad_arguments(native, o, v, P, prec):
 
 
 def test_bad_options_rejected(native):
-    for kw in (dict(split_slices=1), dict(split_slices=9), dict(k_chunk=100), dict(a_block=-2)):
+    for kw in (dict(split_slices=1), dict(split_slices=5), dict(k_chunk=100), dict(a_block=-2),
+               dict(split_depth=3), dict(split_depth=-1)):
         with pytest.raises(native.LadderError) as e:
             native.cc_ladder_workspace_query(3, 8, 10, "fp32", opts=native.make_opts(**kw))
         assert e.value.code == native.CC_LADDER_EINVAL

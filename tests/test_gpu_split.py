@@ -1,0 +1,106 @@
+"""GPU parity of the split-bf16 form (exponent-aligned bf16 digits, exact
+float32 chunks drained to float64) against the float64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2310_04559_amd.inputs import (CONFIGS, integer_inputs, make_inputs, random_general,
+                                         seed_for)
+from tests import split_model
+from tests.gpu_common import TOL_SPLIT, TOL_SPLIT_WORKLOAD, announce, dev, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+SPLIT = 2
+
+
+def run_split(native, L, t, R0, slices, **kw):
+    R = dev(R0)
+    native.cc_ladder_residual(dev(L), dev(t), R, SPLIT,
+                              opts=native.make_opts(split_slices=slices, **kw))
+    torch.cuda.synchronize()
+    return host(R)
+
+
+@pytest.mark.parametrize("slices,depth", [(2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)])
+@pytest.mark.parametrize("o,v,P", [(5, 20, 75), (9, 37, 101), (3, 44, 131)])
+def test_split_kernel_implements_the_digit_scheme(gpu_lib, o, v, P, slices, depth):
+    # digit products and chunk sums are exact on both sides: only float64
+    # rounding of the drains separates the kernel from the scheme
+    announce("split-model", o, v, P, slices, depth)
+    L, t, _ = random_general(o, v, P, 500 + o + v)
+    model = split_model.ladder(L, t, slices, depth)
+    got = run_split(gpu_lib, L, t, np.zeros_like(t), slices, split_depth=depth, a_block=7)
+    assert rel_fro(got, model) < 1e-12
+
+
+@pytest.mark.parametrize("slices", [2, 3, 4])
+def test_split_integer_inputs_exact(gpu_lib, slices):
+    # small integers need one digit per operand and two for the integral block:
+    # every digit product and chunk sum is exact, so the result is bitwise exact
+    announce("split-int", slices)
+    L, t = integer_inputs(3, 10, 5, 77)
+    ref = oracle.ladder_forward(L, t)
+    assert np.array_equal(run_split(gpu_lib, L, t, np.zeros_like(t), slices), ref)
+
+
+@pytest.mark.parametrize("slices", [2, 3, 4])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (12, 44, 131, 0),
+                                           (3, 130, 17, 40), (1, 3, 1, 0), (16, 64, 200, 9)])
+def test_split_general_inputs(gpu_lib, o, v, P, a_block, slices):
+    announce("split", o, v, P, "a_block", a_block, "slices", slices)
+    L, t, _ = random_general(o, v, P, 300 + o + v + P)
+    R0 = np.random.default_rng(3).standard_normal(t.shape)
+    inc = oracle.ladder_forward(L, t)
+    got = run_split(gpu_lib, L, t, R0, slices, a_block=a_block)
+    assert rel_fro(got - R0, inc) < TOL_SPLIT[slices]
+
+
+@pytest.mark.parametrize("slices", [2, 4])
+def test_split_c1_workload(gpu_lib, slices):
+    o, v, P = CONFIGS["c1"]
+    announce("split-c1", slices)
+    inp = make_inputs(o, v, P, seed_for("c1"))
+    ref = oracle.ladder_forward(inp.L_vv, inp.t)
+    got = run_split(gpu_lib, inp.L_vv, inp.t, np.zeros_like(inp.t), slices)
+    assert rel_fro(got, ref) < TOL_SPLIT_WORKLOAD[slices]
+
+
+def test_split_bitwise_independent_of_block_size(gpu_lib):
+    announce("split-determinism")
+    L, t, _ = random_general(7, 40, 60, 12)
+    z = np.zeros_like(t)
+    ref = run_split(gpu_lib, L, t, z, 4)
+    for a_block in (1, 6, 40):
+        # the integral block's digit exponents are per (a,b) row: independent of blocking
+        assert np.array_equal(run_split(gpu_lib, L, t, z, 4, a_block=a_block), ref)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_split_full_size_sampled_entries(gpu_lib, name):
+    o, v, P = CONFIGS[name]
+    announce("split-full", name)
+    inp = make_inputs(o, v, P, seed_for(name), device="cuda")
+    Ld, td = dev(inp.L_vv), dev(inp.t)
+    rng = np.random.default_rng(4)
+    pairs = sorted({(0, 0), (v - 1, v - 1)} | {(int(rng.integers(0, v)), int(rng.integers(0, v)))
+                                               for _ in range(22)})
+    ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
+    ia = torch.tensor([a for a, _ in pairs], device="cuda")
+    ib = torch.tensor([b for _, b in pairs], device="cuda")
+    for slices in (2, 4):
+        R = torch.zeros_like(td)
+        gpu_lib.cc_ladder_residual(Ld, td, R, SPLIT, opts=gpu_lib.make_opts(split_slices=slices))
+        torch.cuda.synchronize()
+        got = host(R[:, :, ia, ib].permute(2, 0, 1))
+        assert rel_fro(got, ref) < TOL_SPLIT_WORKLOAD[slices], (name, slices)
+        del R
+
+
+def test_split_backward_is_unsupported(gpu_lib):
+    announce("split-backward")
+    L, t, lam = random_general(2, 6, 4, 5)
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_backward(dev(L), dev(t), dev(lam), dev(np.zeros_like(L)),
+                                   dev(np.zeros_like(t)), SPLIT)
+    assert e.value.code == gpu_lib.CC_LADDER_EUNSUPPORTED

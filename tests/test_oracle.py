@@ -325,3 +325,4 @@ def test_reduce_and_flops():
     y = np.ones(10) * 2
     assert oracle.reduce_dot(x, y) == (90.0, 40.0)
     assert oracle.nominal_flops_forward(40, 360, 1200) == pytest.approx(94.06e12, rel=1e-3)
+
