@@ -239,6 +239,58 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32")):
     return res
 
 
+def bench_large(native):
+    """The large single-GPU workload (o=60, v=600, P=1800): float64 and split-bf16
+    forwards and the float32 adjoint, one call each, planner-chosen blocks."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2310_04559_amd.inputs import CONFIGS, make_inputs, seed_for
+
+    o, v, P = CONFIGS["c5"]
+    inp = make_inputs(o, v, P, seed_for("c5"), with_lambda=True, device="cuda")
+    pairs = sampled_pairs(v, 8, 5)
+    ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
+    L = torch.from_numpy(inp.L_vv).cuda()
+    t = torch.from_numpy(inp.t).cuda()
+    lam = torch.from_numpy(inp.lam).cuda()
+    del inp
+    ia = torch.tensor([a for a, _ in pairs], device="cuda")
+    ib = torch.tensor([b for _, b in pairs], device="cuda")
+    fwd = 2.0 * (P + o * o) * float(v) ** 4
+    res = {"workload": f"o={o},v={v},P={P}", "nominal_tflop_forward": fwd / 1e12}
+    R = torch.zeros_like(t)
+    for form in ("fp64", "split_bf16"):
+        prec, slices = native.PRECISIONS[FORMS[form][0]], FORMS[form][1]
+        R.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        native.cc_ladder_residual(L, t, R, prec, opts=native.make_opts(split_slices=slices))
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        got = R[:, :, ia, ib].permute(2, 0, 1).cpu().numpy()
+        res[form] = {"ms": ms, "tflops": fwd / (ms * 1e-3) / 1e12,
+                     "rel_err_vs_oracle_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+        log(f"large {form}: {ms:.0f} ms {res[form]['tflops']:.1f} TFLOP/s")
+    del R
+    dL = torch.zeros_like(L)
+    dt = torch.zeros_like(t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    native.cc_ladder_backward(L, t, lam, dL, dt, native.CC_LADDER_FP32)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    bwd = (6.0 * P + 4.0 * o * o) * float(v) ** 4
+    res["adjoint_fp32"] = {"ms": ms, "tflops": bwd / (ms * 1e-3) / 1e12}
+    log(f"large adjoint fp32: {ms:.0f} ms {res['adjoint_fp32']['tflops']:.1f} TFLOP/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +300,8 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--large", action="store_true",
+                    help="also run the o=60, v=600, P=1800 workload (about two minutes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "reference for HBM byte counters)")
@@ -365,6 +419,9 @@ def main():
     if not args.no_adjoint:
         log("adjoint ...")
         line["adjoint"] = bench_adjoint(native, max(1, min(args.steps, 2)))
+    if args.large:
+        log("large workload ...")
+        line["large"] = bench_large(native)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(inp)

@@ -56,6 +56,14 @@ typedef enum {
                                 products on bf16 MFMA, exact float32 chunks drained to float64 */
 } cc_ladder_precision;
 
+/* opts.flags bits */
+#define CC_LADDER_PAIR_SYMMETRIC 1u  /* caller asserts t[i][j][c][d] == t[j][i][d][c] (true of CC
+                                        doubles amplitudes).  The integral then enters only through
+                                        its rows (a,b) with a <= b, stored packed, and each result
+                                        is added at both R[i][j][a][b] and R[j][i][b][a]: half the
+                                        build and half the contraction.  FP64 and FP32 forward only;
+                                        ignored by the adjoint; EUNSUPPORTED with SPLIT_BF16. */
+
 /* Kernel phases reported to an optional trace hook. */
 typedef enum {
   CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam */
@@ -86,6 +94,8 @@ typedef struct {
   size_t workspace_bytes;  /* its size; the plan must fit in it */
   cc_ladder_trace_fn trace;  /* optional per-phase hook, NULL = none */
   void*  trace_user;       /* passed back to `trace` */
+  unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC or 0 */
+  int    reserved;         /* must be 0 */
 } cc_ladder_opts;
 
 /*

@@ -18,6 +18,7 @@
 
 #include "ccladder.h"
 #include "gemm.hpp"
+#include "gemm_direct.hpp"
 #include "plan.h"
 #include "split.hpp"
 
@@ -68,10 +69,28 @@ bool vec_ok(const T* p, long long ld) {
   return (reinterpret_cast<uintptr_t>(p) % 16) == 0 && (ld % per16) == 0;
 }
 
+// Products with both operands K-contiguous and 16-byte aligned rows take the
+// direct-to-LDS kernel (128 x 256 tiles, 8 waves); everything else the
+// register-staged family.
+template <class Tr, int EPI>
+bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, int* rc) {
+  if (!vec_ok(g0.A, g0.lda) || !vec_ok(g0.B, g0.ldb)) return false;
+  GemmArgs<typename Tr::T> g = g0;
+  g.tiles_m = (g.M + kDBM - 1) / kDBM;
+  g.tiles_n = (g.N + kDBN - 1) / kDBN;
+  const long long tiles = (long long)g.tiles_m * g.tiles_n;
+  if (tiles > 0x7fffffffLL) return false;
+  g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
+  hipLaunchKernelGGL((gemm_kc_direct_kernel<Tr, EPI>), dim3(static_cast<unsigned>(tiles)),
+                     dim3(kDThreads), 0, stream, g);
+  *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+  return true;
+}
+
 template <class Tr, int LA, int LB, int EPI>
 int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
                 void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
-                hipStream_t stream) {
+                hipStream_t stream, int o = 0, int a0 = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
   GemmArgs<typename Tr::T> g;
   g.A = A; g.lda = lda;
@@ -79,6 +98,8 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   g.C = C; g.ldc = ldc;
   g.M = M; g.N = N; g.K = K;
   g.v = v;
+  g.o = o;
+  g.a0 = a0;
   g.tiles_m = (M + kBM - 1) / kBM;
   g.tiles_n = (N + kBN - 1) / kBN;
   const long long tiles = (long long)g.tiles_m * g.tiles_n;
@@ -87,6 +108,10 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   // both their row panels and a few column panels.
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
   g.drain_steps = drain_steps > 0 ? drain_steps : 1;
+  if (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
+    int rc = CC_LADDER_OK;
+    if (launch_kc_direct<Tr, EPI>(g, stream, &rc)) return rc;
+  }
   const dim3 grid(static_cast<unsigned>(tiles)), block(kThreads);
   if (vec_ok(A, lda) && vec_ok(B, ldb))
     hipLaunchKernelGGL((gemm_kernel<Tr, LA, LB, EPI, true>), grid, block, 0, stream, g);
@@ -229,6 +254,24 @@ int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
   for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
     const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+    if (pl.pairsym) {
+      // packed rows (a,b), a in the block, b >= a: columns (b,d) from b = a0 on
+      const long long off = (long long)a0 * v;
+      const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
+      tr(CC_LADDER_PHASE_BUILD, blk, 0);
+      int rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
+                                                 static_cast<int>((long long)(v - a0) * v), P, v,
+                                                 drain, s, o, a0);
+      tr(CC_LADDER_PHASE_BUILD, blk, 1);
+      if (rc) return rc;
+      // R[(ij)][(ab)] and R[(ji)][(ba)] += t[(ij)][(cd)] . V_A[pair(a,b)][(cd)]
+      tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
+      rc = launch_gemm<Tr, KC, KC, EPI_PAIR>(t, v2, V, v2, R, v2, o * o, static_cast<int>(npairs),
+                                             static_cast<int>(v2), v, drain, s, o, a0);
+      tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
+      if (rc) return rc;
+      continue;
+    }
     // V_A[a][b][c][d]: rows (a,c) of L's block, columns (b,d) of L, K = x
     tr(CC_LADDER_PHASE_BUILD, blk, 0);
     int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + (long long)a0 * v, v2, L, v2, V, 0, na * v,

@@ -18,6 +18,12 @@
 //             C[a*v^3 + y*v^2 + x*v + d] = acc            (stores, in the operand type, an
 //                                                          integral-shaped block with its
 //                                                          middle indices swapped)
+//   EPI_PACK: the build restricted to b >= a: m = (a - a0, c), n = (b - a0, d);
+//             C[(pair(a,b) - pair(a0,a0))*v^2 + c*v + d] = acc for b >= a, where
+//             pair(a,b) = prefix(a) + b - a numbers the rows a <= b (tiles wholly
+//             below the diagonal exit at once)
+//   EPI_PAIR: the contraction over packed rows: m = (i,j), n = pair(a,b) - pair(a0,a0);
+//             C[m*ldc + a*v + b] += acc and, for a != b, C[(j,i)*ldc + b*v + a] += acc
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, 128x128 workgroup tile, each
 // wave owns a 64x64 sub-tile = 4x4 MFMA 16x16 blocks.  Global tiles are read
@@ -43,7 +49,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 enum { KC = 0, RC = 1 };
-enum { EPI_ACC = 0, EPI_PERM = 1 };
+enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3 };
 
 // float64 operands on v_mfma_f64_16x16x4_f64.
 struct TrF64 {
@@ -54,6 +60,7 @@ struct TrF64 {
   static constexpr int BK = 16;    // K per LDS stage
   static constexpr bool kDrain = false;
   static constexpr int kWaves = 2;  // waves per SIMD the register budget is sized for
+  static constexpr bool kDirectKC = true;  // KC x KC products use the direct-to-LDS kernel
   __device__ static inline Acc mfma(double a, double b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -70,6 +77,7 @@ struct TrF32 {
   static constexpr int BK = 32;
   static constexpr bool kDrain = true;
   static constexpr int kWaves = 1;  // float64 drain registers double the accumulator footprint
+  static constexpr bool kDirectKC = true;
   __device__ static inline Acc mfma(float a, float b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -85,13 +93,60 @@ struct GemmArgs {
   void* C;          // EPI_ACC: double; EPI_PERM: T
   long long ldc;
   int M, N, K;
-  int v;             // EPI_PERM index split
+  int v;             // EPI_PERM/PACK/PAIR index split
+  int o;             // EPI_PAIR: occupied count (rows are (i,j))
+  int a0;            // EPI_PACK/PAIR: first virtual of the integral block
   int tiles_m, tiles_n;
   int group_m;       // tile-order swizzle: rows of tiles walked together
   int drain_steps;   // K-steps between float32 -> float64 drains (TrF32)
 };
 
 constexpr int kBM = 128, kBN = 128;
+
+// Number of packed rows (a', b) with a' < a, i.e. sum_{a' < a} (v - a').
+__device__ __forceinline__ long long pair_prefix_d(long long a, long long v) {
+  return a * v - a * (a - 1) / 2;
+}
+
+// Largest a with pair_prefix(a) <= q (q < v(v+1)/2).
+__device__ __forceinline__ int pair_row(long long q, int v) {
+  const double b = 2.0 * v + 1.0;
+  int a = static_cast<int>((b - sqrt(b * b - 8.0 * static_cast<double>(q))) * 0.5);
+  a = a < 0 ? 0 : (a >= v ? v - 1 : a);
+  while (a + 1 < v && pair_prefix_d(a + 1, v) <= q) ++a;
+  while (a > 0 && pair_prefix_d(a, v) > q) --a;
+  return a;
+}
+
+// Stores result element (m, n) of a product according to the epilogue mode.
+template <class T, int EPI>
+__device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, double val) {
+  const long long v = g.v;
+  if (EPI == EPI_ACC) {
+    static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
+  } else if (EPI == EPI_PERM) {
+    const int a = m / g.v, x = m - a * g.v;
+    const int y = n / g.v, d = n - y * g.v;
+    static_cast<T*>(g.C)[(long long)a * v * v * v + (long long)y * v * v + (long long)x * v + d] =
+        static_cast<T>(val);
+  } else if (EPI == EPI_PACK) {
+    const int al = m / g.v, c = m - al * g.v;
+    const int bl = n / g.v, d = n - bl * g.v;
+    if (bl < al) return;
+    const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (bl - al);
+    static_cast<T*>(g.C)[row * v * v + (long long)c * v + d] = static_cast<T>(val);
+  } else {  // EPI_PAIR
+    const long long q = pair_prefix_d(g.a0, v) + n;
+    const int a = pair_row(q, g.v);
+    const int b = a + static_cast<int>(q - pair_prefix_d(a, v));
+    double* C = static_cast<double*>(g.C);
+    C[(long long)m * g.ldc + (long long)a * v + b] += val;
+    if (a != b) {
+      const int i = m / g.o, j = m - i * g.o;
+      C[(long long)(j * g.o + i) * g.ldc + (long long)b * v + a] += val;
+    }
+  }
+}
 
 template <class Tr, int LAY, int ROWS>
 struct TileIO {
@@ -263,11 +318,10 @@ __device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g,
           for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][e], fb[j][e], acc[i][j]);
     }
   };
-  int until_drain = g.drain_steps;
-  auto drain = [&](bool last) {
+  // float32 forms: partial sums of one chunk of drain_steps K-steps stay in the
+  // MFMA accumulators and are drained into float64 once per chunk.
+  auto drain = [&]() {
     if (!Tr::kDrain) return;
-    if (--until_drain != 0 && !last) return;
-    until_drain = g.drain_steps;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -284,34 +338,37 @@ __device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g,
   IB::store(sB0, rb, tid);
   __syncthreads();
   int kt = 0;
-  // Steady state, two K-steps per trip so the LDS stages stay compile-time.
-  for (; kt + 2 < nkf; kt += 2) {
-    fetch(kt + 1);
-    compute(sA0, sB0);
-    drain(false);
-    IA::store(sA1, ra, tid);
-    IB::store(sB1, rb, tid);
-    __syncthreads();
-    fetch(kt + 2);
-    compute(sA1, sB1);
-    drain(false);
-    IA::store(sA0, ra, tid);
-    IB::store(sB0, rb, tid);
-    __syncthreads();
-  }
-  // Remaining steps (masked loads where needed); stage parity follows kt.
-  for (; kt < nk; ++kt) {
-    typename Tr::T* sa = (kt & 1) ? sA1 : sA0;
-    typename Tr::T* sb = (kt & 1) ? sB1 : sB0;
-    const bool more = kt + 1 < nk;
-    if (more) fetch(kt + 1);
-    compute(sa, sb);
-    drain(!more);
-    if (more) {
-      IA::store((kt & 1) ? sA0 : sA1, ra, tid);
-      IB::store((kt & 1) ? sB0 : sB1, rb, tid);
+  for (;;) {
+    const int kend = (Tr::kDrain && kt + g.drain_steps < nk) ? kt + g.drain_steps : nk;
+    // Steady state, two K-steps per trip so the LDS stages stay compile-time
+    // (chunks hold an even number of steps, so kt is even here).
+    for (; kt + 2 <= kend && kt + 2 < nkf; kt += 2) {
+      fetch(kt + 1);
+      compute(sA0, sB0);
+      IA::store(sA1, ra, tid);
+      IB::store(sB1, rb, tid);
+      __syncthreads();
+      fetch(kt + 2);
+      compute(sA1, sB1);
+      IA::store(sA0, ra, tid);
+      IB::store(sB0, rb, tid);
+      __syncthreads();
     }
-    __syncthreads();
+    // Remaining steps of the chunk (masked loads where needed); stage parity follows kt.
+    for (; kt < kend; ++kt) {
+      typename Tr::T* sa = (kt & 1) ? sA1 : sA0;
+      typename Tr::T* sb = (kt & 1) ? sB1 : sB0;
+      const bool more = kt + 1 < nk;
+      if (more) fetch(kt + 1);
+      compute(sa, sb);
+      if (more) {
+        IA::store((kt & 1) ? sA0 : sA1, ra, tid);
+        IB::store((kt & 1) ? sB0 : sB1, rb, tid);
+      }
+      __syncthreads();
+    }
+    drain();
+    if (kt >= nk) break;
   }
 }
 
@@ -335,6 +392,11 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
   tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   const int m0 = tm * kBM;
   const int n0 = tn * kBN;
+  if (EPI == EPI_PACK) {
+    // every column's b below every row's a: nothing of this tile is kept
+    const int nlast = ((n0 + kBN < g.N) ? n0 + kBN : g.N) - 1;
+    if (nlast / g.v < m0 / g.v) return;
+  }
 
   Acc acc[4][4];
   f64x4 acc64[4][4];
@@ -354,16 +416,10 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
 
   // Epilogue: lane holds column lane%16 of each 16x16 block, rows Tr::row_of(lane, r).
   const int col = lane & 15;
-  const long long v = g.v;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int n = n0 + wn + 16 * j + col;
     if (n >= g.N) continue;
-    long long ncol = n;
-    if (EPI == EPI_PERM) {
-      const int y = n / g.v, d = n - (n / g.v) * g.v;
-      ncol = (long long)y * v * v + d;
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -371,13 +427,7 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
         const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);
         if (m >= g.M) continue;
         const double val = Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]);
-        if (EPI == EPI_ACC) {
-          double* dst = static_cast<double*>(g.C) + (long long)m * g.ldc + n;
-          *dst += val;
-        } else {
-          const int a = m / g.v, x = m - (m / g.v) * g.v;
-          static_cast<T*>(g.C)[(long long)a * v * v * v + ncol + (long long)x * v] = static_cast<T>(val);
-        }
+        epi_store<T, EPI>(g, m, n, val);
       }
     }
   }

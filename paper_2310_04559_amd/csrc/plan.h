@@ -21,6 +21,7 @@ struct Plan {
   int nblocks = 0;      // ceil(v / n_a)
   int slices = 0;       // split-bf16 slice count (0 for the other forms)
   int split_depth = 0;  // split-bf16 anti-diagonals kept beyond the slice triangle (1 or 2)
+  int pairsym = 0;      // forward over packed integral rows a <= b (pair-symmetric amplitudes)
   int k_chunk = 0;      // float32 drain interval along the contracted index
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;
@@ -36,7 +37,11 @@ struct Plan {
 
 // Fills `plan` for a block size of n_a (1 <= n_a <= v).  Returns 0 or CC_LADDER_EINVAL.
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int depth, int k_chunk, Plan* plan);
+                int slices, int depth, int k_chunk, int pairsym, Plan* plan);
+
+// Packed integral rows (a,b), a <= b, ordered by a then b: rows of virtuals
+// [0, a) come first.  pair_prefix(a, v) = sum_{a' < a} (v - a').
+inline long long pair_prefix(long long a, long long v) { return a * v - a * (a - 1) / 2; }
 
 // Picks n_a (honouring opts->a_block when set) so that plan.bytes <= budget
 // (budget 0 = unlimited).  Returns 0, CC_LADDER_EINVAL or CC_LADDER_ENOMEM.

@@ -43,7 +43,12 @@ class CcLadderOpts(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("trace", ctypes.c_void_p),
         ("trace_user", ctypes.c_void_p),
+        ("flags", ctypes.c_uint),
+        ("reserved", ctypes.c_int),
     ]
+
+
+CC_LADDER_PAIR_SYMMETRIC = 1
 
 
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -91,13 +96,15 @@ def strerror(code: int) -> str:
 
 def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
               workspace: Optional[torch.Tensor] = None, trace=None,
-              split_depth: int = 0) -> CcLadderOpts:
+              split_depth: int = 0, pair_symmetric: bool = False) -> CcLadderOpts:
     """``trace`` is a TRACE_FN (keep a reference to it while the options are in use)."""
     o = CcLadderOpts()
     o.a_block = int(a_block)
     o.split_slices = int(split_slices)
     o.k_chunk = int(k_chunk)
     o.split_depth = int(split_depth)
+    o.flags = CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0
+    o.reserved = 0
     o.hbm_budget = int(hbm_budget)
     if workspace is not None:
         o.workspace = workspace.data_ptr()

@@ -34,8 +34,8 @@ def test_exports_every_declared_symbol(native):
 
 def test_opts_struct_layout(native):
     # int a_block, split_slices, k_chunk, split_depth; size_t budget; void* ws; size_t ws_bytes;
-    # trace hook and its user pointer
-    assert ctypes.sizeof(native.CcLadderOpts) == 4 * 4 + 8 * 5
+    # trace hook and its user pointer; unsigned flags, int reserved
+    assert ctypes.sizeof(native.CcLadderOpts) == 4 * 4 + 8 * 5 + 8
 
 
 def test_strerror(native):
@@ -77,6 +77,20 @@ def test_planner_split_footprint(native):
     assert n == v and b4 > b2 >= v ** 4 * 8
     with pytest.raises(native.LadderError) as e:
         native.cc_ladder_workspace_query(o, v, P, "split_bf16", backward=True)
+    assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+
+
+def test_planner_pair_symmetric_footprint(native):
+    # packed rows a <= b: v(v+1)/2 integral rows instead of v^2 for one block
+    o, v, P = 4, 30, 50
+    full, n = native.cc_ladder_workspace_query(o, v, P, "fp64")
+    half, n2 = native.cc_ladder_workspace_query(o, v, P, "fp64", opts=native.make_opts(pair_symmetric=True))
+    assert n == n2 == v
+    rnd = lambda b: (b + 255) // 256 * 256  # buffers are 256-byte aligned
+    assert half == rnd((v * (v + 1) // 2) * v * v * 8)
+    assert full == rnd(v ** 4 * 8)
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(pair_symmetric=True))
     assert e.value.code == native.CC_LADDER_EUNSUPPORTED
 
 

@@ -143,3 +143,42 @@ def test_reduce_matches_oracle(gpu_lib):
         sxy, syy = oracle.reduce_dot(x, y)
         assert abs(out[0] - sxy) <= 1e-13 * np.sum(np.abs(x * y))
         assert abs(out[1] - syy) <= 1e-13 * syy
+
+
+def _pair_symmetric(t):
+    return 0.5 * (t + t.transpose(1, 0, 3, 2))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (4, 44, 131, 13),
+                                           (3, 130, 17, 40), (2, 3, 2, 0), (16, 64, 200, 1)])
+def test_forward_pair_symmetric_path(gpu_lib, o, v, P, a_block, precision):
+    # packed integral rows a <= b and mirrored results; any L, pair-symmetric t
+    announce("forward-pairsym", o, v, P, "a_block", a_block, "precision", precision)
+    L, t, _ = random_general(o, v, P, 700 + o + v)
+    t = _pair_symmetric(t)
+    R0 = np.random.default_rng(8).standard_normal(t.shape)
+    inc = oracle.ladder_forward(L, t)
+    got = run_forward(gpu_lib, L, t, R0, precision, a_block=a_block, pair_symmetric=True)
+    assert rel_fro(got - R0, inc) < TOL[precision]
+
+
+def test_forward_pair_symmetric_full_size(gpu_lib):
+    o, v, P = CONFIGS["c3"]
+    announce("forward-pairsym-full", "c3")
+    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    Ld, td = dev(inp.L_vv), dev(inp.t)
+    pairs = _sampled_pairs(v, 24, 3)
+    ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
+    ia = torch.tensor([a for a, _ in pairs], device="cuda")
+    ib = torch.tensor([b for _, b in pairs], device="cuda")
+    R = torch.zeros_like(td)
+    gpu_lib.cc_ladder_residual(Ld, td, R, 0, opts=gpu_lib.make_opts(pair_symmetric=True))
+    torch.cuda.synchronize()
+    assert rel_fro(host(R[:, :, ia, ib].permute(2, 0, 1)), ref) < TOL[0]
+    # entries with a != b are stored twice from one computed value: exact
+    # mirror; the a == b entries come from rows (i,j) and (j,i) separately
+    off = ~torch.eye(v, dtype=torch.bool, device="cuda")[None, None]
+    Rt = R.permute(1, 0, 3, 2)
+    assert torch.equal(torch.where(off, R, 0.0), torch.where(off, Rt, 0.0))
+    assert float(torch.linalg.vector_norm(R - Rt) / torch.linalg.vector_norm(R)) < 1e-14
