@@ -47,7 +47,8 @@ def mfma_products(form):
     s = FORMS[form][1]
     return s * (s + 1) // 2 if s else 1
 KERNEL_SRC = [os.path.join(ROOT, "paper_2310_04559_amd", "csrc", f)
-              for f in ("gemm.hpp", "ccladder.hip", "split.hip", "split.hpp")]
+              for f in ("gemm.hpp", "gemm_direct.hpp", "ccladder.hip", "split.hip", "split.hpp",
+                        "plan.cpp", "plan.h")]
 
 
 def log(*a):

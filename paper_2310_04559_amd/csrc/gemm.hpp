@@ -118,32 +118,56 @@ __device__ __forceinline__ int pair_row(long long q, int v) {
   return a;
 }
 
+// Column-dependent part of an epilogue address, computed once per column.
+struct EpiCol {
+  long long off;  // PERM: y*v^2 + d; PACK: d; PAIR: a*v + b
+  int x;          // PACK: b - a0; PAIR: a
+  int y;          // PAIR: b
+};
+
+template <class T, int EPI>
+__device__ __forceinline__ EpiCol epi_col(const GemmArgs<T>& g, int n) {
+  EpiCol c{n, 0, 0};
+  const long long v = g.v;
+  if (EPI == EPI_PERM) {
+    const int y = n / g.v, d = n - y * g.v;
+    c.off = (long long)y * v * v + d;
+  } else if (EPI == EPI_PACK) {
+    const int bl = n / g.v;
+    c.x = bl;
+    c.off = n - bl * g.v;
+  } else if (EPI == EPI_PAIR) {
+    const long long q = pair_prefix_d(g.a0, v) + n;
+    const int a = pair_row(q, g.v);
+    const int b = a + static_cast<int>(q - pair_prefix_d(a, v));
+    c.x = a;
+    c.y = b;
+    c.off = (long long)a * v + b;
+  }
+  return c;
+}
+
 // Stores result element (m, n) of a product according to the epilogue mode.
 template <class T, int EPI>
-__device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, double val) {
+__device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, const EpiCol& c,
+                                          double val) {
   const long long v = g.v;
   if (EPI == EPI_ACC) {
     static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
   } else if (EPI == EPI_PERM) {
     const int a = m / g.v, x = m - a * g.v;
-    const int y = n / g.v, d = n - y * g.v;
-    static_cast<T*>(g.C)[(long long)a * v * v * v + (long long)y * v * v + (long long)x * v + d] =
-        static_cast<T>(val);
+    static_cast<T*>(g.C)[(long long)a * v * v * v + c.off + (long long)x * v] = static_cast<T>(val);
   } else if (EPI == EPI_PACK) {
-    const int al = m / g.v, c = m - al * g.v;
-    const int bl = n / g.v, d = n - bl * g.v;
-    if (bl < al) return;
-    const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (bl - al);
-    static_cast<T*>(g.C)[row * v * v + (long long)c * v + d] = static_cast<T>(val);
+    const int al = m / g.v, cc = m - al * g.v;
+    if (c.x < al) return;
+    const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (c.x - al);
+    static_cast<T*>(g.C)[row * v * v + (long long)cc * v + c.off] = static_cast<T>(val);
   } else {  // EPI_PAIR
-    const long long q = pair_prefix_d(g.a0, v) + n;
-    const int a = pair_row(q, g.v);
-    const int b = a + static_cast<int>(q - pair_prefix_d(a, v));
     double* C = static_cast<double*>(g.C);
-    C[(long long)m * g.ldc + (long long)a * v + b] += val;
-    if (a != b) {
+    C[(long long)m * g.ldc + c.off] += val;
+    if (c.x != c.y) {
       const int i = m / g.o, j = m - i * g.o;
-      C[(long long)(j * g.o + i) * g.ldc + (long long)b * v + a] += val;
+      C[(long long)(j * g.o + i) * g.ldc + (long long)c.y * v + c.x] += val;
     }
   }
 }
@@ -420,6 +444,7 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
   for (int j = 0; j < 4; ++j) {
     const int n = n0 + wn + 16 * j + col;
     if (n >= g.N) continue;
+    const EpiCol ec = epi_col<T, EPI>(g, n);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -427,7 +452,7 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
         const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);
         if (m >= g.M) continue;
         const double val = Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]);
-        epi_store<T, EPI>(g, m, n, val);
+        epi_store<T, EPI>(g, m, n, ec, val);
       }
     }
   }

@@ -182,6 +182,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
   for (int j = 0; j < 4; ++j) {
     const int n = n0 + wn + 16 * j + col;
     if (n >= g.N) continue;
+    const EpiCol ec = epi_col<T, EPI>(g, n);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
         const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);
         if (m >= g.M) continue;
         const double val = Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]);
-        epi_store<T, EPI>(g, m, n, val);
+        epi_store<T, EPI>(g, m, n, ec, val);
       }
   }
 }
