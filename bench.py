@@ -32,20 +32,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 at rel err"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_bf16_s2": 2500.0,
-               "split_bf16_s3": 2500.0}  # MI355X dense MFMA
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9, "split_bf16_s2": 8 * 2.0 ** -16,
-       "split_bf16_s3": 8 * 2.0 ** -24}
+               "split_bf16_s3": 2500.0, "fp64_pairsym": 78.6, "fp32_pairsym": 157.3}  # dense MFMA
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9, "split_bf16_s2": 16 * 2.0 ** -16,
+       "split_bf16_s3": 16 * 2.0 ** -24, "fp64_pairsym": 1e-12, "fp32_pairsym": 1e-6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split_bf16_s2": "bf16",
-         "split_bf16_s3": "bf16"}
-# form -> (precision enum name, digit slices); split_bf16 is the 4-slice (10-product) form
-FORMS = {"fp64": ("fp64", 0), "fp32": ("fp32", 0), "split_bf16": ("split_bf16", 4),
-         "split_bf16_s2": ("split_bf16", 2), "split_bf16_s3": ("split_bf16", 3)}
+         "split_bf16_s3": "bf16", "fp64_pairsym": "f64", "fp32_pairsym": "f32"}
+# form -> (precision enum name, digit slices, pair-symmetric amplitudes asserted).
+# split_bf16 is the 4-slice form (13 slice products); the *_pairsym forms use the
+# packed a <= b integral rows, valid because the workload's amplitudes are
+# pair-symmetric (t[i,j,c,d] = t[j,i,d,c]).
+FORMS = {"fp64": ("fp64", 0, False), "fp32": ("fp32", 0, False),
+         "split_bf16": ("split_bf16", 4, False), "split_bf16_s2": ("split_bf16", 2, False),
+         "split_bf16_s3": ("split_bf16", 3, False),
+         "fp64_pairsym": ("fp64", 0, True), "fp32_pairsym": ("fp32", 0, True)}
 
 
 def mfma_products(form):
-    """Slice products per nominal product (executed MFMA work multiplier)."""
+    """Slice products per nominal product (executed MFMA work multiplier): the
+    S(S+1)/2 triangle, plus S-1 for the 4-slice form's extra anti-diagonal."""
     s = FORMS[form][1]
-    return s * (s + 1) // 2 if s else 1
+    if not s:
+        return 1
+    return s * (s + 1) // 2 + (s - 1 if s == 4 else 0)
+
+
+def executed_fraction(form, v):
+    """Share of the nominal flops a form executes: (v+1)/(2v) with packed rows."""
+    return (v + 1) / (2.0 * v) if FORMS[form][2] else 1.0
 KERNEL_SRC = [os.path.join(ROOT, "paper_2310_04559_amd", "csrc", f)
               for f in ("gemm.hpp", "gemm_direct.hpp", "ccladder.hip", "split.hip", "split.hpp",
                         "plan.cpp", "plan.h")]
@@ -129,13 +142,15 @@ def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
     import torch
 
     prec = native.PRECISIONS[FORMS[form][0]]
-    slices = FORMS[form][1]
+    slices, pairsym = FORMS[form][1], FORMS[form][2]
     stream = torch.cuda.current_stream()
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, prec, hbm_budget=ws_bytes,
-                                                   opts=native.make_opts(split_slices=slices))
+    nbytes, n_a = native.cc_ladder_workspace_query(
+        o, v, P, prec, hbm_budget=ws_bytes,
+        opts=native.make_opts(split_slices=slices, pair_symmetric=pairsym))
     timer = PhaseTimer(native, stream)
-    opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices)
+    opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices,
+                            pair_symmetric=pairsym)
 
     def step():
         native.cc_ladder_residual(L, t, R, prec, opts=opts)
@@ -167,7 +182,8 @@ def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
     R = torch.zeros_like(t)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     native.cc_ladder_residual(L, t, R, native.PRECISIONS[FORMS[form][0]],
-                              opts=native.make_opts(workspace=ws, split_slices=FORMS[form][1]))
+                              opts=native.make_opts(workspace=ws, split_slices=FORMS[form][1],
+                                                    pair_symmetric=FORMS[form][2]))
     torch.cuda.synchronize()
     got = R[:, :, idx_a, idx_b].permute(2, 0, 1).cpu().numpy()
     del R, ws
@@ -298,7 +314,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
-    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2")
+    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2,fp64_pairsym")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--large", action="store_true",
@@ -363,6 +379,7 @@ def main():
             continue
         r = bench_form(native, form, L, t, R, out, ws_bytes, args.steps, args.warmup, o, v, P)
         r["tflops"] = flops / (r["ms_per_step"] * 1e-3) / 1e12
+        r["executed_tflops"] = r["tflops"] * executed_fraction(form, v)
         r["rel_err_vs_oracle"] = err
         r["tolerance"] = TOL[form]
         r["within_tolerance"] = err < TOL[form]
@@ -371,7 +388,7 @@ def main():
         c = r["phases"].get("contract")
         if c:
             per_step = c["launches"] / args.steps  # launches of the kernel in one step
-            launch_flops = 2.0 * o * o * float(v) ** 4 / per_step
+            launch_flops = 2.0 * o * o * float(v) ** 4 * executed_fraction(form, v) / per_step
             # executed MFMA flops: the split forms run S(S+1)/2 slice products per product
             achieved = mfma_products(form) * launch_flops / (c["ms_avg"] * 1e-3) / 1e12
             r["roofline"] = {"kernel": "contract", "bound": "mfma", "achieved": achieved,
@@ -382,7 +399,7 @@ def main():
                              "nominal_tflops": launch_flops / (c["ms_avg"] * 1e-3) / 1e12}
         b = r["phases"].get("build")
         if b:
-            bflops = 2.0 * P * float(v) ** 4 / (b["launches"] / args.steps)
+            bflops = 2.0 * P * float(v) ** 4 * executed_fraction(form, v) / (b["launches"] / args.steps)
             r["build_tflops"] = bflops / (b["ms_avg"] * 1e-3) / 1e12
         forms[form] = r
         log(f"{form}: {r['ms_per_step']:.1f} ms/step {r['tflops']:.2f} TFLOP/s err {err:.2e} "

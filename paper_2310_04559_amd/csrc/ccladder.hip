@@ -87,10 +87,23 @@ bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   return true;
 }
 
+// Offsets of the packed build's compact grid: row_tiles[tm] = number of needed
+// tiles in tile rows before tm (one thread; a few thousand rows at most).
+__global__ void pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int acc = 0;
+  for (int tm = 0; tm < tiles_m; ++tm) {
+    row_tiles[tm] = acc;
+    const int first = pack_first_tile(tm, kBM, kBN, v);
+    acc += first < tiles_n ? tiles_n - first : 0;
+  }
+  row_tiles[tiles_m] = acc;
+}
+
 template <class Tr, int LA, int LB, int EPI>
 int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
                 void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
-                hipStream_t stream, int o = 0, int a0 = 0) {
+                hipStream_t stream, int o = 0, int a0 = 0, int* row_tiles = nullptr) {
   if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
   GemmArgs<typename Tr::T> g;
   g.A = A; g.lda = lda;
@@ -100,6 +113,7 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   g.v = v;
   g.o = o;
   g.a0 = a0;
+  g.row_tiles = row_tiles;
   g.tiles_m = (M + kBM - 1) / kBM;
   g.tiles_n = (N + kBN - 1) / kBN;
   const long long tiles = (long long)g.tiles_m * g.tiles_n;
@@ -108,11 +122,25 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   // both their row panels and a few column panels.
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
   g.drain_steps = drain_steps > 0 ? drain_steps : 1;
+  dim3 grid(static_cast<unsigned>(tiles));
+  if (EPI == EPI_PACK) {
+    if (!row_tiles) return CC_LADDER_EINVAL;
+    // the compact grid's size is the sum over tile rows of the needed columns
+    long long needed = 0;
+    for (int tm = 0; tm < g.tiles_m; ++tm) {
+      const int first = pack_first_tile(tm, kBM, kBN, v);
+      needed += first < g.tiles_n ? g.tiles_n - first : 0;
+    }
+    if (needed <= 0) return CC_LADDER_OK;
+    hipLaunchKernelGGL(pack_rows_kernel, dim3(1), dim3(1), 0, stream, row_tiles, g.tiles_m,
+                       g.tiles_n, v);
+    grid = dim3(static_cast<unsigned>(needed));
+  }
   if (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
     int rc = CC_LADDER_OK;
     if (launch_kc_direct<Tr, EPI>(g, stream, &rc)) return rc;
   }
-  const dim3 grid(static_cast<unsigned>(tiles)), block(kThreads);
+  const dim3 block(kThreads);
   if (vec_ok(A, lda) && vec_ok(B, ldb))
     hipLaunchKernelGGL((gemm_kernel<Tr, LA, LB, EPI, true>), grid, block, 0, stream, g);
   else
@@ -248,7 +276,7 @@ int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream
 
 template <class Tr>
 int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t, double* R,
-                   typename Tr::T* V, const Tracer& tr, hipStream_t s) {
+                   typename Tr::T* V, int* row_tiles, const Tracer& tr, hipStream_t s) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
@@ -261,7 +289,7 @@ int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T
       tr(CC_LADDER_PHASE_BUILD, blk, 0);
       int rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
                                                  static_cast<int>((long long)(v - a0) * v), P, v,
-                                                 drain, s, o, a0);
+                                                 drain, s, o, a0, row_tiles);
       tr(CC_LADDER_PHASE_BUILD, blk, 1);
       if (rc) return rc;
       // R[(ij)][(ab)] and R[(ji)][(ba)] += t[(ij)][(cd)] . V_A[pair(a,b)][(cd)]
@@ -355,8 +383,8 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
   const Tracer tr(opts, stream);
   switch (precision) {
     case CC_LADDER_FP64:
-      return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V), tr,
-                                   stream);
+      return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V),
+                                   reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
     case CC_LADDER_FP32: {
       float* L32 = reinterpret_cast<float*>(base + pl.off_L);
       float* t32 = reinterpret_cast<float*>(base + pl.off_t);
@@ -365,8 +393,8 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
       if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
       tr(CC_LADDER_PHASE_PREP, 0, 1);
       if (rc) return rc;
-      return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V), tr,
-                                   stream);
+      return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V),
+                                   reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
     }
     case CC_LADDER_SPLIT_BF16:
       return split_forward(pl, L, t, R, base, tr, stream);

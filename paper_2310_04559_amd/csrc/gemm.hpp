@@ -99,7 +99,15 @@ struct GemmArgs {
   int tiles_m, tiles_n;
   int group_m;       // tile-order swizzle: rows of tiles walked together
   int drain_steps;   // K-steps between float32 -> float64 drains (TrF32)
+  const int* row_tiles;  // EPI_PACK compact grid: first linear tile of each tile row
 };
+
+// First needed tile column of tile row tm in the packed build: columns whose
+// largest b is at least the row's smallest a.
+__host__ __device__ inline int pack_first_tile(int tm, int bm, int bn, int v) {
+  const long long amin = (long long)tm * bm / v;  // smallest (a - a0) of the tile row
+  return static_cast<int>(amin * v / bn);
+}
 
 constexpr int kBM = 128, kBN = 128;
 
@@ -413,7 +421,20 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
   const int wn = (wave & 1) * 64;
 
   int tm, tn;
-  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  if (EPI == EPI_PACK) {
+    // compact grid over the tiles on or above the a = b diagonal: tile row by
+    // binary search over the row offsets, then columns from the row's first
+    const int id = blockIdx.x;
+    int lo = 0, hi = g.tiles_m - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (g.row_tiles[mid] <= id) lo = mid; else hi = mid - 1;
+    }
+    tm = lo;
+    tn = pack_first_tile(tm, kBM, kBN, g.v) + (id - g.row_tiles[tm]);
+  } else {
+    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  }
   const int m0 = tm * kBM;
   const int n0 = tn * kBN;
   if (EPI == EPI_PACK) {

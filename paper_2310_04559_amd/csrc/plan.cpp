@@ -96,6 +96,11 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
     default:
       return CC_LADDER_EINVAL;
   }
+  if (p.pairsym) {
+    // tile-row offsets of the packed build's compact grid (128-row tiles)
+    const size_t tiles_m = (static_cast<size_t>(n_a) * v + 127) / 128;
+    p.off_tiles = take(&cur, (tiles_m + 1) * sizeof(int));
+  }
   p.bytes = cur;
   *plan = p;
   return CC_LADDER_OK;

@@ -32,6 +32,7 @@ struct Plan {
   size_t off_Vs = 0;    // bf16 slices of the integral block
   size_t off_Vexp = 0;  // per-row exponents of the integral block
   size_t off_Ws = 0, off_Wexp = 0;
+  size_t off_tiles = 0; // packed build: first tile of every tile row (int32, tiles_m + 1)
   size_t bytes = 0;     // total scratch
 };
 

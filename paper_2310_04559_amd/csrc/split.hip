@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "gemm.hpp"
 
@@ -321,6 +322,198 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs g) {
   }
 }
 
+// Same product with 8 waves: waves w and w+4 own the same 32 x 64 sub-tile; wave
+// w accumulates the anti-diagonals [0, G0) (slices below G0 only), wave w+4 the
+// anti-diagonals [G0, NG).  Each half fits 256 registers, so two waves share a
+// SIMD and hide each other's LDS and memory latency; their float64 partial sums
+// are added through LDS before the epilogue.
+template <int S, int D>
+struct GroupSplit {
+  static constexpr int NG = S + D - 1;
+  static constexpr int pairs(int q) { return (q < S ? q + 1 : 2 * S - 1 - q); }
+  static constexpr int count(int lo, int hi) { return lo >= hi ? 0 : pairs(lo) + count(lo + 1, hi); }
+  static constexpr int larger(int g) { return count(0, g) > count(g, NG) ? count(0, g) : count(g, NG); }
+  // split point in [1, NG) that minimises the larger half's products
+  static constexpr int pick(int g, int best) {
+    return g >= NG ? best : pick(g + 1, larger(g) < larger(best) ? g : best);
+  }
+  static constexpr int G0 = pick(1, 1);
+  static_assert(G0 >= 1 && G0 < NG, "both halves hold products");
+};
+
+template <int S, int D, int EPI>
+__global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
+  constexpr int NG = S + D - 1;
+  constexpr int G0 = GroupSplit<S, D>::G0;
+  constexpr int A_BYTES = S * kSBM * kRowBytes;
+  constexpr int B_BYTES = S * kSBN * kRowBytes;
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int ASLABS = S * kSBM / 16, BSLABS = S * kSBN / 16;  // 16-row slabs per stage
+  constexpr int LOADS = (ASLABS + BSLABS) / 8;                    // per wave
+  static_assert((ASLABS % 8) == 0 && (BSLABS % 8) == 0, "slab split");
+  static_assert(kStages * STAGE <= 160 * 1024, "LDS");
+  static_assert(4 * 64 * 32 * 8 <= kStages * STAGE, "reduction buffer");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[kStages * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int sub = wave & 3, half = wave >> 2;
+  const int wm = (sub >> 1) * 32;
+  const int wn = (sub & 1) * 64;
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  const int m0 = tm * kSBM, n0 = tn * kSBN;
+
+  const int lrow = lane >> 2;
+  const int lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+  const long long loff = (long long)lrow * g.Kp + lchunk * 8;
+  auto issue = [&](int kt) {
+    unsigned char* st = lds + (kt % kStages) * STAGE;
+    const int ko = kt * kSBK;
+#pragma unroll
+    for (int j = 0; j < ASLABS / 8; ++j) {
+      const int ai = wave + 8 * j, s = ai / (kSBM / 16), r = ai % (kSBM / 16);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(g.A + s * g.sa + (long long)(m0 + 16 * r) * g.Kp + loff + ko),
+          (lds_void_t*)(st + (s * kSBM + 16 * r) * kRowBytes), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < BSLABS / 8; ++j) {
+      const int bi = wave + 8 * j, s = bi / (kSBN / 16), r = bi % (kSBN / 16);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(g.B + s * g.sb + (long long)(n0 + 16 * r) * g.Kp + loff + ko),
+          (lds_void_t*)(st + A_BYTES + (s * kSBN + 16 * r) * kRowBytes), 16, 0, 0);
+    }
+  };
+
+  f64x4 acc64[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
+
+  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 2) & 3)) * 16);
+  const int nk = g.Kp / kSBK;
+
+  // One exact chunk of this wave's anti-diagonals [LO, HI) (slices < SL needed).
+  auto run_chunk = [&](int k0, auto lo_c, auto hi_c) {
+    constexpr int LO = decltype(lo_c)::value, HI = decltype(hi_c)::value;
+    constexpr int SL = (HI - 1) < S ? HI : S;  // slices with index < SL can appear
+    f32x4 acc[HI - LO][2][4];
+#pragma unroll
+    for (int q = 0; q < HI - LO; ++q)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[q][i][j] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < kChunkSteps; ++u) {
+      const int kt = k0 + u;
+      if (kt < nk) {
+        wait_vm(kt + 1 < nk ? LOADS : 0);
+        __builtin_amdgcn_s_barrier();
+        if (kt + 2 < nk) issue(kt + 2);
+        const unsigned char* st = lds + (kt % kStages) * STAGE;
+        bf16x8 fa[SL][2], fb[SL][4];
+#pragma unroll
+        for (int sl = 0; sl < SL; ++sl) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            fa[sl][i] = *reinterpret_cast<const bf16x8*>(
+                st + (sl * kSBM + wm + 16 * i) * kRowBytes + frag_off);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            fb[sl][j] = *reinterpret_cast<const bf16x8*>(
+                st + A_BYTES + (sl * kSBN + wn + 16 * j) * kRowBytes + frag_off);
+        }
+#pragma unroll
+        for (int p = 0; p < SL; ++p)
+#pragma unroll
+          for (int q = 0; q < SL; ++q) {
+            if (p + q < LO || p + q >= HI) continue;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[p + q - LO][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    fa[p][i], fb[q][j], acc[p + q - LO][i][j], 0, 0, 0);
+          }
+      }
+    }
+    double scale = 1.0 / 65536.0;
+#pragma unroll
+    for (int q = 0; q < LO; ++q) scale *= 1.0 / 256.0;
+#pragma unroll
+    for (int q = 0; q < HI - LO; ++q) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc64[i][j][r] = fma(static_cast<double>(acc[q][i][j][r]), scale, acc64[i][j][r]);
+      scale *= 1.0 / 256.0;
+    }
+  };
+
+  issue(0);
+  if (nk > 1) issue(1);
+  for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
+    if (half == 0)
+      run_chunk(k0, std::integral_constant<int, 0>{}, std::integral_constant<int, G0>{});
+    else
+      run_chunk(k0, std::integral_constant<int, G0>{}, std::integral_constant<int, NG>{});
+  }
+
+  // add the upper anti-diagonals' sums (waves 4..7) into waves 0..3
+  __builtin_amdgcn_s_barrier();  // every wave is done reading the operand stages
+  double* red = reinterpret_cast<double*>(lds) + (sub * 64 + lane) * 32;
+  if (half == 1) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(i * 4 + j) * 4 + r] = acc64[i][j][r];
+  }
+  __syncthreads();
+  if (half == 1) return;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[i][j][r] += red[(i * 4 + j) * 4 + r];
+
+  const long long v = g.v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn + 16 * j + (lane & 15);
+    if (n >= g.N) continue;
+    const int en = g.eb[n];
+    long long ncol = n;
+    if (EPI == EPI_PERM) {
+      const int y = n / g.v, d = n - y * g.v;
+      ncol = (long long)y * v * v + d;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (m >= g.M) continue;
+        const double val = ldexp(acc64[i][j][r], g.ea[m] + en);
+        if (EPI == EPI_ACC) {
+          static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
+        } else {
+          const int a = m / g.v, x = m - a * g.v;
+          static_cast<double*>(g.C)[(long long)a * v * v * v + ncol + (long long)x * v] = val;
+        }
+      }
+  }
+}
+
 template <int S, int D, int EPI>
 int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
   SplitArgs a = a0;
@@ -330,8 +523,12 @@ int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
   const long long tiles = (long long)a.tiles_m * a.tiles_n;
   if (tiles > 0x7fffffffLL) return CC_LADDER_EINVAL;
   a.group_m = a.tiles_m < 16 ? a.tiles_m : 16;
-  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI>), dim3(static_cast<unsigned>(tiles)), dim3(256),
-                     0, s, a);
+  if constexpr (S == 4)  // enough products for both halves of the 8-wave kernel
+    hipLaunchKernelGGL((split_gemm2_kernel<S, D, EPI>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(256), 0, s, a);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
