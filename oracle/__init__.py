@@ -15,6 +15,8 @@ What it computes (arXiv 2310.04559):
   with ``W[a,b,c,d] = sum_{i,j} lam[i,j,a,b] t[i,j,c,d]``,
   ``dL[x,p,q] = sum_{b,d} W[p,b,q,d] L[x,b,d] + sum_{a,c} W[a,p,c,q] L[x,a,c]``
   (entrywise gradient: each array entry of L is an independent variable).
+* eq. (vfunction2): the exchange partner ``R[i,j,a,b] += sum_{c,d} (ad|bc) t[i,j,c,d]``
+  and its adjoint.
 
 Algorithm: the paper's loop over one virtual index (Sec. "Pythonic
 implementations of the CC vector function", the tensordot variant that keeps
@@ -30,6 +32,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_loss",
+           "exchange_forward", "exchange_backward",
            "reduce_dot", "eri_slice", "nominal_flops_forward", "nominal_flops_backward"]
 
 
@@ -71,6 +74,51 @@ def ladder_forward(L, t, R=None, a_begin: int = 0, a_end=None) -> np.ndarray:
         # R[(i,j), a, b] += sum_{(c,d)} T[(i,j),(c,d)] * Va[b,(c,d)]
         R[:, :, a, :] += (T @ Va.reshape(v, v * v).T).reshape(o, o, v)
     return R
+
+
+def exchange_forward(L, t, R=None) -> np.ndarray:
+    """Exchange partner of the ladder (eq. vfunction2):
+    ``R[i,j,a,b] += sum_{c,d} (ad|bc) t[i,j,c,d]`` with
+    ``(ad|bc) = sum_x L[x,a,d] L[x,b,c]``; same loop over ``a``."""
+    L, t = _check(L, t)
+    P, v, _ = L.shape
+    o = t.shape[0]
+    if R is None:
+        R = np.zeros((o, o, v, v))
+    T = t.reshape(o * o, v * v)                       # [(i,j)][(c,d)]
+    Lf = L.reshape(P, v * v)
+    for a in range(v):
+        # X[d][(b,c)] = sum_x L[x,a,d] L[x,b,c]
+        X = (L[:, a, :].T @ Lf).reshape(v, v, v)      # [d][b][c]
+        Xa = X.transpose(1, 2, 0).reshape(v, v * v)   # [b][(c,d)]
+        R[:, :, a, :] += (T @ Xa.T).reshape(o, o, v)
+    return R
+
+
+def exchange_backward(L, t, lam):
+    """Entrywise ``(dL, dt)`` of ``sum lam * R`` with R the exchange term, from
+    the definitions: with ``Y[a,b,c,d] = sum_{i,j} lam[i,j,a,b] t[i,j,c,d]``,
+    ``dt[i,j,c,d] = sum_{a,b} lam[i,j,a,b] (ad|bc)``,
+    ``dL[x,p,q] = sum_{b,c} Y[p,b,c,q] L[x,b,c] + sum_{a,d} Y[a,p,q,d] L[x,a,d]``."""
+    L, t = _check(L, t)
+    lam = np.asarray(lam, dtype=np.float64)
+    P, v, _ = L.shape
+    o = t.shape[0]
+    T = t.reshape(o * o, v * v)
+    Lf = L.reshape(P, v * v)
+    dt = np.zeros((o * o, v * v))
+    dL = np.zeros((P, v, v))
+    for a in range(v):
+        X = (L[:, a, :].T @ Lf).reshape(v, v, v)      # [d][b][c] = (ad|bc)
+        lam_a = lam[:, :, a, :].reshape(o * o, v)     # [(i,j)][b]
+        # dt[(i,j),(c,d)] += sum_b lam[i,j,a,b] (ad|bc)
+        dt += lam_a @ X.transpose(1, 2, 0).reshape(v, v * v)
+        Ya = (lam_a.T @ T).reshape(v, v, v)          # [b][c][d] = Y[a,b,c,d]
+        # dL[x,a,d] += sum_{b,c} L[x,b,c] Y[a,b,c,d]
+        dL[:, a, :] += Lf @ Ya.reshape(v * v, v)
+        # dL[x,b,c] += sum_d L[x,a,d] Y[a,b,c,d]
+        dL += np.einsum("xd,bcd->xbc", L[:, a, :], Ya)
+    return dL, dt.reshape(o, o, v, v)
 
 
 def ladder_backward(L, t, lam):

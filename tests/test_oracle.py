@@ -326,3 +326,64 @@ def test_reduce_and_flops():
     assert oracle.reduce_dot(x, y) == (90.0, 40.0)
     assert oracle.nominal_flops_forward(40, 360, 1200) == pytest.approx(94.06e12, rel=1e-3)
 
+
+
+# ---------------------------------------------------------------------------
+# exchange partner (eq. vfunction2)
+# ---------------------------------------------------------------------------
+
+def _int_exchange(L, t):
+    P, v = len(L), len(L[0])
+    o = len(t)
+    R = [[[[0] * v for _ in range(v)] for _ in range(o)] for _ in range(o)]
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        s = 0
+        for c, d in itertools.product(range(v), range(v)):
+            X = sum(L[x][a][d] * L[x][b][c] for x in range(P))
+            s += X * t[i][j][c][d]
+        R[i][j][a][b] = s
+    return R
+
+
+@pytest.mark.parametrize("o,v,P,seed", [(2, 3, 2, 81), (3, 4, 3, 82)])
+def test_exchange_equals_integer_bruteforce(o, v, P, seed):
+    L, t = integer_inputs(o, v, P, seed)
+    exact = np.array(_int_exchange(_to_int(L), _to_int(t)), dtype=np.float64)
+    assert np.array_equal(oracle.exchange_forward(L, t), exact)
+
+
+def test_exchange_is_ladder_of_swapped_amplitudes():
+    # (ad|bc) t[i,j,c,d] summed over c,d equals (ac|bd) t[i,j,d,c]
+    L, t, _ = random_general(3, 9, 7, 83)
+    ref = oracle.ladder_forward(L, t.transpose(0, 1, 3, 2).copy())
+    assert rel_fro(oracle.exchange_forward(L, t), ref) < 1e-14
+
+
+def test_exchange_backward_exact_differences_and_euler():
+    o, v, P = 2, 3, 2
+    L, t = integer_inputs(o, v, P, 84)
+    lam = np.random.default_rng(85).integers(-2, 3, size=(o, o, v, v)).astype(np.float64)
+    Li, ti, lami = _to_int(L), _to_int(t), _to_int(lam)
+
+    def loss(Lx, tx):
+        R = _int_exchange(Lx, tx)
+        return sum(lami[i][j][a][b] * R[i][j][a][b]
+                   for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)))
+
+    dL, dt = oracle.exchange_backward(L, t, lam)
+    for x, p, q in itertools.product(range(P), range(v), range(v)):
+        Lp = [[row[:] for row in m] for m in Li]
+        Lm = [[row[:] for row in m] for m in Li]
+        Lp[x][p][q] += 1
+        Lm[x][p][q] -= 1
+        assert dL[x, p, q] == (loss(Lp, ti) - loss(Lm, ti)) / 2
+    base = loss(Li, ti)
+    for i, j, c, d in itertools.product(range(o), range(o), range(v), range(v)):
+        tp = [[[row[:] for row in m] for m in blk] for blk in ti]
+        tp[i][j][c][d] += 1
+        assert dt[i, j, c, d] == loss(Li, tp) - base
+    L2, t2, lam2 = random_general(3, 7, 5, 86)
+    dL2, dt2 = oracle.exchange_backward(L2, t2, lam2)
+    lo = oracle.ladder_loss(lam2, oracle.exchange_forward(L2, t2))
+    assert abs(np.sum(dt2 * t2) - lo) <= 1e-13 * abs(lo)
+    assert abs(np.sum(dL2 * L2) - 2 * lo) <= 1e-13 * abs(lo)
