@@ -31,20 +31,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 at rel err"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_bf16_s2": 2500.0,
-               "split_bf16_s3": 2500.0, "fp64_pairsym": 78.6, "fp32_pairsym": 157.3}  # dense MFMA
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9, "split_bf16_s2": 16 * 2.0 ** -16,
-       "split_bf16_s3": 16 * 2.0 ** -24, "fp64_pairsym": 1e-12, "fp32_pairsym": 1e-6}
-DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split_bf16_s2": "bf16",
-         "split_bf16_s3": "bf16", "fp64_pairsym": "f64", "fp32_pairsym": "f32"}
-# form -> (precision enum name, digit slices, pair-symmetric amplitudes asserted).
-# split_bf16 is the 4-slice form (13 slice products); the *_pairsym forms use the
-# packed a <= b integral rows, valid because the workload's amplitudes are
-# pair-symmetric (t[i,j,c,d] = t[j,i,d,c]).
-FORMS = {"fp64": ("fp64", 0, False), "fp32": ("fp32", 0, False),
-         "split_bf16": ("split_bf16", 4, False), "split_bf16_s2": ("split_bf16", 2, False),
-         "split_bf16_s3": ("split_bf16", 3, False),
-         "fp64_pairsym": ("fp64", 0, True), "fp32_pairsym": ("fp32", 0, True)}
+# form -> (precision enum name, digit slices, pair-symmetric amplitudes asserted,
+# exchange partner).  split_bf16 is the 4-slice form (13 slice products); the
+# *_pairsym forms use the packed a <= b integral rows, valid because the
+# workload's amplitudes are pair-symmetric (t[i,j,c,d] = t[j,i,d,c]); the
+# *_exchange forms evaluate the exchange partner sum_cd (ad|bc) t[i,j,c,d]
+# (eq. vfunction2) with the same nominal flops.
+FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
+         "split_bf16": ("split_bf16", 4, False, False),
+         "split_bf16_s2": ("split_bf16", 2, False, False),
+         "split_bf16_s3": ("split_bf16", 3, False, False),
+         "fp64_pairsym": ("fp64", 0, True, False), "fp32_pairsym": ("fp32", 0, True, False),
+         "fp64_exchange": ("fp64", 0, False, True), "fp32_exchange": ("fp32", 0, False, True),
+         "split_bf16_exchange": ("split_bf16", 4, False, True)}
+_PEAK = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}  # dense MFMA, TFLOP/s
+_DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16"}
+_SPLIT_TOL = {2: 16 * 2.0 ** -16, 3: 16 * 2.0 ** -24, 4: 1e-9}
+PEAK_TFLOPS = {f: _PEAK[p[0]] for f, p in FORMS.items()}
+DTYPE = {f: _DTYPE[p[0]] for f, p in FORMS.items()}
+TOL = {f: (_SPLIT_TOL[p[1]] if p[1] else {"fp64": 1e-12, "fp32": 1e-6}[p[0]])
+       for f, p in FORMS.items()}
 
 
 def mfma_products(form):
@@ -142,15 +148,15 @@ def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
     import torch
 
     prec = native.PRECISIONS[FORMS[form][0]]
-    slices, pairsym = FORMS[form][1], FORMS[form][2]
+    slices, pairsym, exchange = FORMS[form][1:]
     stream = torch.cuda.current_stream()
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     nbytes, n_a = native.cc_ladder_workspace_query(
         o, v, P, prec, hbm_budget=ws_bytes,
-        opts=native.make_opts(split_slices=slices, pair_symmetric=pairsym))
+        opts=native.make_opts(split_slices=slices, pair_symmetric=pairsym, exchange=exchange))
     timer = PhaseTimer(native, stream)
     opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices,
-                            pair_symmetric=pairsym)
+                            pair_symmetric=pairsym, exchange=exchange)
 
     def step():
         native.cc_ladder_residual(L, t, R, prec, opts=opts)
@@ -183,7 +189,8 @@ def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     native.cc_ladder_residual(L, t, R, native.PRECISIONS[FORMS[form][0]],
                               opts=native.make_opts(workspace=ws, split_slices=FORMS[form][1],
-                                                    pair_symmetric=FORMS[form][2]))
+                                                    pair_symmetric=FORMS[form][2],
+                                                    exchange=FORMS[form][3]))
     torch.cuda.synchronize()
     got = R[:, :, idx_a, idx_b].permute(2, 0, 1).cpu().numpy()
     del R, ws
@@ -314,7 +321,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
-    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2,fp64_pairsym")
+    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2,fp64_pairsym,"
+                                       "fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--large", action="store_true",
@@ -366,13 +374,16 @@ def main():
 
     pairs = sampled_pairs(v, 24, 3)
     ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
+    # exchange partner: the ladder of the amplitudes with c and d swapped
+    ref_x = oracle.ladder_pairs(inp.L_vv, np.ascontiguousarray(inp.t.transpose(0, 1, 3, 2)), pairs)
     idx_a = torch.tensor([a for a, _ in pairs], device="cuda")
     idx_b = torch.tensor([b for _, b in pairs], device="cuda")
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
         try:
-            err = rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes)
+            err = rel_err_form(native, form, L, t, ref_x if FORMS[form][3] else ref, idx_a, idx_b,
+                               ws_bytes)
         except native.LadderError as e:
             forms[form] = {"status": "unsupported", "detail": str(e)}
             log(f"{form}: {e}")

@@ -64,9 +64,19 @@ typedef enum {
                                         build and half the contraction.  FP64 and FP32 forward only;
                                         ignored by the adjoint; EUNSUPPORTED with SPLIT_BF16. */
 
+#define CC_LADDER_EXCHANGE 2u        /* evaluate the exchange partner instead (eq. vfunction2):
+                                        R[i][j][a][b] += sum_{c,d} (ad|bc) t[i][j][c][d], i.e. the
+                                        ladder of t with its last two indices swapped.  The swapped
+                                        copy lives in scratch (o^2 v^2 float64; the FP32 form swaps
+                                        into its float32 copy instead), and the adjoint accumulates
+                                        dt in swapped order in another o^2 v^2 float64 buffer before
+                                        swapping it back; the adjoint returns the exchange term's
+                                        gradients.  Combines with PAIR_SYMMETRIC and every form. */
+
 /* Kernel phases reported to an optional trace hook. */
 typedef enum {
-  CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam */
+  CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam; the exchange swaps
+                                    (block 1: the adjoint's final swap of dt) */
   CC_LADDER_PHASE_BUILD = 1,     /* integral block V_A (eq. cholesky) */
   CC_LADDER_PHASE_CONTRACT = 2,  /* R += t . V_A (eq. vfunction) */
   CC_LADDER_PHASE_DT = 3,        /* adjoint: dt += lam . V_A */
@@ -94,7 +104,7 @@ typedef struct {
   size_t workspace_bytes;  /* its size; the plan must fit in it */
   cc_ladder_trace_fn trace;  /* optional per-phase hook, NULL = none */
   void*  trace_user;       /* passed back to `trace` */
-  unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC or 0 */
+  unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE, or 0 */
   int    reserved;         /* must be 0 */
 } cc_ladder_opts;
 

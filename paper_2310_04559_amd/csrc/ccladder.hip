@@ -9,6 +9,9 @@
 //   W'_A[a][c][b][d] = sum_(ij) lam[(ij)][(ab)] t[(ij)][(cd)]
 //   dL[x][(a c)]  += sum_(bd) L[x][(bd)] W'_A[(ac)][(bd)]          (a in A)
 //   dL[x][(b d)]  += sum_(a in A, c) L[x][(ac)] W'_A[(ac)][(bd)]
+// Exchange partner (eq. vfunction2): the same schedule on t with c and d swapped,
+// since sum_(cd) (ad|bc) t[i][j][c][d] = sum_(cd) (ac|bd) t[i][j][d][c]; the
+// adjoint's dt comes back with the swap undone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -164,6 +167,52 @@ int to_f32(const double* x, float* y, size_t n, hipStream_t s) {
   const long long blocks = std::min<long long>((n + 255) / 256, 8192);
   hipLaunchKernelGGL(to_f32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x, y,
                      static_cast<long long>(n));
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+// y[m][d][c] = x[m][c][d] for o^2 matrices m of v x v, through a 32 x 32 LDS
+// tile so that both the read and the write of a tile row are coalesced.  One
+// workgroup per (matrix, tile) pair, grid-stride.  Out is double or float
+// (the float32 form swaps while converting, round to nearest even).
+constexpr int kSwapTile = 32;
+
+template <typename Out>
+__global__ __launch_bounds__(256) void swap_cd_kernel(const double* __restrict__ x,
+                                                      Out* __restrict__ y, int v, long long nmat,
+                                                      int tiles) {
+  __shared__ double tile[kSwapTile][kSwapTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of 32 lanes
+  const long long per_mat = (long long)tiles * tiles;
+  const long long v2 = (long long)v * v;
+  for (long long w = blockIdx.x; w < nmat * per_mat; w += gridDim.x) {
+    const long long m = w / per_mat;
+    const int r = static_cast<int>(w - m * per_mat);
+    const int c0 = (r / tiles) * kSwapTile, d0 = (r % tiles) * kSwapTile;
+    const double* xm = x + m * v2;
+    Out* ym = y + m * v2;
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      const int c = c0 + k, d = d0 + tx;
+      if (c < v && d < v) tile[k][tx] = xm[(long long)c * v + d];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      const int d = d0 + k, c = c0 + tx;
+      if (c < v && d < v) ym[(long long)d * v + c] = static_cast<Out>(tile[tx][k]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename Out>
+int swap_cd(const double* x, Out* y, int o, int v, hipStream_t s) {
+  const long long nmat = (long long)o * o;
+  const int tiles = (v + kSwapTile - 1) / kSwapTile;
+  const long long work = nmat * tiles * tiles;
+  const long long blocks = std::min<long long>(work, 16384);
+  hipLaunchKernelGGL(swap_cd_kernel<Out>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x,
+                     y, v, nmat, tiles);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -381,6 +430,15 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
   if (rc) return rc;
   char* base = ws.base;
   const Tracer tr(opts, stream);
+  if (pl.exchange && precision != CC_LADDER_FP32) {
+    // the exchange partner is the ladder of the swapped amplitudes
+    double* tx = reinterpret_cast<double*>(base + pl.off_tx);
+    tr(CC_LADDER_PHASE_PREP, 0, 0);
+    rc = swap_cd(t, tx, o, v, stream);
+    tr(CC_LADDER_PHASE_PREP, 0, 1);
+    if (rc) return rc;
+    t = tx;
+  }
   switch (precision) {
     case CC_LADDER_FP64:
       return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V),
@@ -390,7 +448,8 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
       float* t32 = reinterpret_cast<float*>(base + pl.off_t);
       tr(CC_LADDER_PHASE_PREP, 0, 0);
       rc = to_f32(L, L32, (size_t)P * v * v, stream);
-      if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
+      if (!rc)
+        rc = pl.exchange ? swap_cd(t, t32, o, v, stream) : to_f32(t, t32, (size_t)o * o * v * v, stream);
       tr(CC_LADDER_PHASE_PREP, 0, 1);
       if (rc) return rc;
       return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V),
@@ -426,23 +485,42 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
   if (rc) return rc;
   char* base = ws.base;
   const Tracer tr(opts, stream);
-  if (precision == CC_LADDER_FP64) {
-    return backward_blocks<TrF64>(pl, L, t, lam, dL, dt,
-                                  reinterpret_cast<double*>(base + pl.off_V),
-                                  reinterpret_cast<double*>(base + pl.off_W), tr, stream);
+  // exchange: gradients of the ladder at the swapped amplitudes; dt is
+  // accumulated in swapped order in scratch and swapped back at the end
+  double* dtx = pl.exchange ? reinterpret_cast<double*>(base + pl.off_dtx) : dt;
+  if (pl.exchange) {
+    tr(CC_LADDER_PHASE_PREP, 0, 0);
+    rc = swap_cd(dt, dtx, o, v, stream);
+    if (!rc && precision == CC_LADDER_FP64) {
+      rc = swap_cd(t, reinterpret_cast<double*>(base + pl.off_tx), o, v, stream);
+      t = reinterpret_cast<const double*>(base + pl.off_tx);
+    }
+    tr(CC_LADDER_PHASE_PREP, 0, 1);
+    if (rc) return rc;
   }
-  float* L32 = reinterpret_cast<float*>(base + pl.off_L);
-  float* t32 = reinterpret_cast<float*>(base + pl.off_t);
-  float* lam32 = reinterpret_cast<float*>(base + pl.off_lam);
-  tr(CC_LADDER_PHASE_PREP, 0, 0);
-  rc = to_f32(L, L32, (size_t)P * v * v, stream);
-  if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
-  if (!rc) rc = to_f32(lam, lam32, (size_t)o * o * v * v, stream);
-  tr(CC_LADDER_PHASE_PREP, 0, 1);
-  if (rc) return rc;
-  return backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dt,
+  if (precision == CC_LADDER_FP64) {
+    rc = backward_blocks<TrF64>(pl, L, t, lam, dL, dtx, reinterpret_cast<double*>(base + pl.off_V),
+                                reinterpret_cast<double*>(base + pl.off_W), tr, stream);
+  } else {
+    float* L32 = reinterpret_cast<float*>(base + pl.off_L);
+    float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+    float* lam32 = reinterpret_cast<float*>(base + pl.off_lam);
+    tr(CC_LADDER_PHASE_PREP, 0, 0);
+    rc = to_f32(L, L32, (size_t)P * v * v, stream);
+    if (!rc)
+      rc = pl.exchange ? swap_cd(t, t32, o, v, stream) : to_f32(t, t32, (size_t)o * o * v * v, stream);
+    if (!rc) rc = to_f32(lam, lam32, (size_t)o * o * v * v, stream);
+    tr(CC_LADDER_PHASE_PREP, 0, 1);
+    if (rc) return rc;
+    rc = backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dtx,
                                 reinterpret_cast<float*>(base + pl.off_V),
                                 reinterpret_cast<float*>(base + pl.off_W), tr, stream);
+  }
+  if (rc || !pl.exchange) return rc;
+  tr(CC_LADDER_PHASE_PREP, 1, 0);
+  rc = swap_cd(dtx, dt, o, v, stream);
+  tr(CC_LADDER_PHASE_PREP, 1, 1);
+  return rc;
 }
 
 extern "C" int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out_dev,

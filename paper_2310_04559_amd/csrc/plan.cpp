@@ -35,7 +35,8 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
     return CC_LADDER_EINVAL;
   if (!opts) return CC_LADDER_OK;
   if (opts->a_block < 0 || opts->split_depth < 0 || opts->split_depth > 2) return CC_LADDER_EINVAL;
-  if ((opts->flags & ~CC_LADDER_PAIR_SYMMETRIC) != 0 || opts->reserved != 0) return CC_LADDER_EINVAL;
+  if ((opts->flags & ~(CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE)) != 0 || opts->reserved != 0)
+    return CC_LADDER_EINVAL;
   if (opts->split_slices != 0 && (opts->split_slices < 2 || opts->split_slices > 4))
     return CC_LADDER_EINVAL;
   if (opts->k_chunk < 0 || opts->k_chunk % 64 != 0) return CC_LADDER_EINVAL;
@@ -45,7 +46,8 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
 }
 
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int depth, int k_chunk, int pairsym, Plan* plan) {
+                int slices, int depth, int k_chunk, unsigned flags, Plan* plan) {
+  const int pairsym = (flags & CC_LADDER_PAIR_SYMMETRIC) ? 1 : 0;
   if (n_a < 1 || n_a > v) return CC_LADDER_EINVAL;
   Plan p;
   p.o = o; p.v = v; p.P = P;
@@ -62,6 +64,12 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   const size_t rows = p.pairsym ? static_cast<size_t>(pair_prefix(n_a, v)) : static_cast<size_t>(n_a) * v;
   const size_t blk = rows * v2;
   size_t cur = 0;
+  p.exchange = (flags & CC_LADDER_EXCHANGE) ? 1 : 0;
+  if (p.exchange) {
+    // the float32 form swaps while converting into its own operand copy
+    if (precision != CC_LADDER_FP32) p.off_tx = take(&cur, o2 * v2 * sizeof(double));
+    if (p.backward) p.off_dtx = take(&cur, o2 * v2 * sizeof(double));
+  }
   switch (precision) {
     case CC_LADDER_FP64:
       p.off_V = take(&cur, blk * sizeof(double));
@@ -114,24 +122,24 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   if (rc) return rc;
   const int slices = opts ? opts->split_slices : 0;
   const int depth = opts ? opts->split_depth : 0;
-  const int pairsym = (opts && (opts->flags & CC_LADDER_PAIR_SYMMETRIC)) ? 1 : 0;
+  const unsigned flags = opts ? opts->flags : 0u;
   const int k_chunk = opts ? opts->k_chunk : 0;
   if (opts && opts->a_block > 0) {
     const int n_a = opts->a_block < v ? opts->a_block : v;
-    rc = layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, pairsym, plan);
+    rc = layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, flags, plan);
     if (rc) return rc;
     return (budget && plan->bytes > budget) ? CC_LADDER_ENOMEM : CC_LADDER_OK;
   }
   // Largest block that fits: the footprint grows monotonically with n_a.
   Plan best;
-  rc = layout_plan(o, v, P, precision, backward, 1, slices, depth, k_chunk, pairsym, &best);
+  rc = layout_plan(o, v, P, precision, backward, 1, slices, depth, k_chunk, flags, &best);
   if (rc) return rc;
   if (budget && best.bytes > budget) return CC_LADDER_ENOMEM;
   int lo = 1, hi = v;
   while (lo < hi) {
     const int mid = lo + (hi - lo + 1) / 2;
     Plan trial;
-    rc = layout_plan(o, v, P, precision, backward, mid, slices, depth, k_chunk, pairsym, &trial);
+    rc = layout_plan(o, v, P, precision, backward, mid, slices, depth, k_chunk, flags, &trial);
     if (rc) return rc;
     if (!budget || trial.bytes <= budget) {
       lo = mid;
@@ -144,7 +152,7 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   const int nb = (v + best.n_a - 1) / best.n_a;
   const int n_eq = (v + nb - 1) / nb;
   if (n_eq != best.n_a) {
-    rc = layout_plan(o, v, P, precision, backward, n_eq, slices, depth, k_chunk, pairsym, &best);
+    rc = layout_plan(o, v, P, precision, backward, n_eq, slices, depth, k_chunk, flags, &best);
     if (rc) return rc;
   }
   *plan = best;

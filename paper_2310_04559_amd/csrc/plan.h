@@ -22,6 +22,9 @@ struct Plan {
   int slices = 0;       // split-bf16 slice count (0 for the other forms)
   int split_depth = 0;  // split-bf16 anti-diagonals kept beyond the slice triangle (1 or 2)
   int pairsym = 0;      // forward over packed integral rows a <= b (pair-symmetric amplitudes)
+  int exchange = 0;     // exchange partner: amplitudes (and dt) with c,d swapped
+  size_t off_tx = 0;    // exchange: t with its last two indices swapped (float64; not in FP32)
+  size_t off_dtx = 0;   // exchange adjoint: dt of the swapped amplitudes (float64)
   int k_chunk = 0;      // float32 drain interval along the contracted index
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;
@@ -38,7 +41,7 @@ struct Plan {
 
 // Fills `plan` for a block size of n_a (1 <= n_a <= v).  Returns 0 or CC_LADDER_EINVAL.
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int depth, int k_chunk, int pairsym, Plan* plan);
+                int slices, int depth, int k_chunk, unsigned flags, Plan* plan);
 
 // Packed integral rows (a,b), a <= b, ordered by a then b: rows of virtuals
 // [0, a) come first.  pair_prefix(a, v) = sum_{a' < a} (v - a').

@@ -5,7 +5,8 @@ R[i,j,a,b] = sum_cd (sum_x L[x,a,c] L[x,b,d]) t[i,j,c,d]  (eqs. cholesky and
 vfunction); its backward calls the library's hand-written adjoint, which
 rebuilds the integral blocks instead of storing them.  Gradients are
 entrywise in L (no symmetrisation) and need no pair symmetry of the upstream
-gradient.
+gradient.  Options carrying the exchange flag give the exchange partner
+(eq. vfunction2) and its gradients instead.
 """
 from __future__ import annotations
 

@@ -49,6 +49,7 @@ class CcLadderOpts(ctypes.Structure):
 
 
 CC_LADDER_PAIR_SYMMETRIC = 1
+CC_LADDER_EXCHANGE = 2
 
 
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -96,14 +97,16 @@ def strerror(code: int) -> str:
 
 def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
               workspace: Optional[torch.Tensor] = None, trace=None,
-              split_depth: int = 0, pair_symmetric: bool = False) -> CcLadderOpts:
+              split_depth: int = 0, pair_symmetric: bool = False,
+              exchange: bool = False) -> CcLadderOpts:
     """``trace`` is a TRACE_FN (keep a reference to it while the options are in use)."""
     o = CcLadderOpts()
     o.a_block = int(a_block)
     o.split_slices = int(split_slices)
     o.k_chunk = int(k_chunk)
     o.split_depth = int(split_depth)
-    o.flags = CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0
+    o.flags = (CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0) | (
+        CC_LADDER_EXCHANGE if exchange else 0)
     o.reserved = 0
     o.hbm_budget = int(hbm_budget)
     if workspace is not None:

@@ -95,6 +95,23 @@ def test_planner_pair_symmetric_footprint(native):
     assert e.value.code == native.CC_LADDER_EUNSUPPORTED
 
 
+def test_planner_exchange_footprint(native):
+    # the swapped amplitudes (float64; the float32 form swaps into its own copy)
+    # and, for the adjoint, dt in swapped order
+    o, v, P = 4, 30, 50
+    rnd = lambda b: (b + 255) // 256 * 256
+    t64 = rnd(o * o * v * v * 8)
+    ex = native.make_opts(exchange=True)
+    for prec, bwd, extra in (("fp64", False, t64), ("fp64", True, 2 * t64), ("fp32", False, 0),
+                             ("fp32", True, t64), ("split_bf16", False, t64)):
+        plain, n = native.cc_ladder_workspace_query(o, v, P, prec, backward=bwd)
+        swapped, n2 = native.cc_ladder_workspace_query(o, v, P, prec, backward=bwd, opts=ex)
+        assert n == n2 == v and swapped == plain + extra, (prec, bwd)
+    both = native.make_opts(exchange=True, pair_symmetric=True)
+    ps, _ = native.cc_ladder_workspace_query(o, v, P, "fp64", opts=native.make_opts(pair_symmetric=True))
+    assert native.cc_ladder_workspace_query(o, v, P, "fp64", opts=both)[0] == ps + t64
+
+
 def test_planner_explicit_block_and_enomem(native):
     opts = native.make_opts(a_block=7)
     nbytes, n_a = native.cc_ladder_workspace_query(5, 20, 75, "fp64", opts=opts)
@@ -120,6 +137,12 @@ def test_bad_options_rejected(native):
                dict(split_depth=3), dict(split_depth=-1)):
         with pytest.raises(native.LadderError) as e:
             native.cc_ladder_workspace_query(3, 8, 10, "fp32", opts=native.make_opts(**kw))
+        assert e.value.code == native.CC_LADDER_EINVAL
+    for flags, reserved in ((4, 0), (1 << 31, 0), (0, 1)):
+        o = native.make_opts()
+        o.flags, o.reserved = flags, reserved
+        with pytest.raises(native.LadderError) as e:
+            native.cc_ladder_workspace_query(3, 8, 10, "fp64", opts=o)
         assert e.value.code == native.CC_LADDER_EINVAL
 
 

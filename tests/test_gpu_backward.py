@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2310_04559_amd.inputs import CONFIGS, make_inputs, random_general, seed_for
+from paper_2310_04559_amd.inputs import CONFIGS, integer_inputs, make_inputs, random_general, seed_for
 from tests.gpu_common import announce, dev, host, rel_fro
 
 pytestmark = pytest.mark.gpu
@@ -112,3 +112,43 @@ def test_central_differences_gradient_workload(gpu_lib):
         fd = (fp - fm) / (2 * h)
         g = float(dt[idx])
         assert abs(fd - g) <= 1e-6 * abs(g) + 1e-9 * gtmax, (k, idx, fd, g)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 23, 37, 5), (3, 130, 17, 40), (9, 37, 101, 0)])
+def test_backward_exchange(gpu_lib, o, v, P, a_block, precision):
+    # adjoint of the exchange partner (eq. vfunction2), accumulated onto given
+    # dL and dt, against the oracle's gradients of that term
+    announce("backward-exchange", o, v, P, "a_block", a_block, "precision", precision)
+    L, t, lam = random_general(o, v, P, 600 + o + v)
+    dL0 = np.random.default_rng(3).standard_normal(L.shape)
+    dt0 = np.random.default_rng(4).standard_normal(t.shape)
+    dL_ref, dt_ref = oracle.exchange_backward(L, t, lam)
+    dL, dt = run_backward(gpu_lib, L, t, lam, precision, dL0, dt0, a_block=a_block, exchange=True)
+    assert rel_fro(dL - dL0, dL_ref) < TOL_BWD[precision]
+    assert rel_fro(dt - dt0, dt_ref) < TOL_BWD[precision]
+
+
+def test_backward_exchange_integer_exact(gpu_lib):
+    announce("backward-exchange-int")
+    L, t = integer_inputs(3, 10, 5, 79)
+    lam = integer_inputs(3, 10, 5, 80)[1]
+    dL_ref, dt_ref = oracle.exchange_backward(L, t, lam)
+    for precision in (0, 1):
+        dL, dt = run_backward(gpu_lib, L, t, lam, precision, exchange=True)
+        assert np.array_equal(dL, dL_ref) and np.array_equal(dt, dt_ref), precision
+
+
+def test_autograd_function_exchange(gpu_lib):
+    announce("autograd-exchange")
+    from paper_2310_04559_amd.ladder import ladder
+
+    L, t, lam = random_general(4, 18, 25, 32)
+    Ld = dev(L).requires_grad_(True)
+    td = dev(t).requires_grad_(True)
+    R = ladder(Ld, td, opts=gpu_lib.make_opts(exchange=True))
+    gL, gt = torch.autograd.grad((R * dev(lam)).sum(), (Ld, td))
+    dL_ref, dt_ref = oracle.exchange_backward(L, t, lam)
+    assert rel_fro(host(R), oracle.exchange_forward(L, t)) < 1e-12
+    assert rel_fro(host(gL), dL_ref) < 1e-12
+    assert rel_fro(host(gt), dt_ref) < 1e-12

@@ -6,7 +6,7 @@ import torch
 import oracle
 from paper_2310_04559_amd.inputs import (CONFIGS, integer_inputs, make_inputs, random_general,
                                          seed_for)
-from tests.gpu_common import TOL, announce, dev, host, rel_fro
+from tests.gpu_common import TOL, TOL_SPLIT, TOL_SPLIT_WORKLOAD, announce, dev, host, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -182,3 +182,60 @@ def test_forward_pair_symmetric_full_size(gpu_lib):
     Rt = R.permute(1, 0, 3, 2)
     assert torch.equal(torch.where(off, R, 0.0), torch.where(off, Rt, 0.0))
     assert float(torch.linalg.vector_norm(R - Rt) / torch.linalg.vector_norm(R)) < 1e-14
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (3, 130, 17, 40),
+                                           (2, 1, 3, 0), (12, 44, 131, 13)])
+def test_forward_exchange(gpu_lib, o, v, P, a_block, precision):
+    # exchange partner (eq. vfunction2) on unsymmetric inputs: (ad|bc) differs
+    # from (ac|bd) and nothing cancels; ragged v spans several 32-wide swap tiles
+    announce("forward-exchange", o, v, P, "a_block", a_block, "precision", precision)
+    L, t, _ = random_general(o, v, P, 900 + o + v)
+    R0 = np.random.default_rng(9).standard_normal(t.shape)
+    inc = oracle.exchange_forward(L, t)
+    got = run_forward(gpu_lib, L, t, R0, precision, a_block=a_block, exchange=True)
+    tol = TOL_SPLIT[4] if precision == 2 else TOL[precision]
+    assert rel_fro(got - R0, inc) < tol
+
+
+def test_forward_exchange_integer_exact(gpu_lib):
+    announce("forward-exchange-int")
+    L, t = integer_inputs(3, 10, 5, 78)
+    ref = oracle.exchange_forward(L, t)
+    for precision in (0, 1, 2):
+        got = run_forward(gpu_lib, L, t, np.zeros_like(t), precision, exchange=True)
+        assert np.array_equal(got, ref), precision
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forward_exchange_pair_symmetric(gpu_lib, precision):
+    # swapping c and d keeps pair symmetry, so both flags combine
+    announce("forward-exchange-pairsym", precision)
+    L, t, _ = random_general(9, 37, 101, 44)
+    t = _pair_symmetric(t)
+    inc = oracle.exchange_forward(L, t)
+    got = run_forward(gpu_lib, L, t, np.zeros_like(t), precision, a_block=7, exchange=True,
+                      pair_symmetric=True)
+    assert rel_fro(got, inc) < TOL[precision]
+
+
+def test_forward_exchange_full_size_sampled(gpu_lib):
+    # the exchange partner at the 40/360/1200 workload, default options; the
+    # oracle's columns come from the ladder of the swapped amplitudes, whose
+    # identity with the exchange term is pinned on the CPU
+    o, v, P = CONFIGS["c3"]
+    announce("forward-exchange-full", "c3")
+    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    Ld, td = dev(inp.L_vv), dev(inp.t)
+    pairs = _sampled_pairs(v, 16, 4)
+    ref = oracle.ladder_pairs(inp.L_vv, np.ascontiguousarray(inp.t.transpose(0, 1, 3, 2)), pairs)
+    ia = torch.tensor([a for a, _ in pairs], device="cuda")
+    ib = torch.tensor([b for _, b in pairs], device="cuda")
+    for precision in (0, 1, 2):
+        R = torch.zeros_like(td)
+        gpu_lib.cc_ladder_residual(Ld, td, R, precision, opts=gpu_lib.make_opts(exchange=True))
+        torch.cuda.synchronize()
+        tol = TOL_SPLIT_WORKLOAD[4] if precision == 2 else TOL[precision]
+        assert rel_fro(host(R[:, :, ia, ib].permute(2, 0, 1)), ref) < tol, precision
+        del R
