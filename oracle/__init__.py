@@ -17,6 +17,10 @@ What it computes (arXiv 2310.04559):
   (entrywise gradient: each array entry of L is an independent variable).
 * eq. (vfunction2): the exchange partner ``R[i,j,a,b] += sum_{c,d} (ad|bc) t[i,j,c,d]``
   and its adjoint.
+* eq. (vfunction3): ``X[i,j,k,l] += sum_{c,d} (kc|ld) t[i,j,c,d]`` and
+  eq. (vfunction4): ``Y[i,j,b,k] += sum_{c,d} (bd|kc) t[i,j,c,d]``, with the
+  occupied-virtual vectors ``L_ov[x][k][c]`` in ``(kc|ld) = sum_x L_ov[x,k,c] L_ov[x,l,d]``
+  and ``(bd|kc) = sum_x L[x,b,d] L_ov[x,k,c]``.
 
 Algorithm: the paper's loop over one virtual index (Sec. "Pythonic
 implementations of the CC vector function", the tensordot variant that keeps
@@ -24,16 +28,18 @@ intermediates at v^3): for each ``a`` the slice ``V[a,:,:,:]`` is built from
 the Cholesky vectors and contracted with the amplitudes.  Each step is one
 library matrix product in float64; there is no further blocking or fusion.
 
-Layouts: ``L[x][p][q]`` (the virtual-virtual block), ``t, R, lam[i][j][a][b]``,
-all float64 C-contiguous.
+Layouts: ``L[x][p][q]`` (the virtual-virtual block), ``L_ov[x][k][c]``,
+``t, R, lam[i][j][a][b]``, ``X[i][j][k][l]``, ``Y[i][j][b][k]``, all float64
+C-contiguous.
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_loss",
-           "exchange_forward", "exchange_backward",
-           "reduce_dot", "eri_slice", "nominal_flops_forward", "nominal_flops_backward"]
+           "exchange_forward", "exchange_backward", "intermediate_ijkl", "intermediate_ijbk",
+           "reduce_dot", "eri_slice", "nominal_flops_forward", "nominal_flops_backward",
+           "nominal_flops_ijkl", "nominal_flops_ijbk"]
 
 
 def _check(L, t):
@@ -121,6 +127,56 @@ def exchange_backward(L, t, lam):
     return dL, dt.reshape(o, o, v, v)
 
 
+def _check_ov(L_ov, t):
+    L_ov = np.asarray(L_ov, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    if L_ov.ndim != 3 or t.ndim != 4 or t.shape[0] != t.shape[1] or t.shape[2] != t.shape[3]:
+        raise ValueError("L_ov must be [P][o][v] and t [o][o][v][v]")
+    if L_ov.shape[1] != t.shape[0] or L_ov.shape[2] != t.shape[2]:
+        raise ValueError("L_ov and t disagree on o or v")
+    return L_ov, t
+
+
+def intermediate_ijkl(L_ov, t, X=None, k_begin: int = 0, k_end=None) -> np.ndarray:
+    """``X[i,j,k,l] += sum_{c,d} (kc|ld) t[i,j,c,d]`` (eq. vfunction3), with
+    ``(kc|ld) = sum_x L_ov[x,k,c] L_ov[x,l,d]``; loop over the occupied ``k``,
+    building ``(kc|ld)`` for one ``k`` at a time.  ``[k_begin, k_end)``
+    restricts the loop (a bounded sample)."""
+    L_ov, t = _check_ov(L_ov, t)
+    P, o, v = L_ov.shape
+    if X is None:
+        X = np.zeros((o, o, o, o))
+    k_end = o if k_end is None else k_end
+    T = t.reshape(o * o, v * v)                       # [(i,j)][(c,d)]
+    Lf = L_ov.reshape(P, o * v)
+    for k in range(k_begin, k_end):
+        G = (L_ov[:, k, :].T @ Lf).reshape(v, o, v)   # [c][l][d] = (kc|ld)
+        Gk = G.transpose(1, 0, 2).reshape(o, v * v)   # [l][(c,d)]
+        X[:, :, k, :] += (T @ Gk.T).reshape(o, o, o)
+    return X
+
+
+def intermediate_ijbk(L, L_ov, t, Y=None, b_begin: int = 0, b_end=None) -> np.ndarray:
+    """``Y[i,j,b,k] += sum_{c,d} (bd|kc) t[i,j,c,d]`` (eq. vfunction4), with
+    ``(bd|kc) = sum_x L[x,b,d] L_ov[x,k,c]``; loop over the virtual ``b``.
+    ``[b_begin, b_end)`` restricts the loop (a bounded sample)."""
+    L, t = _check(L, t)
+    L_ov, _ = _check_ov(L_ov, t)
+    P, o, v = L_ov.shape
+    if L.shape[0] != P:
+        raise ValueError("L and L_ov disagree on P")
+    if Y is None:
+        Y = np.zeros((o, o, v, o))
+    b_end = v if b_end is None else b_end
+    T = t.reshape(o * o, v * v)
+    Lf = L_ov.reshape(P, o * v)
+    for b in range(b_begin, b_end):
+        G = (L[:, b, :].T @ Lf).reshape(v, o, v)      # [d][k][c] = (bd|kc)
+        Gb = G.transpose(1, 2, 0).reshape(o, v * v)   # [k][(c,d)]
+        Y[:, :, b, :] += (T @ Gb.T).reshape(o, o, o)
+    return Y
+
+
 def ladder_backward(L, t, lam):
     """Entrywise gradients ``(dL, dt)`` of ``sum lam * R`` with R the ladder
     term; one pass over ``a`` as in the forward, V[a] rebuilt, not stored."""
@@ -180,6 +236,16 @@ def nominal_flops_forward(o: int, v: int, P: int) -> float:
     """Factorised cost of one forward: 2 P v^4 (integral slices) + 2 o^2 v^4
     (amplitude contraction)."""
     return 2.0 * (P + o * o) * float(v) ** 4
+
+
+def nominal_flops_ijkl(o: int, v: int, P: int) -> float:
+    """Integrals (kc|ld) for all k, l (2 P o^2 v^2) + contraction (2 o^4 v^2)."""
+    return 2.0 * (P + o * o) * float(o * v) ** 2
+
+
+def nominal_flops_ijbk(o: int, v: int, P: int) -> float:
+    """Integrals (bd|kc) (2 P o v^3) + contraction (2 o^3 v^3)."""
+    return 2.0 * (P + o * o) * o * float(v) ** 3
 
 
 def nominal_flops_backward(o: int, v: int, P: int) -> float:

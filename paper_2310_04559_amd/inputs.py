@@ -20,7 +20,8 @@ stand in for it):
 4. ``(ia|jb) = sum_x L[x,i,o+a] L[x,j,o+b]`` and
    ``t[i,j,a,b] = (ia|jb) / (e_i + e_j - e_a - e_b)`` (MP2-like amplitudes;
    the denominator lies in [-10, -0.8], never zero).
-5. ``L_vv = L[:, o:, o:]`` (contiguous ``[P][v][v]``).
+5. ``L_vv = L[:, o:, o:]`` (contiguous ``[P][v][v]``) and
+   ``L_ov = L[:, :o, o:]`` (contiguous ``[P][o][v]``, occupied first).
 6. With ``with_lambda``: ``G = 1e-2 * rng.standard_normal((o, o, v, v))`` and
    ``lam = (G + G.transpose(1, 0, 3, 2)) / 2`` (pair-symmetric), drawn after
    everything above.
@@ -35,7 +36,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["LadderInputs", "make_inputs", "paper_shape", "CONFIGS", "seed_for"]
+__all__ = ["LadderInputs", "make_inputs", "paper_shape", "CONFIGS", "seed_for", "random_general",
+           "integer_inputs", "random_ov", "integer_ov"]
 
 
 @dataclass
@@ -50,6 +52,7 @@ class LadderInputs:
     e_vir: np.ndarray         # [v]
     ovov: np.ndarray          # (ia|jb) stored as [i][j][a][b]
     lam: Optional[np.ndarray] = None  # [o][o][v][v]
+    L_ov: Optional[np.ndarray] = None  # [P][o][v]
 
 
 # Workload shapes: (o, v, P).  c1 is the brute-force tier, c2 the first GPU
@@ -108,7 +111,8 @@ def make_inputs(o: int, v: int, P: int, seed: int, with_lambda: bool = False,
     L *= (np.exp(-np.arange(P, dtype=np.float64) / 25.0) / np.sqrt(n))[:, None, None]
     e_occ = np.sort(rng.uniform(-2.0, -0.3, o))
     e_vir = np.sort(rng.uniform(0.1, 3.0, v))
-    ovov = _ovov(np.ascontiguousarray(L[:, :o, o:]), device)
+    L_ov = np.ascontiguousarray(L[:, :o, o:])
+    ovov = _ovov(L_ov, device)
     D = (e_occ[:, None, None, None] + e_occ[None, :, None, None]
          - e_vir[None, None, :, None] - e_vir[None, None, None, :])
     t = ovov / D
@@ -121,7 +125,7 @@ def make_inputs(o: int, v: int, P: int, seed: int, with_lambda: bool = False,
         lam = 0.5 * (G + G.transpose(1, 0, 3, 2))
         lam = np.ascontiguousarray(lam)
     return LadderInputs(o=o, v=v, P=P, seed=seed, L_vv=L_vv, t=np.ascontiguousarray(t),
-                        e_occ=e_occ, e_vir=e_vir, ovov=ovov, lam=lam)
+                        e_occ=e_occ, e_vir=e_vir, ovov=ovov, lam=lam, L_ov=L_ov)
 
 
 def integer_inputs(o: int, v: int, P: int, seed: int, lo: int = -2, hi: int = 2):
@@ -141,3 +145,15 @@ def random_general(o: int, v: int, P: int, seed: int):
     t = rng.standard_normal((o, o, v, v)) / v
     lam = rng.standard_normal((o, o, v, v)) / v
     return L, t, lam
+
+
+def random_ov(o: int, v: int, P: int, seed: int):
+    """Unstructured N(0,1)/sqrt(v) occupied-virtual Cholesky vectors [P][o][v]."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((P, o, v)) / np.sqrt(v)
+
+
+def integer_ov(o: int, v: int, P: int, seed: int, lo: int = -2, hi: int = 2):
+    """Small-integer occupied-virtual Cholesky vectors [P][o][v]."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(lo, hi + 1, size=(P, o, v)).astype(np.float64)

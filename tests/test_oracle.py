@@ -12,8 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2310_04559_amd.inputs import (CONFIGS, integer_inputs, make_inputs, paper_shape,
-                                         random_general, seed_for)
+from paper_2310_04559_amd.inputs import (CONFIGS, integer_inputs, integer_ov, make_inputs,
+                                         paper_shape, random_general, random_ov, seed_for)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -387,3 +387,113 @@ def test_exchange_backward_exact_differences_and_euler():
     lo = oracle.ladder_loss(lam2, oracle.exchange_forward(L2, t2))
     assert abs(np.sum(dt2 * t2) - lo) <= 1e-13 * abs(lo)
     assert abs(np.sum(dL2 * L2) - 2 * lo) <= 1e-13 * abs(lo)
+
+
+# ---------------------------------------------------------------------------
+# occupied intermediates (eqs. vfunction3 and vfunction4)
+# ---------------------------------------------------------------------------
+
+def _int_ijkl(Lov, t):
+    P, o, v = len(Lov), len(Lov[0]), len(Lov[0][0])
+    X = [[[[0] * o for _ in range(o)] for _ in range(o)] for _ in range(o)]
+    for i, j, k, l in itertools.product(range(o), repeat=4):
+        s = 0
+        for c, d in itertools.product(range(v), range(v)):
+            s += sum(Lov[x][k][c] * Lov[x][l][d] for x in range(P)) * t[i][j][c][d]
+        X[i][j][k][l] = s
+    return X
+
+
+def _int_ijbk(L, Lov, t):
+    P, o, v = len(Lov), len(Lov[0]), len(Lov[0][0])
+    Y = [[[[0] * o for _ in range(v)] for _ in range(o)] for _ in range(o)]
+    for i, j, b, k in itertools.product(range(o), range(o), range(v), range(o)):
+        s = 0
+        for c, d in itertools.product(range(v), range(v)):
+            s += sum(L[x][b][d] * Lov[x][k][c] for x in range(P)) * t[i][j][c][d]
+        Y[i][j][b][k] = s
+    return Y
+
+
+@pytest.mark.parametrize("o,v,P,seed", [(2, 3, 2, 91), (3, 2, 3, 92), (3, 4, 2, 93)])
+def test_intermediates_equal_integer_bruteforce(o, v, P, seed):
+    L, t = integer_inputs(o, v, P, seed)
+    Lov = integer_ov(o, v, P, seed + 100)
+    X = np.array(_int_ijkl(_to_int(Lov), _to_int(t)), dtype=np.float64)
+    Y = np.array(_int_ijbk(_to_int(L), _to_int(Lov), _to_int(t)), dtype=np.float64)
+    assert np.array_equal(oracle.intermediate_ijkl(Lov, t), X)
+    assert np.array_equal(oracle.intermediate_ijbk(L, Lov, t), Y)
+
+
+def test_intermediates_reduce_to_ladder_and_exchange():
+    # with as many occupied as virtual orbitals and L_ov = L, (kc|ld) is the
+    # ladder's (ac|bd) and (bd|kc) the exchange integral (ad|bc) renamed
+    L, t, _ = random_general(4, 4, 9, 94)
+    assert rel_fro(oracle.intermediate_ijkl(L, t), oracle.ladder_forward(L, t)) < 1e-14
+    assert rel_fro(oracle.intermediate_ijbk(L, L, t), oracle.exchange_forward(L, t)) < 1e-14
+
+
+def test_intermediates_rank_one_closed_form():
+    # L_ov[x,k,c] = u_x p_k q_c, L[x,b,d] = u_x r_b s_d:
+    # X = |u|^2 p_k p_l (q^T t_ij q), Y = |u|^2 r_b p_k (q^T t_ij s)
+    rng = np.random.default_rng(95)
+    o, v, P = 3, 5, 4
+    u, p, q = rng.standard_normal(P), rng.standard_normal(o), rng.standard_normal(v)
+    r, s = rng.standard_normal(v), rng.standard_normal(v)
+    t = rng.standard_normal((o, o, v, v))
+    Lov = u[:, None, None] * p[None, :, None] * q[None, None, :]
+    L = u[:, None, None] * r[None, :, None] * s[None, None, :]
+    uu = float(u @ u)
+    qtq = np.array([[q @ t[i, j] @ q for j in range(o)] for i in range(o)])
+    qts = np.array([[q @ t[i, j] @ s for j in range(o)] for i in range(o)])
+    X = uu * qtq[:, :, None, None] * p[None, None, :, None] * p[None, None, None, :]
+    Y = uu * qts[:, :, None, None] * r[None, None, :, None] * p[None, None, None, :]
+    assert rel_fro(oracle.intermediate_ijkl(Lov, t), X) < 1e-14
+    assert rel_fro(oracle.intermediate_ijbk(L, Lov, t), Y) < 1e-14
+
+
+def test_intermediates_unit_amplitude_picks_one_integral():
+    # t[i,j,c,d] = 1 at (c0,d0) only: X[i,j,k,l] = (k c0|l d0) and
+    # Y[i,j,b,k] = (b d0|k c0) for every (i,j)
+    o, v, P = 3, 6, 5
+    Lov = random_ov(o, v, P, 96)
+    L, _, _ = random_general(o, v, P, 97)
+    c0, d0 = 4, 1
+    t = np.zeros((o, o, v, v))
+    t[:, :, c0, d0] = 1.0
+    X = oracle.intermediate_ijkl(Lov, t)
+    Y = oracle.intermediate_ijbk(L, Lov, t)
+    for k, l in itertools.product(range(o), range(o)):
+        assert np.allclose(X[:, :, k, l], sum(Lov[x, k, c0] * Lov[x, l, d0] for x in range(P)),
+                           rtol=1e-14, atol=0)
+    for b, k in itertools.product(range(v), range(o)):
+        assert np.allclose(Y[:, :, b, k], sum(L[x, b, d0] * Lov[x, k, c0] for x in range(P)),
+                           rtol=1e-14, atol=0)
+
+
+def test_ijkl_pair_symmetry_and_ranges():
+    # (kc|ld) = (ld|kc): a pair-symmetric t gives X[i,j,k,l] = X[j,i,l,k];
+    # the sampled k (or b) ranges reproduce the full result
+    o, v, P = 4, 7, 6
+    L, t, _ = random_general(o, v, P, 98)
+    t = 0.5 * (t + t.transpose(1, 0, 3, 2))
+    Lov = random_ov(o, v, P, 99)
+    X = oracle.intermediate_ijkl(Lov, t)
+    assert rel_fro(X.transpose(1, 0, 3, 2), X) < 1e-15
+    Xs = np.zeros_like(X)
+    for k0, k1 in ((0, 1), (1, 3), (3, 4)):
+        oracle.intermediate_ijkl(Lov, t, Xs, k0, k1)
+    assert np.array_equal(Xs, X)
+    Y = oracle.intermediate_ijbk(L, Lov, t)
+    Ys = np.zeros_like(Y)
+    for b0, b1 in ((0, 2), (2, 7)):
+        oracle.intermediate_ijbk(L, Lov, t, Ys, b0, b1)
+    assert np.array_equal(Ys, Y)
+
+
+def test_generator_ov_block_matches_full_vectors():
+    # L_ov is the occupied-virtual block of the same symmetric vectors whose
+    # occupied-virtual products define the amplitudes' numerator (ia|jb)
+    inp = make_inputs(3, 5, 7, 1234)
+    ovov = np.einsum("xia,xjb->ijab", inp.L_ov, inp.L_ov)
+    assert rel_fro(ovov, inp.ovov) < 1e-14
