@@ -12,9 +12,11 @@ float64 form; the float32 and split-bf16 forms are timed the same way and
 reported with their error against the float64 oracle.
 
 Also reported: the dominant kernel's roofline (HIP events recorded around its
-launches through the library's trace hook), the adjoint's throughput on the
-gradient workload (o=30, v=300, P=900), and the oracle timed on the host's
-cores over a bounded sample of the same workload.
+launches through the library's trace hook), the exchange partner, the
+occupied intermediates X[i,j,k,l] and Y[i,j,b,k] on the same workload's
+vectors, the adjoint's throughput on the gradient workload (o=30, v=300,
+P=900), and the oracle timed on the host's cores over a bounded sample of the
+same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
 """
@@ -315,6 +317,74 @@ def bench_large(native):
     return res
 
 
+def bench_intermediates(native, inp, steps, warmup, ws_bytes):
+    """The occupied intermediates (eqs. vfunction3/vfunction4) on the throughput
+    workload's own L_ov, L_vv and t: time per call with HIP events on the
+    call's stream, nominal TFLOP/s, and the error of sampled first-index
+    slices against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    o, v, P = inp.o, inp.v, inp.P
+    Ld = torch.from_numpy(inp.L_vv).cuda()
+    Lovd = torch.from_numpy(inp.L_ov).cuda()
+    td = torch.from_numpy(inp.t).cuda()
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    res = {}
+    for which in ("ijkl", "ijbk"):
+        shape = (o, o, o, o) if which == "ijkl" else (o, o, v, o)
+        firsts = [0, o - 1] if which == "ijkl" else [0, v // 2, v - 1]
+        ref = np.zeros(shape)
+        for p in firsts:
+            if which == "ijkl":
+                oracle.intermediate_ijkl(inp.L_ov, inp.t, ref, p, p + 1)
+            else:
+                oracle.intermediate_ijbk(inp.L_vv, inp.L_ov, inp.t, ref, p, p + 1)
+        flops = (oracle.nominal_flops_ijkl if which == "ijkl" else oracle.nominal_flops_ijbk)(o, v, P)
+        Z = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        for prec_name in ("fp64", "fp32"):
+            prec = native.PRECISIONS[prec_name]
+            timer = PhaseTimer(native, stream)
+            opts = native.make_opts(workspace=ws, trace=timer.fn)
+            _, block = native.cc_intermediate_workspace_query(which, o, v, P, prec, hbm_budget=ws_bytes)
+
+            def call():
+                if which == "ijkl":
+                    native.cc_intermediate_ijkl(Lovd, td, Z, prec, opts=opts)
+                else:
+                    native.cc_intermediate_ijbk(Ld, Lovd, td, Z, prec, opts=opts)
+
+            Z.zero_()
+            call()
+            torch.cuda.synchronize()
+            got = Z.cpu().numpy()[:, :, firsts, :]
+            err = float(np.linalg.norm(got - ref[:, :, firsts, :]) / np.linalg.norm(ref[:, :, firsts, :]))
+            for _ in range(warmup):
+                call()
+            torch.cuda.synchronize()
+            timer.reset()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            r = {"ms_per_call": ms, "tflops": flops / (ms * 1e-3) / 1e12, "block": block,
+                 "nominal_tflop": flops / 1e12, "rel_err_vs_oracle_sampled": err,
+                 "within_tolerance": err < TOL[prec_name],
+                 "phases_ms_avg": {k: d["ms_avg"] for k, d in timer.summary().items()}}
+            res[f"{which}_{prec_name}"] = r
+            log(f"intermediate {which} {prec_name}: {ms:.2f} ms {r['tflops']:.1f} TFLOP/s "
+                f"err {err:.2e} block {block} phases {json.dumps(r['phases_ms_avg'])}")
+        del Z
+    del ws, Ld, Lovd, td
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +395,7 @@ def main():
                                        "fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-intermediates", action="store_true")
     ap.add_argument("--large", action="store_true",
                     help="also run the o=60, v=600, P=1800 workload (about two minutes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -445,6 +516,10 @@ def main():
     }
     del L, t, R
     torch.cuda.empty_cache()
+    if not args.no_intermediates:
+        log("intermediates ...")
+        line["intermediates"] = bench_intermediates(native, inp, args.steps, args.warmup, ws_bytes)
+        torch.cuda.empty_cache()
     if not args.no_adjoint:
         log("adjoint ...")
         line["adjoint"] = bench_adjoint(native, max(1, min(args.steps, 2)))

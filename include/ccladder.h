@@ -12,14 +12,22 @@
  * Sec. "tensordot", generalised to blocks sized to device memory as in
  * Sec. "CuPy and batch-wise computations").
  *
+ * The same build-then-contract scheme gives the exchange partner of the
+ * ladder (eq. vfunction2, an option flag) and the two occupied intermediates
+ * that share one contraction pattern (eqs. vfunction3 and vfunction4), which
+ * take the occupied-virtual block of the Cholesky vectors as well.
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  * - Tensor pointers are DEVICE pointers to float64, C-contiguous:
  *     L   [P][v][v]      virtual-virtual block of the Cholesky vectors
  *     t   [o][o][v][v]   t[i][j][c][d]
  *     R   [o][o][v][v]   R[i][j][a][b]
+ *     L_ov [P][o][v]     occupied-virtual block of the Cholesky vectors, L_ov[x][k][c]
+ *     X   [o][o][o][o]   X[i][j][k][l]  (eq. vfunction3)
+ *     Y   [o][o][v][o]   Y[i][j][b][k]  (eq. vfunction4)
  *   The caller owns all of them; the library never frees caller memory.
- * - Results are ACCUMULATED (+=) into R, dL and dt; zero them for the bare term.
+ * - Results are ACCUMULATED (+=) into R, dL, dt, X and Y; zero them for the bare term.
  * - Calls enqueue work on `stream` (NULL = the legacy default stream) and
  *   return without a host synchronisation.  Kernel faults surface at the
  *   caller's next synchronisation of that stream.
@@ -150,6 +158,45 @@ int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out
 int cc_ladder_workspace_query(int o, int v, int P, int precision, int backward,
                               size_t hbm_budget, const cc_ladder_opts* opts,
                               size_t* bytes, int* a_block);
+
+/* Which occupied intermediate (eqs. vfunction3 and vfunction4). */
+typedef enum {
+  CC_INTERMEDIATE_IJKL = 0,  /* X[i][j][k][l] += sum_{c,d} (kc|ld) t[i][j][c][d] */
+  CC_INTERMEDIATE_IJBK = 1   /* Y[i][j][b][k] += sum_{c,d} (bd|kc) t[i][j][c][d] */
+} cc_intermediate_kind;
+
+/*
+ * Occupied-occupied intermediate (eq. vfunction3):
+ *   X[i][j][k][l] += sum_{c,d} ( sum_x L_ov[x][k][c] L_ov[x][l][d] ) t[i][j][c][d]
+ * The integrals (kc|ld) are rebuilt for blocks of the occupied index k
+ * (opts->a_block counts occupied indices here).  FP64 and FP32 forms;
+ * SPLIT_BF16 and every opts->flags bit return CC_LADDER_EUNSUPPORTED.
+ * o, v, P > 0.  X must not overlap L_ov or t.
+ */
+int cc_intermediate_ijkl(int o, int v, int P,
+                         const double* L_ov, const double* t, double* X,
+                         int precision, hipStream_t stream, const cc_ladder_opts* opts);
+
+/*
+ * Intermediate with one virtual and one occupied output index (eq. vfunction4):
+ *   Y[i][j][b][k] += sum_{c,d} ( sum_x L[x][b][d] L_ov[x][k][c] ) t[i][j][c][d]
+ * The integrals (bd|kc) are rebuilt for blocks of the virtual index b; the
+ * amplitudes are met with c and d swapped (a copy in scratch, or inside the
+ * FP32 form's float32 copy).  Forms and flags as cc_intermediate_ijkl.
+ * Y must not overlap L, L_ov or t.
+ */
+int cc_intermediate_ijbk(int o, int v, int P,
+                         const double* L, const double* L_ov, const double* t, double* Y,
+                         int precision, hipStream_t stream, const cc_ladder_opts* opts);
+
+/*
+ * Host-only planner query for the intermediates (`which` a cc_intermediate_kind):
+ * scratch bytes and first indices per integral block under `hbm_budget`
+ * (0 = no limit), as cc_ladder_workspace_query.
+ */
+int cc_intermediate_workspace_query(int which, int o, int v, int P, int precision,
+                                    size_t hbm_budget, const cc_ladder_opts* opts,
+                                    size_t* bytes, int* block);
 
 /* Static description of an error code (never NULL). */
 const char* cc_ladder_strerror(int code);

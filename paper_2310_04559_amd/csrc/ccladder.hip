@@ -9,6 +9,11 @@
 //   W'_A[a][c][b][d] = sum_(ij) lam[(ij)][(ab)] t[(ij)][(cd)]
 //   dL[x][(a c)]  += sum_(bd) L[x][(bd)] W'_A[(ac)][(bd)]          (a in A)
 //   dL[x][(b d)]  += sum_(a in A, c) L[x][(ac)] W'_A[(ac)][(bd)]
+// Occupied intermediates (eqs. vfunction3/vfunction4), per block of first index p:
+//   build    G[p][y][x][d] = sum_x' Lrow[x'][p][x] L_ov[x'][y][d]   GEMM M=(p,x) N=(y,d) K=x'
+//   contract Z[(ij)][(p y)] += sum_(xd) t'[(ij)][(xd)] G[(py)][(xd)]
+// ijkl: Lrow = L_ov, t' = t; ijbk: Lrow = L, t' = t with c and d swapped, since
+// G[b][k][d][c] = (bd|kc) carries its last two indices in (d, c) order.
 // Exchange partner (eq. vfunction2): the same schedule on t with c and d swapped,
 // since sum_(cd) (ad|bc) t[i][j][c][d] = sum_(cd) (ac|bd) t[i][j][d][c]; the
 // adjoint's dt comes back with the swap undone.
@@ -290,6 +295,26 @@ size_t default_budget() {
   return half < cap ? half : cap;
 }
 
+// The caller's workspace when given (it must hold the plan), else a stream-
+// ordered allocation released when `ws` goes out of scope.
+int take_scratch(const Plan& plan, hipStream_t stream, const cc_ladder_opts* opts, Scratch* ws) {
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < plan.bytes) return CC_LADDER_ENOMEM;
+    ws->base = static_cast<char*>(opts->workspace);
+    return CC_LADDER_OK;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipMallocAsync(&p, plan.bytes ? plan.bytes : 256, stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? CC_LADDER_ENOMEM : CC_LADDER_EHIP;
+  }
+  ws->base = static_cast<char*>(p);
+  ws->owned = true;
+  ws->stream = stream;
+  return CC_LADDER_OK;
+}
+
 int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream_t stream,
                      const cc_ladder_opts* opts, Plan* plan, Scratch* ws) {
   size_t budget;
@@ -300,23 +325,9 @@ int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream
   else
     budget = default_budget();
   if (!budget) return CC_LADDER_EHIP;
-  int rc = make_plan(o, v, P, precision, backward, budget, opts, plan);
+  const int rc = make_plan(o, v, P, precision, backward, budget, opts, plan);
   if (rc) return rc;
-  if (opts && opts->workspace) {
-    if (opts->workspace_bytes < plan->bytes) return CC_LADDER_ENOMEM;
-    ws->base = static_cast<char*>(opts->workspace);
-    return CC_LADDER_OK;
-  }
-  void* p = nullptr;
-  const hipError_t e = hipMallocAsync(&p, plan->bytes ? plan->bytes : 256, stream);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return e == hipErrorOutOfMemory ? CC_LADDER_ENOMEM : CC_LADDER_EHIP;
-  }
-  ws->base = static_cast<char*>(p);
-  ws->owned = true;
-  ws->stream = stream;
-  return CC_LADDER_OK;
+  return take_scratch(*plan, stream, opts, ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,6 +415,97 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     if (rc) return rc;
   }
   return CC_LADDER_OK;
+}
+
+// Occupied intermediates: Z[(ij)][(p, y)] += sum_(x,d) t[(ij)][(x,d)] G[(p,y)][(x,d)],
+// G built per block of first indices p from rows (p, x) of Lrow ([P][n_first*v],
+// leading dimension ld_row) and columns (y, d) of L_ov ([P][o*v]).
+template <class Tr>
+int intermediate_blocks(const Plan& pl, const typename Tr::T* Lrow, long long ld_row,
+                        const typename Tr::T* Lov, const typename Tr::T* t, double* Z,
+                        typename Tr::T* V, const Tracer& tr, hipStream_t s) {
+  const int o = pl.o, v = pl.v, P = pl.P;
+  const long long v2 = (long long)v * v;
+  const int n_first = pl.op == kOpIjkl ? o : v;
+  const long long ld_out = (long long)n_first * o;
+  const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  for (int p0 = 0, blk = 0; p0 < n_first; p0 += pl.n_a, ++blk) {
+    const int np = (n_first - p0) < pl.n_a ? (n_first - p0) : pl.n_a;
+    tr(CC_LADDER_PHASE_BUILD, blk, 0);
+    int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(Lrow + (long long)p0 * v, ld_row, Lov,
+                                               (long long)o * v, V, 0, np * v, o * v, P, v, drain,
+                                               s);
+    tr(CC_LADDER_PHASE_BUILD, blk, 1);
+    if (rc) return rc;
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
+    rc = launch_gemm<Tr, KC, KC, EPI_ACC>(t, v2, V, v2, Z + (long long)p0 * o, ld_out, o * o,
+                                          np * o, static_cast<int>(v2), v, drain, s);
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
+    if (rc) return rc;
+  }
+  return CC_LADDER_OK;
+}
+
+// Shared body of the two intermediates; Lrow is L_ov (ijkl) or L (ijbk).
+int intermediate_call(int which, int o, int v, int P, const double* Lrow, const double* Lov,
+                      const double* t, double* Z, int precision, hipStream_t stream,
+                      const cc_ladder_opts* opts) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  if (!Lrow || !Lov || !t || !Z) return CC_LADDER_EINVAL;
+  const bool ijkl = which == CC_INTERMEDIATE_IJKL;
+  const long long n_first = ijkl ? o : v;
+  const size_t nt = (size_t)o * o * v * v * sizeof(double);
+  const size_t nov = (size_t)P * o * v * sizeof(double);
+  const size_t nrow = (size_t)P * n_first * v * sizeof(double);
+  const size_t nz = (size_t)o * o * n_first * o * sizeof(double);
+  if (overlaps(Z, nz, t, nt) || overlaps(Z, nz, Lov, nov) || overlaps(Z, nz, Lrow, nrow))
+    return CC_LADDER_EINVAL;
+  if (precision == CC_LADDER_SPLIT_BF16 || (opts && opts->flags)) return CC_LADDER_EUNSUPPORTED;
+  rc = check_device();
+  if (rc) return rc;
+  Plan pl;
+  Scratch ws;
+  size_t budget;
+  if (opts && opts->workspace)
+    budget = opts->workspace_bytes;
+  else if (opts && opts->hbm_budget)
+    budget = opts->hbm_budget;
+  else
+    budget = default_budget();
+  if (!budget) return CC_LADDER_EHIP;
+  rc = make_plan_intermediate(which, o, v, P, precision, budget, opts, &pl);
+  if (rc) return rc;
+  rc = take_scratch(pl, stream, opts, &ws);
+  if (rc) return rc;
+  char* base = ws.base;
+  const Tracer tr(opts, stream);
+  const long long ld_row = n_first * v;
+  if (precision == CC_LADDER_FP64) {
+    if (!ijkl) {
+      double* tx = reinterpret_cast<double*>(base + pl.off_tx);
+      tr(CC_LADDER_PHASE_PREP, 0, 0);
+      rc = swap_cd(t, tx, o, v, stream);
+      tr(CC_LADDER_PHASE_PREP, 0, 1);
+      if (rc) return rc;
+      t = tx;
+    }
+    return intermediate_blocks<TrF64>(pl, Lrow, ld_row, Lov, t, Z,
+                                      reinterpret_cast<double*>(base + pl.off_V), tr, stream);
+  }
+  float* Lov32 = reinterpret_cast<float*>(base + pl.off_L);
+  float* Lrow32 = ijkl ? Lov32 : reinterpret_cast<float*>(base + pl.off_L2);
+  float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+  tr(CC_LADDER_PHASE_PREP, 0, 0);
+  rc = to_f32(Lov, Lov32, (size_t)P * o * v, stream);
+  if (!rc && !ijkl) rc = to_f32(Lrow, Lrow32, (size_t)P * v * v, stream);
+  if (!rc) rc = ijkl ? to_f32(t, t32, (size_t)o * o * v * v, stream) : swap_cd(t, t32, o, v, stream);
+  tr(CC_LADDER_PHASE_PREP, 0, 1);
+  if (rc) return rc;
+  return intermediate_blocks<TrF32>(pl, Lrow32, ld_row, Lov32, t32, Z,
+                                    reinterpret_cast<float*>(base + pl.off_V), tr, stream);
 }
 
 }  // namespace
@@ -558,6 +660,31 @@ extern "C" int cc_ladder_workspace_query(int o, int v, int P, int precision, int
   if (rc) return rc;
   *bytes = pl.bytes;
   *a_block = pl.n_a;
+  return CC_LADDER_OK;
+}
+
+extern "C" int cc_intermediate_ijkl(int o, int v, int P, const double* L_ov, const double* t,
+                                    double* X, int precision, hipStream_t stream,
+                                    const cc_ladder_opts* opts) {
+  return intermediate_call(CC_INTERMEDIATE_IJKL, o, v, P, L_ov, L_ov, t, X, precision, stream,
+                           opts);
+}
+
+extern "C" int cc_intermediate_ijbk(int o, int v, int P, const double* L, const double* L_ov,
+                                    const double* t, double* Y, int precision, hipStream_t stream,
+                                    const cc_ladder_opts* opts) {
+  return intermediate_call(CC_INTERMEDIATE_IJBK, o, v, P, L, L_ov, t, Y, precision, stream, opts);
+}
+
+extern "C" int cc_intermediate_workspace_query(int which, int o, int v, int P, int precision,
+                                               size_t hbm_budget, const cc_ladder_opts* opts,
+                                               size_t* bytes, int* block) {
+  if (!bytes || !block) return CC_LADDER_EINVAL;
+  Plan pl;
+  const int rc = make_plan_intermediate(which, o, v, P, precision, hbm_budget, opts, &pl);
+  if (rc) return rc;
+  *bytes = pl.bytes;
+  *block = pl.n_a;
   return CC_LADDER_OK;
 }
 

@@ -14,10 +14,12 @@
 //
 // Epilogues:
 //   EPI_ACC : C[m*ldc + n] += acc                         (float64 accumulation)
-//   EPI_PERM: m = (a, x), n = (y, d) with x, d < v:
-//             C[a*v^3 + y*v^2 + x*v + d] = acc            (stores, in the operand type, an
+//   EPI_PERM: m = (a, x), n = (y, d) with x, d < v and y < N/v:
+//             C[a*N*v + y*v^2 + x*v + d] = acc            (stores, in the operand type, an
 //                                                          integral-shaped block with its
-//                                                          middle indices swapped)
+//                                                          middle indices swapped; N = v^2
+//                                                          for the virtual-virtual build,
+//                                                          o*v for occupied columns)
 //   EPI_PACK: the build restricted to b >= a: m = (a - a0, c), n = (b - a0, d);
 //             C[(pair(a,b) - pair(a0,a0))*v^2 + c*v + d] = acc for b >= a, where
 //             pair(a,b) = prefix(a) + b - a numbers the rows a <= b (tiles wholly
@@ -164,7 +166,7 @@ __device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, co
     static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
   } else if (EPI == EPI_PERM) {
     const int a = m / g.v, x = m - a * g.v;
-    static_cast<T*>(g.C)[(long long)a * v * v * v + c.off + (long long)x * v] = static_cast<T>(val);
+    static_cast<T*>(g.C)[(long long)a * g.N * v + c.off + (long long)x * v] = static_cast<T>(val);
   } else if (EPI == EPI_PACK) {
     const int al = m / g.v, cc = m - al * g.v;
     if (c.x < al) return;

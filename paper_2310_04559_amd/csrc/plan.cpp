@@ -114,6 +114,49 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   return CC_LADDER_OK;
 }
 
+namespace {
+
+// Largest block of first indices (1..n_max) whose layout fits `budget`
+// (0 = unlimited), then equalised: the same block count with the smallest
+// block that achieves it.  `fixed` > 0 takes that block size as given.
+template <class Layout>
+int search_block(int n_max, size_t budget, int fixed, Layout layout, Plan* plan) {
+  int rc;
+  if (fixed > 0) {
+    rc = layout(fixed < n_max ? fixed : n_max, plan);
+    if (rc) return rc;
+    return (budget && plan->bytes > budget) ? CC_LADDER_ENOMEM : CC_LADDER_OK;
+  }
+  // the footprint grows monotonically with the block size
+  Plan best;
+  rc = layout(1, &best);
+  if (rc) return rc;
+  if (budget && best.bytes > budget) return CC_LADDER_ENOMEM;
+  int lo = 1, hi = n_max;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    Plan trial;
+    rc = layout(mid, &trial);
+    if (rc) return rc;
+    if (!budget || trial.bytes <= budget) {
+      lo = mid;
+      best = trial;
+    } else {
+      hi = mid - 1;
+    }
+  }
+  const int nb = (n_max + best.n_a - 1) / best.n_a;
+  const int n_eq = (n_max + nb - 1) / nb;
+  if (n_eq != best.n_a) {
+    rc = layout(n_eq, &best);
+    if (rc) return rc;
+  }
+  *plan = best;
+  return CC_LADDER_OK;
+}
+
+}  // namespace
+
 int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
               const cc_ladder_opts* opts, Plan* plan) {
   int rc = check_dims(o, v, P);
@@ -124,39 +167,64 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   const int depth = opts ? opts->split_depth : 0;
   const unsigned flags = opts ? opts->flags : 0u;
   const int k_chunk = opts ? opts->k_chunk : 0;
-  if (opts && opts->a_block > 0) {
-    const int n_a = opts->a_block < v ? opts->a_block : v;
-    rc = layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, flags, plan);
-    if (rc) return rc;
-    return (budget && plan->bytes > budget) ? CC_LADDER_ENOMEM : CC_LADDER_OK;
+  return search_block(v, budget, opts ? opts->a_block : 0, [&](int n_a, Plan* p) {
+    return layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, flags, p);
+  }, plan);
+}
+
+int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, int k_chunk,
+                        Plan* plan) {
+  const int n_first = which == CC_INTERMEDIATE_IJKL ? o : v;
+  if (n_p < 1 || n_p > n_first) return CC_LADDER_EINVAL;
+  Plan p;
+  p.o = o; p.v = v; p.P = P;
+  p.precision = precision;
+  p.op = which == CC_INTERMEDIATE_IJKL ? kOpIjkl : kOpIjbk;
+  p.n_a = n_p;
+  p.nblocks = (n_first + n_p - 1) / n_p;
+  const size_t v2 = static_cast<size_t>(v) * v;
+  const size_t o2 = static_cast<size_t>(o) * o;
+  const size_t ov = static_cast<size_t>(o) * v;
+  const size_t blk = static_cast<size_t>(n_p) * o * v2;  // block rows (p, y), y occupied
+  size_t cur = 0;
+  switch (precision) {
+    case CC_LADDER_FP64:
+      // (bd|kc) is built with its last two indices in (d, c) order and met by
+      // the amplitudes with c, d swapped
+      if (p.op == kOpIjbk) p.off_tx = take(&cur, o2 * v2 * sizeof(double));
+      p.off_V = take(&cur, blk * sizeof(double));
+      break;
+    case CC_LADDER_FP32:
+      p.k_chunk = k_chunk ? k_chunk : 512;
+      p.off_L = take(&cur, static_cast<size_t>(P) * ov * sizeof(float));          // L_ov
+      if (p.op == kOpIjbk) p.off_L2 = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
+      p.off_t = take(&cur, o2 * v2 * sizeof(float));
+      p.off_V = take(&cur, blk * sizeof(float));
+      break;
+    case CC_LADDER_SPLIT_BF16:
+      return CC_LADDER_EUNSUPPORTED;
+    default:
+      return CC_LADDER_EINVAL;
   }
-  // Largest block that fits: the footprint grows monotonically with n_a.
-  Plan best;
-  rc = layout_plan(o, v, P, precision, backward, 1, slices, depth, k_chunk, flags, &best);
-  if (rc) return rc;
-  if (budget && best.bytes > budget) return CC_LADDER_ENOMEM;
-  int lo = 1, hi = v;
-  while (lo < hi) {
-    const int mid = lo + (hi - lo + 1) / 2;
-    Plan trial;
-    rc = layout_plan(o, v, P, precision, backward, mid, slices, depth, k_chunk, flags, &trial);
-    if (rc) return rc;
-    if (!budget || trial.bytes <= budget) {
-      lo = mid;
-      best = trial;
-    } else {
-      hi = mid - 1;
-    }
-  }
-  // Equalise the blocks: same block count, smallest n_a that achieves it.
-  const int nb = (v + best.n_a - 1) / best.n_a;
-  const int n_eq = (v + nb - 1) / nb;
-  if (n_eq != best.n_a) {
-    rc = layout_plan(o, v, P, precision, backward, n_eq, slices, depth, k_chunk, flags, &best);
-    if (rc) return rc;
-  }
-  *plan = best;
+  p.bytes = cur;
+  *plan = p;
   return CC_LADDER_OK;
+}
+
+int make_plan_intermediate(int which, int o, int v, int P, int precision, size_t budget,
+                           const cc_ladder_opts* opts, Plan* plan) {
+  if (which != CC_INTERMEDIATE_IJKL && which != CC_INTERMEDIATE_IJBK) return CC_LADDER_EINVAL;
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  // the packed and exchange variants belong to the ladder term only
+  if (opts && opts->flags) return CC_LADDER_EUNSUPPORTED;
+  const int k_chunk = opts ? opts->k_chunk : 0;
+  const int n_first = which == CC_INTERMEDIATE_IJKL ? o : v;
+  return search_block(n_first, budget, opts ? opts->a_block : 0, [&](int n_p, Plan* p) {
+    return layout_intermediate(which, o, v, P, precision, n_p, k_chunk, p);
+  }, plan);
 }
 
 }  // namespace ccl

@@ -12,13 +12,17 @@
 
 namespace ccl {
 
+// Operation a plan is made for.
+enum { kOpLadder = 0, kOpIjkl = 1, kOpIjbk = 2 };
+
 // Scratch buffers of one call, as byte offsets into a single workspace.
 struct Plan {
+  int op = kOpLadder;
   int o = 0, v = 0, P = 0;
   int precision = 0;
   int backward = 0;
-  int n_a = 0;          // virtuals per integral block
-  int nblocks = 0;      // ceil(v / n_a)
+  int n_a = 0;          // first indices per integral block (virtuals; occupied for ijkl)
+  int nblocks = 0;      // ceil(v / n_a) (ceil(o / n_a) for ijkl)
   int slices = 0;       // split-bf16 slice count (0 for the other forms)
   int split_depth = 0;  // split-bf16 anti-diagonals kept beyond the slice triangle (1 or 2)
   int pairsym = 0;      // forward over packed integral rows a <= b (pair-symmetric amplitudes)
@@ -28,6 +32,7 @@ struct Plan {
   int k_chunk = 0;      // float32 drain interval along the contracted index
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;
+  size_t off_L2 = 0;    // intermediate ijbk, FP32: the virtual-virtual vectors (off_L: L_ov)
   size_t off_Lexp = 0, off_texp = 0, off_lamexp = 0;
   // per-block buffers
   size_t off_V = 0;     // float64 or float32 integral block [n_a][v][v][v]
@@ -51,6 +56,15 @@ inline long long pair_prefix(long long a, long long v) { return a * v - a * (a -
 // (budget 0 = unlimited).  Returns 0, CC_LADDER_EINVAL or CC_LADDER_ENOMEM.
 int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
               const cc_ladder_opts* opts, Plan* plan);
+
+// The occupied intermediates (eqs. vfunction3/vfunction4): blocks of n_p first
+// indices (occupied k for ijkl, virtual b for ijbk), integral block
+// [n_p][o][v][v].  Same search and return codes as make_plan; flags are
+// CC_LADDER_EUNSUPPORTED, SPLIT_BF16 too.
+int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, int k_chunk,
+                        Plan* plan);
+int make_plan_intermediate(int which, int o, int v, int P, int precision, size_t budget,
+                           const cc_ladder_opts* opts, Plan* plan);
 
 // Forwards phase boundaries to the caller's optional trace hook.
 struct Tracer {

@@ -29,7 +29,8 @@ CC_LADDER_EHIP = -4
 CC_LADDER_EUNSUPPORTED = -5
 
 EXPORTS = ("cc_ladder_residual", "cc_ladder_backward", "cc_ladder_reduce",
-           "cc_ladder_workspace_query", "cc_ladder_strerror")
+           "cc_ladder_workspace_query", "cc_ladder_strerror", "cc_intermediate_ijkl",
+           "cc_intermediate_ijbk", "cc_intermediate_workspace_query")
 
 
 class CcLadderOpts(ctypes.Structure):
@@ -50,6 +51,9 @@ class CcLadderOpts(ctypes.Structure):
 
 CC_LADDER_PAIR_SYMMETRIC = 1
 CC_LADDER_EXCHANGE = 2
+CC_INTERMEDIATE_IJKL = 0
+CC_INTERMEDIATE_IJBK = 1
+INTERMEDIATES = {"ijkl": CC_INTERMEDIATE_IJKL, "ijbk": CC_INTERMEDIATE_IJBK}
 
 
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -85,6 +89,13 @@ def load():
     lib.cc_ladder_workspace_query.argtypes = [i, i, i, i, i, st, opts_p,
                                               ctypes.POINTER(st), ctypes.POINTER(i)]
     lib.cc_ladder_workspace_query.restype = i
+    lib.cc_intermediate_ijkl.argtypes = [i, i, i, p, p, p, i, p, opts_p]
+    lib.cc_intermediate_ijkl.restype = i
+    lib.cc_intermediate_ijbk.argtypes = [i, i, i, p, p, p, p, i, p, opts_p]
+    lib.cc_intermediate_ijbk.restype = i
+    lib.cc_intermediate_workspace_query.argtypes = [i, i, i, i, i, st, opts_p,
+                                                    ctypes.POINTER(st), ctypes.POINTER(i)]
+    lib.cc_intermediate_workspace_query.restype = i
     lib.cc_ladder_strerror.argtypes = [i]
     lib.cc_ladder_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -210,6 +221,49 @@ def cc_ladder_workspace_query(o: int, v: int, P: int, precision=0, backward: boo
                                        ctypes.byref(a_block))
     _check(rc, "cc_ladder_workspace_query")
     return nbytes.value, a_block.value
+
+
+def cc_intermediate_ijkl(L_ov: torch.Tensor, t: torch.Tensor, X: torch.Tensor, precision=0,
+                         stream=None, opts: Optional[CcLadderOpts] = None) -> torch.Tensor:
+    """X[i,j,k,l] += sum_cd (sum_x L_ov[x,k,c] L_ov[x,l,d]) t[i,j,c,d]; returns X."""
+    lib = load()
+    P, o, v = L_ov.shape
+    args = (_dev_f64(L_ov, "L_ov", (P, o, v)), _dev_f64(t, "t", (o, o, v, v)),
+            _dev_f64(X, "X", (o, o, o, o)))
+    with torch.cuda.device(X.device):
+        rc = lib.cc_intermediate_ijkl(o, v, P, *args, _prec(precision),
+                                      _stream(X.device, stream), _opts_ref(opts))
+    _check(rc, "cc_intermediate_ijkl")
+    return X
+
+
+def cc_intermediate_ijbk(L: torch.Tensor, L_ov: torch.Tensor, t: torch.Tensor, Y: torch.Tensor,
+                         precision=0, stream=None,
+                         opts: Optional[CcLadderOpts] = None) -> torch.Tensor:
+    """Y[i,j,b,k] += sum_cd (sum_x L[x,b,d] L_ov[x,k,c]) t[i,j,c,d]; returns Y."""
+    lib = load()
+    P, o, v = L_ov.shape
+    args = (_dev_f64(L, "L", (P, v, v)), _dev_f64(L_ov, "L_ov", (P, o, v)),
+            _dev_f64(t, "t", (o, o, v, v)), _dev_f64(Y, "Y", (o, o, v, o)))
+    with torch.cuda.device(Y.device):
+        rc = lib.cc_intermediate_ijbk(o, v, P, *args, _prec(precision),
+                                      _stream(Y.device, stream), _opts_ref(opts))
+    _check(rc, "cc_intermediate_ijbk")
+    return Y
+
+
+def cc_intermediate_workspace_query(which, o: int, v: int, P: int, precision=0,
+                                    hbm_budget: int = 0, opts: Optional[CcLadderOpts] = None):
+    """(scratch bytes, first indices per block) for an intermediate; needs no device."""
+    lib = load()
+    w = INTERMEDIATES[which] if isinstance(which, str) else int(which)
+    nbytes = ctypes.c_size_t(0)
+    block = ctypes.c_int(0)
+    rc = lib.cc_intermediate_workspace_query(w, int(o), int(v), int(P), _prec(precision),
+                                             int(hbm_budget), _opts_ref(opts), ctypes.byref(nbytes),
+                                             ctypes.byref(block))
+    _check(rc, "cc_intermediate_workspace_query")
+    return nbytes.value, block.value
 
 
 def cc_ladder_strerror(code: int) -> str:

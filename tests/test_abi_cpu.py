@@ -21,7 +21,7 @@ def native():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cc_ladder_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cc_(?:ladder|intermediate)_\w+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol(native):
@@ -112,6 +112,37 @@ def test_planner_exchange_footprint(native):
     assert native.cc_ladder_workspace_query(o, v, P, "fp64", opts=both)[0] == ps + t64
 
 
+def test_planner_intermediate_footprints(native):
+    # integral block [n_p][o][v][v] over first indices p (occupied k for ijkl,
+    # virtual b for ijbk); ijbk also holds the swapped amplitudes (float64)
+    o, v, P = 4, 30, 50
+    rnd = lambda b: (b + 255) // 256 * 256
+    b, n = native.cc_intermediate_workspace_query("ijkl", o, v, P, "fp64")
+    assert n == o and b == rnd(o * o * v * v * 8)
+    b, n = native.cc_intermediate_workspace_query("ijbk", o, v, P, "fp64")
+    assert n == v and b == rnd(o * o * v * v * 8) + rnd(v * o * v * v * 8)
+    b, n = native.cc_intermediate_workspace_query("ijkl", o, v, P, "fp32")
+    assert n == o and b == rnd(P * o * v * 4) + rnd(o * o * v * v * 4) + rnd(o * o * v * v * 4)
+    b, n = native.cc_intermediate_workspace_query("ijbk", o, v, P, "fp32")
+    assert n == v and b == (rnd(P * o * v * 4) + rnd(P * v * v * 4) + rnd(o * o * v * v * 4)
+                            + rnd(v * o * v * v * 4))
+    # budget: 7 virtuals' blocks fit, equalised to ceil(30 / ceil(30/7)) = 6
+    per_b = o * v * v * 8
+    b, n = native.cc_intermediate_workspace_query("ijbk", o, v, P, "fp64",
+                                                   hbm_budget=rnd(o * o * v * v * 8) + 7 * per_b)
+    assert n == 6
+    b, n = native.cc_intermediate_workspace_query("ijkl", o, v, P, "fp64", opts=native.make_opts(a_block=3))
+    assert n == 3 and b == rnd(3 * o * v * v * 8)
+    for kw, prec in ((dict(), "split_bf16"), (dict(exchange=True), "fp64"),
+                     (dict(pair_symmetric=True), "fp32")):
+        with pytest.raises(native.LadderError) as e:
+            native.cc_intermediate_workspace_query("ijkl", o, v, P, prec, opts=native.make_opts(**kw))
+        assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+    with pytest.raises(native.LadderError) as e:
+        native.cc_intermediate_workspace_query(2, o, v, P, "fp64")
+    assert e.value.code == native.CC_LADDER_EINVAL
+
+
 def test_planner_explicit_block_and_enomem(native):
     opts = native.make_opts(a_block=7)
     nbytes, n_a = native.cc_ladder_workspace_query(5, 20, 75, "fp64", opts=opts)
@@ -157,6 +188,18 @@ def test_argument_checks_precede_device_checks(native):
     assert lib.cc_ladder_reduce(2, 4, None, 1 << 20, 1 << 24, None) == native.CC_LADDER_EINVAL
 
 
+def test_intermediate_argument_checks_precede_device_checks(native):
+    lib = native.load()
+    # null pointers and an output overlapping an input are host-side errors
+    assert lib.cc_intermediate_ijkl(2, 4, 2, None, 1 << 24, 1 << 26, 0, None, None) == native.CC_LADDER_EINVAL
+    t = 1 << 24
+    assert lib.cc_intermediate_ijkl(2, 4, 2, 1 << 28, t, t + 64, 0, None, None) == native.CC_LADDER_EINVAL
+    assert lib.cc_intermediate_ijbk(2, 4, 2, 1 << 28, 1 << 30, t, t - 8, 0, None,
+                                    None) == native.CC_LADDER_EINVAL
+    assert lib.cc_intermediate_ijbk(0, 4, 2, 1 << 28, 1 << 30, t, 1 << 32, 0, None,
+                                    None) == native.CC_LADDER_EINVAL
+
+
 def test_no_device_is_reported(native):
     import torch
 
@@ -166,3 +209,7 @@ def test_no_device_is_reported(native):
     rc = lib.cc_ladder_residual(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None, None)
     assert rc == native.CC_LADDER_ENODEV
     assert lib.cc_ladder_reduce(2, 4, 1 << 24, 1 << 26, 1 << 28, None) == native.CC_LADDER_ENODEV
+    assert lib.cc_intermediate_ijkl(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None,
+                                    None) == native.CC_LADDER_ENODEV
+    assert lib.cc_intermediate_ijbk(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 1 << 30, 1, None,
+                                    None) == native.CC_LADDER_ENODEV
