@@ -144,7 +144,7 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
                        g.tiles_n, v);
     grid = dim3(static_cast<unsigned>(needed));
   }
-  if (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
+  if constexpr (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
     int rc = CC_LADDER_OK;
     if (launch_kc_direct<Tr, EPI>(g, stream, &rc)) return rc;
   }
@@ -153,6 +153,58 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
     hipLaunchKernelGGL((gemm_kernel<Tr, LA, LB, EPI, true>), grid, block, 0, stream, g);
   else
     hipLaunchKernelGGL((gemm_kernel<Tr, LA, LB, EPI, false>), grid, block, 0, stream, g);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+// C[m*ldc + n] += sum_s part[s*stride + m*N + n], the split partials summed in
+// order of s (the same order for every element, whatever the tiling).
+__global__ __launch_bounds__(256) void part_reduce_kernel(const double* __restrict__ part, int S,
+                                                          long long stride, int N, long long MN,
+                                                          double* __restrict__ C, long long ldc) {
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += step) {
+    double acc = part[e];
+    for (int q = 1; q < S; ++q) acc += part[q * stride + e];
+    const long long m = e / N;
+    C[m * ldc + (e - m * N)] += acc;
+  }
+}
+
+// C[m*ldc + n] += sum_k A[m*lda + k] B[n*ldb + k] with K cut into `splits`
+// ranges of whole K-steps, one workgroup per (tile, range), float64 partials in
+// `part` (splits * M * N) and an ordered reduction.  For products whose tile grid
+// alone leaves compute units idle (small M x N, long K).  Falls back to the plain
+// product when there is one range or the operands do not suit the direct kernel.
+template <class Tr>
+int launch_contract_split(const typename Tr::T* A, long long lda, const typename Tr::T* B,
+                          long long ldb, double* C, long long ldc, int M, int N, int K, int splits,
+                          double* part, int drain_steps, hipStream_t stream) {
+  if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
+  if (splits <= 1 || !part || !vec_ok(A, lda) || !vec_ok(B, ldb))
+    return launch_gemm<Tr, KC, KC, EPI_ACC>(A, lda, B, ldb, C, ldc, M, N, K, 0, drain_steps, stream);
+  GemmArgs<typename Tr::T> g;
+  g.A = A; g.lda = lda;
+  g.B = B; g.ldb = ldb;
+  g.C = part; g.ldc = N;
+  g.M = M; g.N = N; g.K = K;
+  g.v = 0; g.o = 0; g.a0 = 0; g.row_tiles = nullptr;
+  g.tiles_m = (M + kDBM - 1) / kDBM;
+  g.tiles_n = (N + kDBN - 1) / kDBN;
+  g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
+  g.drain_steps = drain_steps > 0 ? drain_steps : 1;
+  const int bk = kDRow / static_cast<int>(sizeof(typename Tr::T));
+  const int nk = (K + bk - 1) / bk;
+  g.split_steps = (nk + splits - 1) / splits;
+  const int S = (nk + g.split_steps - 1) / g.split_steps;  // non-empty ranges
+  g.part_stride = (long long)M * N;
+  const long long grid = (long long)g.tiles_m * g.tiles_n * S;
+  if (grid > 0x7fffffffLL) return CC_LADDER_EINVAL;
+  hipLaunchKernelGGL((gemm_kc_direct_kernel<Tr, EPI_PART>), dim3(static_cast<unsigned>(grid)),
+                     dim3(kDThreads), 0, stream, g);
+  const long long MN = (long long)M * N;
+  const long long blocks = std::min<long long>((MN + 255) / 256, 4096);
+  hipLaunchKernelGGL(part_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                     static_cast<const double*>(part), S, g.part_stride, N, MN, C, ldc);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -423,7 +475,7 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
 template <class Tr>
 int intermediate_blocks(const Plan& pl, const typename Tr::T* Lrow, long long ld_row,
                         const typename Tr::T* Lov, const typename Tr::T* t, double* Z,
-                        typename Tr::T* V, const Tracer& tr, hipStream_t s) {
+                        typename Tr::T* V, double* part, const Tracer& tr, hipStream_t s) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int n_first = pl.op == kOpIjkl ? o : v;
@@ -438,8 +490,8 @@ int intermediate_blocks(const Plan& pl, const typename Tr::T* Lrow, long long ld
     tr(CC_LADDER_PHASE_BUILD, blk, 1);
     if (rc) return rc;
     tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
-    rc = launch_gemm<Tr, KC, KC, EPI_ACC>(t, v2, V, v2, Z + (long long)p0 * o, ld_out, o * o,
-                                          np * o, static_cast<int>(v2), v, drain, s);
+    rc = launch_contract_split<Tr>(t, v2, V, v2, Z + (long long)p0 * o, ld_out, o * o, np * o,
+                                   static_cast<int>(v2), pl.k_splits, part, drain, s);
     tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
     if (rc) return rc;
   }
@@ -483,6 +535,7 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
   char* base = ws.base;
   const Tracer tr(opts, stream);
   const long long ld_row = n_first * v;
+  double* part = pl.k_splits > 1 ? reinterpret_cast<double*>(base + pl.off_part) : nullptr;
   if (precision == CC_LADDER_FP64) {
     if (!ijkl) {
       double* tx = reinterpret_cast<double*>(base + pl.off_tx);
@@ -493,7 +546,7 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
       t = tx;
     }
     return intermediate_blocks<TrF64>(pl, Lrow, ld_row, Lov, t, Z,
-                                      reinterpret_cast<double*>(base + pl.off_V), tr, stream);
+                                      reinterpret_cast<double*>(base + pl.off_V), part, tr, stream);
   }
   float* Lov32 = reinterpret_cast<float*>(base + pl.off_L);
   float* Lrow32 = ijkl ? Lov32 : reinterpret_cast<float*>(base + pl.off_L2);
@@ -505,7 +558,7 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
   tr(CC_LADDER_PHASE_PREP, 0, 1);
   if (rc) return rc;
   return intermediate_blocks<TrF32>(pl, Lrow32, ld_row, Lov32, t32, Z,
-                                    reinterpret_cast<float*>(base + pl.off_V), tr, stream);
+                                    reinterpret_cast<float*>(base + pl.off_V), part, tr, stream);
 }
 
 }  // namespace

@@ -26,6 +26,9 @@
 //             below the diagonal exit at once)
 //   EPI_PAIR: the contraction over packed rows: m = (i,j), n = pair(a,b) - pair(a0,a0);
 //             C[m*ldc + a*v + b] += acc and, for a != b, C[(j,i)*ldc + b*v + a] += acc
+//   EPI_PART: split K: workgroup s of a tile sums K-steps [s*split_steps, (s+1)*split_steps)
+//             and stores C[s*part_stride + m*ldc + n] = acc (float64 partials, summed
+//             in order of s by a separate pass)
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, 128x128 workgroup tile, each
 // wave owns a 64x64 sub-tile = 4x4 MFMA 16x16 blocks.  Global tiles are read
@@ -51,7 +54,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 enum { KC = 0, RC = 1 };
-enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3 };
+enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3, EPI_PART = 4 };
 
 // float64 operands on v_mfma_f64_16x16x4_f64.
 struct TrF64 {
@@ -102,6 +105,8 @@ struct GemmArgs {
   int group_m;       // tile-order swizzle: rows of tiles walked together
   int drain_steps;   // K-steps between float32 -> float64 drains (TrF32)
   const int* row_tiles;  // EPI_PACK compact grid: first linear tile of each tile row
+  int split_steps;       // EPI_PART: K-steps per split
+  long long part_stride; // EPI_PART: elements between consecutive splits' partials
 };
 
 // First needed tile column of tile row tm in the packed build: columns whose
@@ -164,6 +169,8 @@ __device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, co
   const long long v = g.v;
   if (EPI == EPI_ACC) {
     static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
+  } else if (EPI == EPI_PART) {
+    static_cast<double*>(g.C)[(long long)m * g.ldc + n] = val;
   } else if (EPI == EPI_PERM) {
     const int a = m / g.v, x = m - a * g.v;
     static_cast<T*>(g.C)[(long long)a * g.N * v + c.off + (long long)x * v] = static_cast<T>(val);
@@ -283,17 +290,29 @@ struct TileIO {
 // round-robin; the remap gives each XCD a contiguous range of logical tiles so
 // that co-resident tiles share operand panels in that XCD's L2.  Logical tiles
 // are walked in bands of group_m tile rows.
-__device__ inline void tile_of(int bid, int nwg, int tiles_m, int group_m, int& tm, int& tn) {
+// Dispatch order -> linear work index: workgroups are handed to the 8 XCDs
+// round-robin, so consecutive indices of one XCD get consecutive ids.
+__device__ inline int xcd_linear(int bid, int nwg) {
   const int per = nwg / 8, extra = nwg % 8;
   const int xcd = bid % 8, local = bid / 8;
-  const int id = xcd * per + (xcd < extra ? xcd : extra) + local;
-  const int band = group_m * (nwg / tiles_m);  // tiles in one band (tiles_n tiles per row)
+  return xcd * per + (xcd < extra ? xcd : extra) + local;
+}
+
+// Linear tile id -> (tile row, tile column), walking bands of group_m tile rows
+// column by column so that co-resident tiles share row and column panels.
+__device__ inline void tile_from_linear(int id, int ntiles, int tiles_m, int group_m, int& tm,
+                                        int& tn) {
+  const int band = group_m * (ntiles / tiles_m);  // tiles in one band (tiles_n tiles per row)
   const int b = id / band;
   const int first = b * group_m;
   const int rows = (tiles_m - first) < group_m ? (tiles_m - first) : group_m;
   const int in = id - b * band;
   tm = first + in % rows;
   tn = in / rows;
+}
+
+__device__ inline void tile_of(int bid, int nwg, int tiles_m, int group_m, int& tm, int& tn) {
+  tile_from_linear(xcd_linear(bid, nwg), nwg, tiles_m, group_m, tm, tn);
 }
 
 // K loop of one tile.  FAST: the tile lies inside M x N and its operands are

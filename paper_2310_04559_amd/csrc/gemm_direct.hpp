@@ -1,6 +1,7 @@
 // Amplitude-contraction GEMM with direct global->LDS operand loads (gfx950).
 //
-//   C[m][n] (+)= sum_k A[m*lda + k] B[n*ldb + k]          (both operands KC; EPI_ACC or EPI_PAIR)
+//   C[m][n] (+)= sum_k A[m*lda + k] B[n*ldb + k]   (both operands KC; EPI_ACC, EPI_PAIR,
+//                                                   or EPI_PART: one K-range per workgroup)
 //
 // 512 threads = 8 wave64s in a 2 x 4 grid over a 128 x 256 tile; each wave owns
 // 64 x 64 = 4 x 4 MFMA blocks (v_mfma_f64_16x16x4_f64 or v_mfma_f32_16x16x4_f32).
@@ -41,6 +42,7 @@ __device__ __forceinline__ void d_wait_vm(int n) {
 
 template <class Tr, int EPI>
 __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<typename Tr::T> g) {
+  static_assert(EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PART, "K-contiguous epilogues");
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using Chunk = typename Tr::Chunk;
@@ -58,7 +60,20 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
   const int wm = (wave >> 2) * 64;
   const int wn = (wave & 3) * 64;
   int tm, tn;
-  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  const int nk_all = (g.K + BK - 1) / BK;
+  int ks0 = 0, ks1 = nk_all;  // K-steps of this workgroup
+  if (EPI == EPI_PART) {
+    // grid = tiles x splits; the split is the outer index of the linear id
+    const int ntiles = g.tiles_m * g.tiles_n;
+    const int id = xcd_linear(blockIdx.x, gridDim.x);
+    const int split = id / ntiles;
+    tile_from_linear(id - split * ntiles, ntiles, g.tiles_m, g.group_m, tm, tn);
+    ks0 = split * g.split_steps;
+    ks1 = ks0 + g.split_steps < nk_all ? ks0 + g.split_steps : nk_all;
+    g.C = static_cast<double*>(g.C) + split * g.part_stride;
+  } else {
+    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  }
   const int m0 = tm * kDBM, n0 = tn * kDBN;
 
   // Slabs: A rows 8*(wave + 8*j), j < 2; B rows 8*(wave + 8*j), j < 4.  The
@@ -126,22 +141,23 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
   // of 16, so the row's swizzle is ((lane & 15) >> 1)), logical chunk 4*gi + lane/16
   const int frow = (lane & 15) * kDRow;
   const int fsw = (lane & 15) >> 1;
-  const int nk = (g.K + BK - 1) / BK;
-  const int nkf = g.K / BK;
+  const int nk = ks1;        // one past this workgroup's last K-step
+  const int nkf = g.K / BK;  // full K-steps; a ragged last one goes through registers
   auto stage_in = [&](int kt) {
     if (kt < nkf)
       issue(kt);
     else
       issue_tail(kt);
   };
-  stage_in(0);
-  if (nk > 1) stage_in(1);
-  for (int k0 = 0; k0 < nk;) {
+  if (ks0 < nk) stage_in(ks0);
+  if (ks0 + 1 < nk) stage_in(ks0 + 1);
+  for (int k0 = ks0; k0 < nk;) {
     const int kend = (Tr::kDrain && k0 + g.drain_steps < nk) ? k0 + g.drain_steps : nk;
     for (int kt = k0; kt < kend; ++kt) {
       // step kt's direct loads have landed once only step kt+1's remain in flight
-      // (a ragged step kt+1 goes through registers and is already complete)
-      d_wait_vm(kt + 1 < nkf ? LOADS : 0);
+      // (a ragged step kt+1 goes through registers and is already complete, and
+      // past this workgroup's range nothing more was issued)
+      d_wait_vm(kt + 1 < nkf && kt + 1 < nk ? LOADS : 0);
       __builtin_amdgcn_s_barrier();
       if (kt + 2 < nk) stage_in(kt + 2);
       const unsigned char* st = lds + (kt % kDStages) * STAGE;

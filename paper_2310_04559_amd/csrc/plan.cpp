@@ -172,6 +172,25 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   }, plan);
 }
 
+int choose_k_splits(long long M, long long N, long long K, int bk) {
+  constexpr long long kCUs = 256;           // compute units of one MI355X
+  constexpr long long kTM = 128, kTN = 256;  // the K-contiguous kernel's tile
+  const long long tiles = ((M + kTM - 1) / kTM) * ((N + kTN - 1) / kTN);
+  const long long nk = (K + bk - 1) / bk;
+  if (tiles <= 0 || tiles >= kCUs) return 1;
+  int best = 1;
+  double best_cost = 1.0;  // waves per unit of work without a split
+  for (int s = 2; s <= 16; ++s) {
+    if (nk / s < 64) break;
+    const double cost = static_cast<double>((tiles * s + kCUs - 1) / kCUs) / s;
+    if (cost < best_cost * 0.999) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, int k_chunk,
                         Plan* plan) {
   const int n_first = which == CC_INTERMEDIATE_IJKL ? o : v;
@@ -206,6 +225,12 @@ int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, 
     default:
       return CC_LADDER_EINVAL;
   }
+  // split K from the whole output's tile count, so every block sums in the
+  // same order whatever n_p is
+  p.k_splits = choose_k_splits(static_cast<long long>(o2), static_cast<long long>(n_first) * o,
+                               static_cast<long long>(v2), precision == CC_LADDER_FP64 ? 16 : 32);
+  if (p.k_splits > 1)
+    p.off_part = take(&cur, static_cast<size_t>(p.k_splits) * o2 * n_p * o * sizeof(double));
   p.bytes = cur;
   *plan = p;
   return CC_LADDER_OK;

@@ -33,6 +33,9 @@ struct Plan {
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;
   size_t off_L2 = 0;    // intermediate ijbk, FP32: the virtual-virtual vectors (off_L: L_ov)
+  int k_splits = 1;     // intermediates: K ranges of the contraction (split K when its tile
+                        // grid alone leaves compute units idle)
+  size_t off_part = 0;  // float64 partials of the split contraction [k_splits][o^2][n_a*o]
   size_t off_Lexp = 0, off_texp = 0, off_lamexp = 0;
   // per-block buffers
   size_t off_V = 0;     // float64 or float32 integral block [n_a][v][v][v]
@@ -61,6 +64,11 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
 // indices (occupied k for ijkl, virtual b for ijbk), integral block
 // [n_p][o][v][v].  Same search and return codes as make_plan; flags are
 // CC_LADDER_EUNSUPPORTED, SPLIT_BF16 too.
+// K ranges for a K-contiguous product of M x N (tiles of 128 x 256) over K
+// elements in steps of `bk`: 1 when the tiles fill the chip, otherwise the count
+// that minimises the waves per unit of work (at least 64 K-steps per range).
+int choose_k_splits(long long M, long long N, long long K, int bk);
+
 int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, int k_chunk,
                         Plan* plan);
 int make_plan_intermediate(int which, int o, int v, int P, int precision, size_t budget,

@@ -143,6 +143,43 @@ def test_planner_intermediate_footprints(native):
     assert e.value.code == native.CC_LADDER_EINVAL
 
 
+def _waves_per_work(tiles, s, cus=256):
+    return -(-tiles * s // cus) / s
+
+
+@pytest.mark.parametrize("o,v,P,which,prec", [(40, 360, 1200, "ijkl", "fp64"),
+                                              (20, 180, 600, "ijkl", "fp32"),
+                                              (16, 64, 200, "ijbk", "fp64"),
+                                              (40, 360, 1200, "ijbk", "fp64")])
+def test_planner_intermediate_split_partials(native, o, v, P, which, prec):
+    # the contraction's 128 x 256 tile grid over o^2 x (n_first*o); when it alone
+    # leaves the 256 compute units idle, K = v^2 is cut into S ranges (at least
+    # 64 K-steps each) that minimise waves per unit of work, with float64
+    # partials [S][o^2][n_p*o] in scratch
+    rnd = lambda b: (b + 255) // 256 * 256
+    n_first = o if which == "ijkl" else v
+    tiles = -(-o * o // 128) * -(-n_first * o // 256)
+    nk = -(-v * v // (16 if prec == "fp64" else 32))
+    S, best = 1, 1.0
+    if tiles < 256:
+        for s in range(2, 17):
+            if nk // s < 64:
+                break
+            if _waves_per_work(tiles, s) < best * 0.999:
+                S, best = s, _waves_per_work(tiles, s)
+    b, n = native.cc_intermediate_workspace_query(which, o, v, P, prec)
+    base, _ = native.cc_intermediate_workspace_query(which, o, v, P, prec,
+                                                      opts=native.make_opts(a_block=n))
+    assert b == base
+    esz = 8 if prec == "fp64" else 4
+    ops = (rnd(P * o * v * 4) + (rnd(P * v * v * 4) if which == "ijbk" else 0) + rnd(o * o * v * v * 4)
+           if prec == "fp32" else (rnd(o * o * v * v * 8) if which == "ijbk" else 0))
+    part = rnd(S * o * o * n * o * 8) if S > 1 else 0
+    assert b == ops + rnd(n * o * v * v * esz) + part
+    if (o, v, which) == (40, 360, "ijkl"):
+        assert S == 14  # 91 tiles: 14 ranges give 1274 workgroups in 5 waves
+
+
 def test_planner_explicit_block_and_enomem(native):
     opts = native.make_opts(a_block=7)
     nbytes, n_a = native.cc_ladder_workspace_query(5, 20, 75, "fp64", opts=opts)

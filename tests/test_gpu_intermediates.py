@@ -64,15 +64,19 @@ def test_intermediate_integer_inputs_exact(gpu_lib, which):
 
 
 @pytest.mark.parametrize("which", ["ijkl", "ijbk"])
-def test_intermediate_bitwise_independent_of_block_size(gpu_lib, which):
-    announce("intermediate-determinism", which)
-    o, v, P = 9, 37, 101
+@pytest.mark.parametrize("o,v,P", [(9, 37, 101), (16, 64, 200)])
+def test_intermediate_bitwise_independent_of_block_size(gpu_lib, which, o, v, P):
+    # (16, 64, 200) splits the contraction's K into ranges; the ranges depend on
+    # the whole output, not on the block, so every block sums in one order
+    announce("intermediate-determinism", which, o, v, P)
     L, t, _ = random_general(o, v, P, 12)
     Lov = random_ov(o, v, P, 13)
     z = np.zeros(out_shape(which, o, v))
-    ref = run(gpu_lib, which, L, Lov, t, z, 0)
-    for block in (1, 4, 7):
-        assert np.array_equal(run(gpu_lib, which, L, Lov, t, z, 0, a_block=block), ref)
+    for precision in (0, 1):
+        ref = run(gpu_lib, which, L, Lov, t, z, precision)
+        for block in (1, 4, 7):
+            got = run(gpu_lib, which, L, Lov, t, z, precision, a_block=block)
+            assert np.array_equal(got, ref), (precision, block)
 
 
 @pytest.mark.parametrize("which", ["ijkl", "ijbk"])
