@@ -21,6 +21,13 @@ What it computes (arXiv 2310.04559):
   eq. (vfunction4): ``Y[i,j,b,k] += sum_{c,d} (bd|kc) t[i,j,c,d]``, with the
   occupied-virtual vectors ``L_ov[x][k][c]`` in ``(kc|ld) = sum_x L_ov[x,k,c] L_ov[x,l,d]``
   and ``(bd|kc) = sum_x L[x,b,d] L_ov[x,k,c]``.
+* the hole-hole ladder that the paper's pCCD-LCCSD vector function also
+  offloads (Sec. "Comparison between CPU and GPU-accelerated
+  implementations", the contraction of order o^4 v^2):
+  ``R[i,j,a,b] += sum_{k,l} (ik|jl) t[k,l,a,b]`` with
+  ``(ik|jl) = sum_x L_oo[x,i,k] L_oo[x,j,l]``.  The paper gives only its
+  einsum subscript; reading its first operand the way the paper translates a
+  Cholesky operand ``abcd`` into ``xac,xbd`` gives this sum.
 
 Algorithm: the paper's loop over one virtual index (Sec. "Pythonic
 implementations of the CC vector function", the tensordot variant that keeps
@@ -29,8 +36,8 @@ the Cholesky vectors and contracted with the amplitudes.  Each step is one
 library matrix product in float64; there is no further blocking or fusion.
 
 Layouts: ``L[x][p][q]`` (the virtual-virtual block), ``L_ov[x][k][c]``,
-``t, R, lam[i][j][a][b]``, ``X[i][j][k][l]``, ``Y[i][j][b][k]``, all float64
-C-contiguous.
+``L_oo[x][i][k]``, ``t, R, lam[i][j][a][b]``, ``X[i][j][k][l]``,
+``Y[i][j][b][k]``, all float64 C-contiguous.
 """
 from __future__ import annotations
 
@@ -38,8 +45,9 @@ import numpy as np
 
 __all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_loss",
            "exchange_forward", "exchange_backward", "intermediate_ijkl", "intermediate_ijbk",
+           "hole_ladder",
            "reduce_dot", "eri_slice", "nominal_flops_forward", "nominal_flops_backward",
-           "nominal_flops_ijkl", "nominal_flops_ijbk"]
+           "nominal_flops_ijkl", "nominal_flops_ijbk", "nominal_flops_hole"]
 
 
 def _check(L, t):
@@ -177,6 +185,33 @@ def intermediate_ijbk(L, L_ov, t, Y=None, b_begin: int = 0, b_end=None) -> np.nd
     return Y
 
 
+def hole_ladder(L_oo, t, R=None, i_begin: int = 0, i_end=None) -> np.ndarray:
+    """``R[i,j,a,b] += sum_{k,l} (ik|jl) t[k,l,a,b]`` with
+    ``(ik|jl) = sum_x L_oo[x,i,k] L_oo[x,j,l]``; loop over the occupied ``i``,
+    building ``(ik|jl)`` for one ``i`` at a time.  ``[i_begin, i_end)``
+    restricts the loop (a bounded sample)."""
+    L_oo = np.asarray(L_oo, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    if L_oo.ndim != 3 or L_oo.shape[1] != L_oo.shape[2]:
+        raise ValueError("L_oo must be [P][o][o]")
+    if t.ndim != 4 or t.shape[0] != t.shape[1] or t.shape[2] != t.shape[3]:
+        raise ValueError("t must be [o][o][v][v]")
+    if t.shape[0] != L_oo.shape[1]:
+        raise ValueError("L_oo and t disagree on o")
+    P, o, _ = L_oo.shape
+    v = t.shape[2]
+    if R is None:
+        R = np.zeros((o, o, v, v))
+    i_end = o if i_end is None else i_end
+    T = t.reshape(o * o, v * v)                       # [(k,l)][(a,b)]
+    Lf = L_oo.reshape(P, o * o)
+    for i in range(i_begin, i_end):
+        G = (L_oo[:, i, :].T @ Lf).reshape(o, o, o)   # [k][j][l] = (ik|jl)
+        Gi = G.transpose(1, 0, 2).reshape(o, o * o)   # [j][(k,l)]
+        R[i] += (Gi @ T).reshape(o, v, v)
+    return R
+
+
 def ladder_backward(L, t, lam):
     """Entrywise gradients ``(dL, dt)`` of ``sum lam * R`` with R the ladder
     term; one pass over ``a`` as in the forward, V[a] rebuilt, not stored."""
@@ -246,6 +281,11 @@ def nominal_flops_ijkl(o: int, v: int, P: int) -> float:
 def nominal_flops_ijbk(o: int, v: int, P: int) -> float:
     """Integrals (bd|kc) (2 P o v^3) + contraction (2 o^3 v^3)."""
     return 2.0 * (P + o * o) * o * float(v) ** 3
+
+
+def nominal_flops_hole(o: int, v: int, P: int) -> float:
+    """Integrals (ik|jl) (2 P o^4) + contraction (2 o^4 v^2)."""
+    return 2.0 * (P + v * v) * float(o) ** 4
 
 
 def nominal_flops_backward(o: int, v: int, P: int) -> float:

@@ -20,8 +20,9 @@ stand in for it):
 4. ``(ia|jb) = sum_x L[x,i,o+a] L[x,j,o+b]`` and
    ``t[i,j,a,b] = (ia|jb) / (e_i + e_j - e_a - e_b)`` (MP2-like amplitudes;
    the denominator lies in [-10, -0.8], never zero).
-5. ``L_vv = L[:, o:, o:]`` (contiguous ``[P][v][v]``) and
-   ``L_ov = L[:, :o, o:]`` (contiguous ``[P][o][v]``, occupied first).
+5. ``L_vv = L[:, o:, o:]`` (contiguous ``[P][v][v]``),
+   ``L_ov = L[:, :o, o:]`` (contiguous ``[P][o][v]``, occupied first) and
+   ``L_oo = L[:, :o, :o]`` (contiguous ``[P][o][o]``).
 6. With ``with_lambda``: ``G = 1e-2 * rng.standard_normal((o, o, v, v))`` and
    ``lam = (G + G.transpose(1, 0, 3, 2)) / 2`` (pair-symmetric), drawn after
    everything above.
@@ -53,6 +54,7 @@ class LadderInputs:
     ovov: np.ndarray          # (ia|jb) stored as [i][j][a][b]
     lam: Optional[np.ndarray] = None  # [o][o][v][v]
     L_ov: Optional[np.ndarray] = None  # [P][o][v]
+    L_oo: Optional[np.ndarray] = None  # [P][o][o]
 
 
 # Workload shapes: (o, v, P).  c1 is the brute-force tier, c2 the first GPU
@@ -118,6 +120,7 @@ def make_inputs(o: int, v: int, P: int, seed: int, with_lambda: bool = False,
     t = ovov / D
     del D
     L_vv = np.ascontiguousarray(L[:, o:, o:])
+    L_oo = np.ascontiguousarray(L[:, :o, :o])
     del L
     lam = None
     if with_lambda:
@@ -125,7 +128,7 @@ def make_inputs(o: int, v: int, P: int, seed: int, with_lambda: bool = False,
         lam = 0.5 * (G + G.transpose(1, 0, 3, 2))
         lam = np.ascontiguousarray(lam)
     return LadderInputs(o=o, v=v, P=P, seed=seed, L_vv=L_vv, t=np.ascontiguousarray(t),
-                        e_occ=e_occ, e_vir=e_vir, ovov=ovov, lam=lam, L_ov=L_ov)
+                        e_occ=e_occ, e_vir=e_vir, ovov=ovov, lam=lam, L_ov=L_ov, L_oo=L_oo)
 
 
 def integer_inputs(o: int, v: int, P: int, seed: int, lo: int = -2, hi: int = 2):

@@ -497,3 +497,72 @@ def test_generator_ov_block_matches_full_vectors():
     inp = make_inputs(3, 5, 7, 1234)
     ovov = np.einsum("xia,xjb->ijab", inp.L_ov, inp.L_ov)
     assert rel_fro(ovov, inp.ovov) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# hole-hole ladder (the pCCD-LCCSD term of order o^4 v^2)
+# ---------------------------------------------------------------------------
+
+def _int_hole(Loo, t):
+    P, o = len(Loo), len(Loo[0])
+    v = len(t[0][0])
+    R = [[[[0] * v for _ in range(v)] for _ in range(o)] for _ in range(o)]
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        s = 0
+        for k, l in itertools.product(range(o), range(o)):
+            s += sum(Loo[x][i][k] * Loo[x][j][l] for x in range(P)) * t[k][l][a][b]
+        R[i][j][a][b] = s
+    return R
+
+
+@pytest.mark.parametrize("o,v,P,seed", [(2, 3, 2, 101), (3, 2, 3, 102), (4, 1, 2, 103)])
+def test_hole_ladder_equals_integer_bruteforce(o, v, P, seed):
+    _, t = integer_inputs(o, v, P, seed)
+    Loo = np.random.default_rng(seed + 1).integers(-2, 3, size=(P, o, o)).astype(np.float64)
+    exact = np.array(_int_hole(_to_int(Loo), _to_int(t)), dtype=np.float64)
+    assert np.array_equal(oracle.hole_ladder(Loo, t), exact)
+
+
+def test_hole_ladder_is_particle_ladder_with_index_roles_swapped():
+    # sum_kl (ik|jl) t[k,l,a,b]: the particle ladder of the array s[a,b,k,l] =
+    # t[k,l,a,b] with the occupied vectors in the integral's place
+    o, v, P = 5, 3, 7
+    rng = np.random.default_rng(104)
+    Loo = rng.standard_normal((P, o, o))
+    t = rng.standard_normal((o, o, v, v))
+    s = np.ascontiguousarray(t.transpose(2, 3, 0, 1))
+    ref = oracle.ladder_forward(Loo, s).transpose(2, 3, 0, 1)
+    assert rel_fro(oracle.hole_ladder(Loo, t), ref) < 1e-14
+
+
+def test_hole_ladder_closed_forms_and_ranges():
+    # L_oo[x,i,k] = u_x p_i q_k: R[i,j,a,b] = |u|^2 p_i p_j sum_kl q_k q_l t[k,l,a,b];
+    # a unit amplitude at (k0,l0) picks the column (i k0|j l0); sampled i
+    # ranges reproduce the full result
+    o, v, P = 4, 3, 5
+    rng = np.random.default_rng(105)
+    u, p, q = rng.standard_normal(P), rng.standard_normal(o), rng.standard_normal(o)
+    t = rng.standard_normal((o, o, v, v))
+    Loo = u[:, None, None] * p[None, :, None] * q[None, None, :]
+    qtq = np.tensordot(np.outer(q, q), t, axes=([0, 1], [0, 1]))   # [a][b]
+    R = (u @ u) * p[:, None, None, None] * p[None, :, None, None] * qtq[None, None]
+    assert rel_fro(oracle.hole_ladder(Loo, t), R) < 1e-14
+    Loo = rng.standard_normal((P, o, o))
+    e = np.zeros((o, o, v, v))
+    e[2, 1, :, :] = 1.0
+    got = oracle.hole_ladder(Loo, e)
+    for i, j in itertools.product(range(o), range(o)):
+        want = sum(Loo[x, i, 2] * Loo[x, j, 1] for x in range(P))
+        assert np.allclose(got[i, j], want, rtol=1e-13, atol=1e-14)
+    full = oracle.hole_ladder(Loo, t)
+    part = np.zeros_like(full)
+    for i0, i1 in ((0, 1), (1, 4)):
+        oracle.hole_ladder(Loo, t, part, i0, i1)
+    assert np.array_equal(part, full)
+
+
+def test_hole_ladder_pair_symmetry():
+    # (ik|jl) = (jl|ik): a pair-symmetric t gives a pair-symmetric result
+    inp = make_inputs(4, 6, 9, 106)
+    R = oracle.hole_ladder(inp.L_oo, inp.t)
+    assert rel_fro(R.transpose(1, 0, 3, 2), R) < 1e-15
