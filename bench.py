@@ -13,7 +13,7 @@ reported with their error against the float64 oracle.
 
 Also reported: the dominant kernel's roofline (HIP events recorded around its
 launches through the library's trace hook), the exchange partner, the
-occupied intermediates X[i,j,k,l] and Y[i,j,b,k] on the same workload's
+occupied intermediates X[i,j,k,l] and Y[i,j,b,k] and the hole-hole ladder on the same workload's
 vectors, the adjoint's throughput on the gradient workload (o=30, v=300,
 P=900), and the oracle timed on the host's cores over a bounded sample of the
 same workload.
@@ -318,10 +318,10 @@ def bench_large(native):
 
 
 def bench_intermediates(native, inp, steps, warmup, ws_bytes):
-    """The occupied intermediates (eqs. vfunction3/vfunction4) on the throughput
-    workload's own L_ov, L_vv and t: time per call with HIP events on the
-    call's stream, nominal TFLOP/s, and the error of sampled first-index
-    slices against the oracle."""
+    """The occupied intermediates (eqs. vfunction3/vfunction4) and the
+    hole-hole ladder on the throughput workload's own L_ov, L_oo, L_vv and t:
+    time per call with HIP events on the call's stream, nominal TFLOP/s, and
+    the error of sampled first-index slices against the oracle."""
     import numpy as np
     import torch
 
@@ -330,20 +330,27 @@ def bench_intermediates(native, inp, steps, warmup, ws_bytes):
     o, v, P = inp.o, inp.v, inp.P
     Ld = torch.from_numpy(inp.L_vv).cuda()
     Lovd = torch.from_numpy(inp.L_ov).cuda()
+    Lood = torch.from_numpy(inp.L_oo).cuda()
     td = torch.from_numpy(inp.t).cuda()
     stream = torch.cuda.current_stream()
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     res = {}
-    for which in ("ijkl", "ijbk"):
-        shape = (o, o, o, o) if which == "ijkl" else (o, o, v, o)
-        firsts = [0, o - 1] if which == "ijkl" else [0, v // 2, v - 1]
+    shapes = {"ijkl": (o, o, o, o), "ijbk": (o, o, v, o), "hole": (o, o, v, v)}
+    for which in ("ijkl", "ijbk", "hole"):
+        shape = shapes[which]
+        # sampled first indices: X[:, :, k, :], Y[:, :, b, :]; rows R[i] of the hole ladder
+        firsts = [0, v // 2, v - 1] if which == "ijbk" else [0, o - 1]
         ref = np.zeros(shape)
         for p in firsts:
             if which == "ijkl":
                 oracle.intermediate_ijkl(inp.L_ov, inp.t, ref, p, p + 1)
-            else:
+            elif which == "ijbk":
                 oracle.intermediate_ijbk(inp.L_vv, inp.L_ov, inp.t, ref, p, p + 1)
-        flops = (oracle.nominal_flops_ijkl if which == "ijkl" else oracle.nominal_flops_ijbk)(o, v, P)
+            else:
+                oracle.hole_ladder(inp.L_oo, inp.t, ref, p, p + 1)
+        pick = (lambda a: a[firsts]) if which == "hole" else (lambda a: a[:, :, firsts, :])
+        flops = {"ijkl": oracle.nominal_flops_ijkl, "ijbk": oracle.nominal_flops_ijbk,
+                 "hole": oracle.nominal_flops_hole}[which](o, v, P)
         Z = torch.zeros(shape, dtype=torch.float64, device="cuda")
         for prec_name in ("fp64", "fp32"):
             prec = native.PRECISIONS[prec_name]
@@ -354,14 +361,16 @@ def bench_intermediates(native, inp, steps, warmup, ws_bytes):
             def call():
                 if which == "ijkl":
                     native.cc_intermediate_ijkl(Lovd, td, Z, prec, opts=opts)
-                else:
+                elif which == "ijbk":
                     native.cc_intermediate_ijbk(Ld, Lovd, td, Z, prec, opts=opts)
+                else:
+                    native.cc_hole_ladder(Lood, td, Z, prec, opts=opts)
 
             Z.zero_()
             call()
             torch.cuda.synchronize()
-            got = Z.cpu().numpy()[:, :, firsts, :]
-            err = float(np.linalg.norm(got - ref[:, :, firsts, :]) / np.linalg.norm(ref[:, :, firsts, :]))
+            got = pick(Z.cpu().numpy())
+            err = float(np.linalg.norm(got - pick(ref)) / np.linalg.norm(pick(ref)))
             for _ in range(warmup):
                 call()
             torch.cuda.synchronize()
@@ -381,7 +390,7 @@ def bench_intermediates(native, inp, steps, warmup, ws_bytes):
             log(f"intermediate {which} {prec_name}: {ms:.2f} ms {r['tflops']:.1f} TFLOP/s "
                 f"err {err:.2e} block {block} phases {json.dumps(r['phases_ms_avg'])}")
         del Z
-    del ws, Ld, Lovd, td
+    del ws, Ld, Lovd, Lood, td
     return res
 
 

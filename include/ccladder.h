@@ -24,6 +24,7 @@
  *     t   [o][o][v][v]   t[i][j][c][d]
  *     R   [o][o][v][v]   R[i][j][a][b]
  *     L_ov [P][o][v]     occupied-virtual block of the Cholesky vectors, L_ov[x][k][c]
+ *     L_oo [P][o][o]     occupied-occupied block of the Cholesky vectors, L_oo[x][i][k]
  *     X   [o][o][o][o]   X[i][j][k][l]  (eq. vfunction3)
  *     Y   [o][o][v][o]   Y[i][j][b][k]  (eq. vfunction4)
  *   The caller owns all of them; the library never frees caller memory.
@@ -159,10 +160,12 @@ int cc_ladder_workspace_query(int o, int v, int P, int precision, int backward,
                               size_t hbm_budget, const cc_ladder_opts* opts,
                               size_t* bytes, int* a_block);
 
-/* Which occupied intermediate (eqs. vfunction3 and vfunction4). */
+/* Which occupied-index term (planner query): the intermediates of eqs.
+ * vfunction3 and vfunction4, and the hole-hole ladder. */
 typedef enum {
   CC_INTERMEDIATE_IJKL = 0,  /* X[i][j][k][l] += sum_{c,d} (kc|ld) t[i][j][c][d] */
-  CC_INTERMEDIATE_IJBK = 1   /* Y[i][j][b][k] += sum_{c,d} (bd|kc) t[i][j][c][d] */
+  CC_INTERMEDIATE_IJBK = 1,  /* Y[i][j][b][k] += sum_{c,d} (bd|kc) t[i][j][c][d] */
+  CC_HOLE_LADDER = 2         /* R[i][j][a][b] += sum_{k,l} (ik|jl) t[k][l][a][b] */
 } cc_intermediate_kind;
 
 /*
@@ -190,7 +193,21 @@ int cc_intermediate_ijbk(int o, int v, int P,
                          int precision, hipStream_t stream, const cc_ladder_opts* opts);
 
 /*
- * Host-only planner query for the intermediates (`which` a cc_intermediate_kind):
+ * Hole-hole ladder, the o^4 v^2 term the paper's pCCD-LCCSD vector function
+ * offloads beside the ladder (Sec. "Comparison between CPU and
+ * GPU-accelerated implementations"; the paper gives its contraction pattern,
+ * whose Cholesky operand expands as for eq. cholesky):
+ *   R[i][j][a][b] += sum_{k,l} ( sum_x L_oo[x][i][k] L_oo[x][j][l] ) t[k][l][a][b]
+ * The integrals (ik|jl) are rebuilt for blocks of the occupied index i
+ * (opts->a_block counts occupied indices).  Forms and flags as
+ * cc_intermediate_ijkl.  R must not overlap L_oo or t.
+ */
+int cc_hole_ladder(int o, int v, int P,
+                   const double* L_oo, const double* t, double* R,
+                   int precision, hipStream_t stream, const cc_ladder_opts* opts);
+
+/*
+ * Host-only planner query for the occupied-index terms (`which` a cc_intermediate_kind):
  * scratch bytes and first indices per integral block under `hbm_budget`
  * (0 = no limit), as cc_ladder_workspace_query.
  */

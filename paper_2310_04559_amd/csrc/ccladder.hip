@@ -498,7 +498,33 @@ int intermediate_blocks(const Plan& pl, const typename Tr::T* Lrow, long long ld
   return CC_LADDER_OK;
 }
 
-// Shared body of the two intermediates; Lrow is L_ov (ijkl) or L (ijbk).
+// Hole-hole ladder, per block of occupied i:
+//   build    W[i][j][k][l] = sum_x L_oo[x][i][k] L_oo[x][j][l]    GEMM M=(i,k) N=(j,l) K=x
+//   contract R[(i j)][(ab)] += sum_(kl) W[(ij)][(kl)] t[(kl)][(ab)]  GEMM M=(i,j) N=(a,b) K=(k,l)
+template <class Tr>
+int hole_blocks(const Plan& pl, const typename Tr::T* Loo, const typename Tr::T* t, double* R,
+                typename Tr::T* W, const Tracer& tr, hipStream_t s) {
+  const int o = pl.o, v = pl.v, P = pl.P;
+  const long long o2 = (long long)o * o, v2 = (long long)v * v;
+  const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  for (int i0 = 0, blk = 0; i0 < o; i0 += pl.n_a, ++blk) {
+    const int ni = (o - i0) < pl.n_a ? (o - i0) : pl.n_a;
+    tr(CC_LADDER_PHASE_BUILD, blk, 0);
+    int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(Loo + (long long)i0 * o, o2, Loo, o2, W, 0, ni * o,
+                                               static_cast<int>(o2), P, o, drain, s);
+    tr(CC_LADDER_PHASE_BUILD, blk, 1);
+    if (rc) return rc;
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
+    rc = launch_gemm<Tr, KC, RC, EPI_ACC>(W, o2, t, v2, R + (long long)i0 * o * v2, v2, ni * o,
+                                          static_cast<int>(v2), static_cast<int>(o2), v, drain, s);
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
+    if (rc) return rc;
+  }
+  return CC_LADDER_OK;
+}
+
+// Shared body of the occupied-index terms: the two intermediates (Lrow is L_ov
+// for ijkl, L for ijbk) and the hole-hole ladder (Lrow = Lov = L_oo, Z = R).
 int intermediate_call(int which, int o, int v, int P, const double* Lrow, const double* Lov,
                       const double* t, double* Z, int precision, hipStream_t stream,
                       const cc_ladder_opts* opts) {
@@ -508,11 +534,12 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
   if (rc) return rc;
   if (!Lrow || !Lov || !t || !Z) return CC_LADDER_EINVAL;
   const bool ijkl = which == CC_INTERMEDIATE_IJKL;
-  const long long n_first = ijkl ? o : v;
+  const bool hole = which == CC_HOLE_LADDER;
+  const long long n_first = which == CC_INTERMEDIATE_IJBK ? v : o;
   const size_t nt = (size_t)o * o * v * v * sizeof(double);
-  const size_t nov = (size_t)P * o * v * sizeof(double);
-  const size_t nrow = (size_t)P * n_first * v * sizeof(double);
-  const size_t nz = (size_t)o * o * n_first * o * sizeof(double);
+  const size_t nov = (size_t)P * o * (hole ? o : v) * sizeof(double);
+  const size_t nrow = hole ? nov : (size_t)P * n_first * v * sizeof(double);
+  const size_t nz = hole ? nt : (size_t)o * o * n_first * o * sizeof(double);
   if (overlaps(Z, nz, t, nt) || overlaps(Z, nz, Lov, nov) || overlaps(Z, nz, Lrow, nrow))
     return CC_LADDER_EINVAL;
   if (precision == CC_LADDER_SPLIT_BF16 || (opts && opts->flags)) return CC_LADDER_EUNSUPPORTED;
@@ -534,6 +561,20 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
   if (rc) return rc;
   char* base = ws.base;
   const Tracer tr(opts, stream);
+  if (hole) {
+    if (precision == CC_LADDER_FP64)
+      return hole_blocks<TrF64>(pl, Lov, t, Z, reinterpret_cast<double*>(base + pl.off_V), tr,
+                                stream);
+    float* Loo32 = reinterpret_cast<float*>(base + pl.off_L);
+    float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+    tr(CC_LADDER_PHASE_PREP, 0, 0);
+    rc = to_f32(Lov, Loo32, (size_t)P * o * o, stream);
+    if (!rc) rc = to_f32(t, t32, (size_t)o * o * v * v, stream);
+    tr(CC_LADDER_PHASE_PREP, 0, 1);
+    if (rc) return rc;
+    return hole_blocks<TrF32>(pl, Loo32, t32, Z, reinterpret_cast<float*>(base + pl.off_V), tr,
+                              stream);
+  }
   const long long ld_row = n_first * v;
   double* part = pl.k_splits > 1 ? reinterpret_cast<double*>(base + pl.off_part) : nullptr;
   if (precision == CC_LADDER_FP64) {
@@ -727,6 +768,11 @@ extern "C" int cc_intermediate_ijbk(int o, int v, int P, const double* L, const 
                                     const double* t, double* Y, int precision, hipStream_t stream,
                                     const cc_ladder_opts* opts) {
   return intermediate_call(CC_INTERMEDIATE_IJBK, o, v, P, L, L_ov, t, Y, precision, stream, opts);
+}
+
+extern "C" int cc_hole_ladder(int o, int v, int P, const double* L_oo, const double* t, double* R,
+                              int precision, hipStream_t stream, const cc_ladder_opts* opts) {
+  return intermediate_call(CC_HOLE_LADDER, o, v, P, L_oo, L_oo, t, R, precision, stream, opts);
 }
 
 extern "C" int cc_intermediate_workspace_query(int which, int o, int v, int P, int precision,

@@ -193,18 +193,21 @@ int choose_k_splits(long long M, long long N, long long K, int bk) {
 
 int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, int k_chunk,
                         Plan* plan) {
-  const int n_first = which == CC_INTERMEDIATE_IJKL ? o : v;
+  const int n_first = which == CC_INTERMEDIATE_IJBK ? v : o;
   if (n_p < 1 || n_p > n_first) return CC_LADDER_EINVAL;
   Plan p;
   p.o = o; p.v = v; p.P = P;
   p.precision = precision;
-  p.op = which == CC_INTERMEDIATE_IJKL ? kOpIjkl : kOpIjbk;
+  p.op = which == CC_INTERMEDIATE_IJKL ? kOpIjkl : which == CC_INTERMEDIATE_IJBK ? kOpIjbk : kOpHole;
   p.n_a = n_p;
   p.nblocks = (n_first + n_p - 1) / n_p;
   const size_t v2 = static_cast<size_t>(v) * v;
   const size_t o2 = static_cast<size_t>(o) * o;
   const size_t ov = static_cast<size_t>(o) * v;
-  const size_t blk = static_cast<size_t>(n_p) * o * v2;  // block rows (p, y), y occupied
+  // integral block: [n_p][o][v][v] for the intermediates, (ik|jl) as [n_p][o][o][o]
+  // for the hole-hole ladder
+  const size_t blk = p.op == kOpHole ? static_cast<size_t>(n_p) * o * o2
+                                     : static_cast<size_t>(n_p) * o * v2;
   size_t cur = 0;
   switch (precision) {
     case CC_LADDER_FP64:
@@ -215,7 +218,8 @@ int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, 
       break;
     case CC_LADDER_FP32:
       p.k_chunk = k_chunk ? k_chunk : 512;
-      p.off_L = take(&cur, static_cast<size_t>(P) * ov * sizeof(float));          // L_ov
+      // L_ov (L_oo for the hole-hole ladder)
+      p.off_L = take(&cur, static_cast<size_t>(P) * (p.op == kOpHole ? o2 : ov) * sizeof(float));
       if (p.op == kOpIjbk) p.off_L2 = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
       p.off_t = take(&cur, o2 * v2 * sizeof(float));
       p.off_V = take(&cur, blk * sizeof(float));
@@ -225,12 +229,14 @@ int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, 
     default:
       return CC_LADDER_EINVAL;
   }
-  // split K from the whole output's tile count, so every block sums in the
-  // same order whatever n_p is
-  p.k_splits = choose_k_splits(static_cast<long long>(o2), static_cast<long long>(n_first) * o,
-                               static_cast<long long>(v2), precision == CC_LADDER_FP64 ? 16 : 32);
-  if (p.k_splits > 1)
-    p.off_part = take(&cur, static_cast<size_t>(p.k_splits) * o2 * n_p * o * sizeof(double));
+  if (p.op != kOpHole) {
+    // split K from the whole output's tile count, so every block sums in the
+    // same order whatever n_p is
+    p.k_splits = choose_k_splits(static_cast<long long>(o2), static_cast<long long>(n_first) * o,
+                                 static_cast<long long>(v2), precision == CC_LADDER_FP64 ? 16 : 32);
+    if (p.k_splits > 1)
+      p.off_part = take(&cur, static_cast<size_t>(p.k_splits) * o2 * n_p * o * sizeof(double));
+  }
   p.bytes = cur;
   *plan = p;
   return CC_LADDER_OK;
@@ -238,7 +244,8 @@ int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, 
 
 int make_plan_intermediate(int which, int o, int v, int P, int precision, size_t budget,
                            const cc_ladder_opts* opts, Plan* plan) {
-  if (which != CC_INTERMEDIATE_IJKL && which != CC_INTERMEDIATE_IJBK) return CC_LADDER_EINVAL;
+  if (which != CC_INTERMEDIATE_IJKL && which != CC_INTERMEDIATE_IJBK && which != CC_HOLE_LADDER)
+    return CC_LADDER_EINVAL;
   int rc = check_dims(o, v, P);
   if (rc) return rc;
   rc = check_precision_opts(precision, opts);
@@ -246,7 +253,7 @@ int make_plan_intermediate(int which, int o, int v, int P, int precision, size_t
   // the packed and exchange variants belong to the ladder term only
   if (opts && opts->flags) return CC_LADDER_EUNSUPPORTED;
   const int k_chunk = opts ? opts->k_chunk : 0;
-  const int n_first = which == CC_INTERMEDIATE_IJKL ? o : v;
+  const int n_first = which == CC_INTERMEDIATE_IJBK ? v : o;
   return search_block(n_first, budget, opts ? opts->a_block : 0, [&](int n_p, Plan* p) {
     return layout_intermediate(which, o, v, P, precision, n_p, k_chunk, p);
   }, plan);

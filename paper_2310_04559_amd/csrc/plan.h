@@ -13,7 +13,7 @@
 namespace ccl {
 
 // Operation a plan is made for.
-enum { kOpLadder = 0, kOpIjkl = 1, kOpIjbk = 2 };
+enum { kOpLadder = 0, kOpIjkl = 1, kOpIjbk = 2, kOpHole = 3 };
 
 // Scratch buffers of one call, as byte offsets into a single workspace.
 struct Plan {
@@ -60,10 +60,11 @@ inline long long pair_prefix(long long a, long long v) { return a * v - a * (a -
 int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
               const cc_ladder_opts* opts, Plan* plan);
 
-// The occupied intermediates (eqs. vfunction3/vfunction4): blocks of n_p first
-// indices (occupied k for ijkl, virtual b for ijbk), integral block
-// [n_p][o][v][v].  Same search and return codes as make_plan; flags are
-// CC_LADDER_EUNSUPPORTED, SPLIT_BF16 too.
+// The occupied intermediates (eqs. vfunction3/vfunction4) and the hole-hole
+// ladder: blocks of n_p first indices (occupied k for ijkl, virtual b for ijbk,
+// occupied i for the hole-hole ladder), integral block [n_p][o][v][v]
+// ([n_p][o][o][o] for the hole-hole ladder).  Same search and return codes as
+// make_plan; flags are CC_LADDER_EUNSUPPORTED, SPLIT_BF16 too.
 // K ranges for a K-contiguous product of M x N (tiles of 128 x 256) over K
 // elements in steps of `bk`: 1 when the tiles fill the chip, otherwise the count
 // that minimises the waves per unit of work (at least 64 K-steps per range).

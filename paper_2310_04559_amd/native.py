@@ -30,7 +30,7 @@ CC_LADDER_EUNSUPPORTED = -5
 
 EXPORTS = ("cc_ladder_residual", "cc_ladder_backward", "cc_ladder_reduce",
            "cc_ladder_workspace_query", "cc_ladder_strerror", "cc_intermediate_ijkl",
-           "cc_intermediate_ijbk", "cc_intermediate_workspace_query")
+           "cc_intermediate_ijbk", "cc_intermediate_workspace_query", "cc_hole_ladder")
 
 
 class CcLadderOpts(ctypes.Structure):
@@ -53,7 +53,8 @@ CC_LADDER_PAIR_SYMMETRIC = 1
 CC_LADDER_EXCHANGE = 2
 CC_INTERMEDIATE_IJKL = 0
 CC_INTERMEDIATE_IJBK = 1
-INTERMEDIATES = {"ijkl": CC_INTERMEDIATE_IJKL, "ijbk": CC_INTERMEDIATE_IJBK}
+CC_HOLE_LADDER = 2
+INTERMEDIATES = {"ijkl": CC_INTERMEDIATE_IJKL, "ijbk": CC_INTERMEDIATE_IJBK, "hole": CC_HOLE_LADDER}
 
 
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -93,6 +94,8 @@ def load():
     lib.cc_intermediate_ijkl.restype = i
     lib.cc_intermediate_ijbk.argtypes = [i, i, i, p, p, p, p, i, p, opts_p]
     lib.cc_intermediate_ijbk.restype = i
+    lib.cc_hole_ladder.argtypes = [i, i, i, p, p, p, i, p, opts_p]
+    lib.cc_hole_ladder.restype = i
     lib.cc_intermediate_workspace_query.argtypes = [i, i, i, i, i, st, opts_p,
                                                     ctypes.POINTER(st), ctypes.POINTER(i)]
     lib.cc_intermediate_workspace_query.restype = i
@@ -250,6 +253,21 @@ def cc_intermediate_ijbk(L: torch.Tensor, L_ov: torch.Tensor, t: torch.Tensor, Y
                                       _stream(Y.device, stream), _opts_ref(opts))
     _check(rc, "cc_intermediate_ijbk")
     return Y
+
+
+def cc_hole_ladder(L_oo: torch.Tensor, t: torch.Tensor, R: torch.Tensor, precision=0, stream=None,
+                   opts: Optional[CcLadderOpts] = None) -> torch.Tensor:
+    """R[i,j,a,b] += sum_kl (sum_x L_oo[x,i,k] L_oo[x,j,l]) t[k,l,a,b]; returns R."""
+    lib = load()
+    P, o, _ = L_oo.shape
+    v = t.shape[2]
+    args = (_dev_f64(L_oo, "L_oo", (P, o, o)), _dev_f64(t, "t", (o, o, v, v)),
+            _dev_f64(R, "R", (o, o, v, v)))
+    with torch.cuda.device(R.device):
+        rc = lib.cc_hole_ladder(o, v, P, *args, _prec(precision), _stream(R.device, stream),
+                                _opts_ref(opts))
+    _check(rc, "cc_hole_ladder")
+    return R
 
 
 def cc_intermediate_workspace_query(which, o: int, v: int, P: int, precision=0,

@@ -21,7 +21,7 @@ def native():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cc_(?:ladder|intermediate)_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cc_(?:ladder|intermediate|hole)_\w+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol(native):
@@ -139,7 +139,7 @@ def test_planner_intermediate_footprints(native):
             native.cc_intermediate_workspace_query("ijkl", o, v, P, prec, opts=native.make_opts(**kw))
         assert e.value.code == native.CC_LADDER_EUNSUPPORTED
     with pytest.raises(native.LadderError) as e:
-        native.cc_intermediate_workspace_query(2, o, v, P, "fp64")
+        native.cc_intermediate_workspace_query(3, o, v, P, "fp64")
     assert e.value.code == native.CC_LADDER_EINVAL
 
 
@@ -178,6 +178,19 @@ def test_planner_intermediate_split_partials(native, o, v, P, which, prec):
     assert b == ops + rnd(n * o * v * v * esz) + part
     if (o, v, which) == (40, 360, "ijkl"):
         assert S == 14  # 91 tiles: 14 ranges give 1274 workgroups in 5 waves
+
+
+def test_planner_hole_ladder_footprint(native):
+    # (ik|jl) for a block of occupied i: [n_p][o][o][o]; the float32 form adds
+    # its copies of L_oo and t
+    o, v, P = 6, 30, 50
+    rnd = lambda b: (b + 255) // 256 * 256
+    b, n = native.cc_intermediate_workspace_query("hole", o, v, P, "fp64")
+    assert n == o and b == rnd(o ** 4 * 8)
+    b, n = native.cc_intermediate_workspace_query("hole", o, v, P, "fp32")
+    assert n == o and b == rnd(P * o * o * 4) + rnd(o * o * v * v * 4) + rnd(o ** 4 * 4)
+    b, n = native.cc_intermediate_workspace_query("hole", o, v, P, "fp64", hbm_budget=rnd(2 * o ** 3 * 8))
+    assert n == 2 and b == rnd(2 * o ** 3 * 8)
 
 
 def test_planner_explicit_block_and_enomem(native):
@@ -235,6 +248,8 @@ def test_intermediate_argument_checks_precede_device_checks(native):
                                     None) == native.CC_LADDER_EINVAL
     assert lib.cc_intermediate_ijbk(0, 4, 2, 1 << 28, 1 << 30, t, 1 << 32, 0, None,
                                     None) == native.CC_LADDER_EINVAL
+    assert lib.cc_hole_ladder(2, 4, 2, 1 << 28, t, t + 128, 0, None, None) == native.CC_LADDER_EINVAL
+    assert lib.cc_hole_ladder(2, 4, 2, None, t, 1 << 30, 0, None, None) == native.CC_LADDER_EINVAL
 
 
 def test_no_device_is_reported(native):
@@ -250,3 +265,4 @@ def test_no_device_is_reported(native):
                                     None) == native.CC_LADDER_ENODEV
     assert lib.cc_intermediate_ijbk(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 1 << 30, 1, None,
                                     None) == native.CC_LADDER_ENODEV
+    assert lib.cc_hole_ladder(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None, None) == native.CC_LADDER_ENODEV

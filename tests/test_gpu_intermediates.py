@@ -1,5 +1,5 @@
 """GPU parity of the occupied intermediates (eqs. vfunction3 and vfunction4)
-against the float64 oracle, through the C ABI."""
+and of the hole-hole ladder against the float64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 import torch
@@ -150,3 +150,66 @@ def test_intermediate_caller_workspace_and_unsupported(gpu_lib):
     with pytest.raises(gpu_lib.LadderError) as e:
         gpu_lib.cc_intermediate_ijkl(dev(Lov), dev(t), X, 2)
     assert e.value.code == gpu_lib.CC_LADDER_EUNSUPPORTED
+
+
+def random_oo(o, P, seed):
+    return np.random.default_rng(seed).standard_normal((P, o, o)) / np.sqrt(o)
+
+
+def run_hole(native, Loo, t, R0, precision, **kw):
+    R = dev(R0)
+    native.cc_hole_ladder(dev(Loo), dev(t), R, precision, opts=native.make_opts(**kw))
+    torch.cuda.synchronize()
+    return host(R)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("o,v,P", SHAPES + [(37, 9, 40), (130, 3, 7)])
+@pytest.mark.parametrize("block", [0, 3])
+def test_hole_ladder_general_inputs(gpu_lib, o, v, P, block, precision):
+    # unsymmetric L_oo and t; o up to 130 spans several tiles of the (i,k) rows
+    announce("hole", o, v, P, "block", block, "precision", precision)
+    _, t, _ = random_general(o, v, P, 800 + o + v)
+    Loo = random_oo(o, P, 810 + o)
+    R0 = np.random.default_rng(7).standard_normal(t.shape)
+    inc = oracle.hole_ladder(Loo, t)
+    got = run_hole(gpu_lib, Loo, t, R0, precision, a_block=block)
+    assert rel_fro(got - R0, inc) < TOL[precision]
+
+
+def test_hole_ladder_integer_exact_and_deterministic(gpu_lib):
+    announce("hole-int")
+    _, t = integer_inputs(7, 6, 5, 89)
+    Loo = np.random.default_rng(90).integers(-2, 3, size=(5, 7, 7)).astype(np.float64)
+    ref = oracle.hole_ladder(Loo, t)
+    for precision in (0, 1):
+        assert np.array_equal(run_hole(gpu_lib, Loo, t, np.zeros_like(t), precision), ref)
+    _, t, _ = random_general(13, 44, 131, 91)
+    Loo = random_oo(13, 131, 92)
+    z = np.zeros_like(t)
+    base = run_hole(gpu_lib, Loo, t, z, 0)
+    for block in (1, 5):
+        assert np.array_equal(run_hole(gpu_lib, Loo, t, z, 0, a_block=block), base)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_hole_ladder_workloads(gpu_lib, name):
+    # the generator's own occupied-occupied vectors; at 40/360/1200 the oracle
+    # computes the rows of a few occupied i
+    o, v, P = CONFIGS[name]
+    announce("hole-workload", name)
+    inp = make_inputs(o, v, P, seed_for(name), device="cuda" if name == "c3" else None)
+    rows = list(range(o)) if name != "c3" else [0, o // 2, o - 1]
+    ref = np.zeros_like(inp.t)
+    for i in rows:
+        oracle.hole_ladder(inp.L_oo, inp.t, ref, i, i + 1)
+    Ld, td = dev(inp.L_oo), dev(inp.t)
+    for precision in (0, 1):
+        R = torch.zeros_like(td)
+        gpu_lib.cc_hole_ladder(Ld, td, R, precision)
+        torch.cuda.synchronize()
+        got = host(R)
+        assert rel_fro(got[rows], ref[rows]) < TOL[precision], precision
+        # (ik|jl) = (jl|ik) with pair-symmetric t: R[i,j,a,b] = R[j,i,b,a]
+        assert rel_fro(got.transpose(1, 0, 3, 2), got) < 10 * TOL[precision]
+        del R
