@@ -212,3 +212,231 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
 }
 
 }  // namespace ccl
+
+namespace ccl {
+
+// Integral-build GEMM with both operands row-contiguous (RC) and direct
+// global->LDS loads (gfx950):
+//
+//   C = perm( sum_k A[k*lda + m] B[k*ldb + n] )          (EPI_PERM store in the operand type)
+//
+// Same 128 x 256 tile, 8 waves and 3-stage LDS ring as the K-contiguous kernel.
+// A stage holds BK rows of k: 128 contiguous m of A and 256 contiguous n of B per
+// row, filled 1 KB per wave instruction (lane l writes 16 bytes at +16*l).  An
+// MFMA operand needs one value per lane from one k row, so the rows of the 4 x 4
+// blocks of a wave are interleaved: block i's row r is wave row pos(i, r) with
+// pos = 4r + i (float32) or 32*(i/2) + 2r + (i%2) (float64), making the values a
+// lane needs for all four blocks one 16-byte LDS read (two for float64), the 16
+// lanes of a k row reading 256 contiguous bytes (no bank conflicts, no swizzle).
+// Columns are interleaved the same way, which also makes the values a lane stores
+// for the four column blocks adjacent in the output: the permuted epilogue writes
+// them with 16-byte stores when v is a multiple of the chunk.  Needs M and N
+// multiples of the 16-byte chunk and 16-byte aligned operand rows; rows past M or
+// N are clamped onto the last chunk (never stored); a ragged last K-step is
+// loaded through registers with zero fill.
+template <class Tr>
+__device__ __forceinline__ int rc_pos(int i, int r) {
+  if constexpr (Tr::CH == 4)
+    return 4 * r + i;
+  else
+    return 32 * (i >> 1) + 2 * r + (i & 1);
+}
+
+template <class Tr>
+__global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<typename Tr::T> g) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  using Chunk = typename Tr::Chunk;
+  constexpr int CH = Tr::CH;
+  constexpr int BK = kDRow / sizeof(T);          // 16 float64 / 32 float32 k rows per stage
+  constexpr int ROWA = kDBM * sizeof(T);         // bytes of one k row of A (128 m)
+  constexpr int ROWB = kDBN * sizeof(T);         // bytes of one k row of B (256 n)
+  constexpr int A_BYTES = BK * ROWA;             // 16 KB
+  constexpr int B_BYTES = BK * ROWB;             // 32 KB
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int AI = A_BYTES / 1024 / 8;         // 1 KB wave instructions per wave: A (2)
+  constexpr int BI = B_BYTES / 1024 / 8;         // B (4)
+  constexpr int LOADS = AI + BI;
+  constexpr int CPRA = kDBM / CH;                // 16-byte chunks per A row
+  constexpr int CPRB = kDBN / CH;                // per B row
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[kDStages * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = (wave >> 2) * 64;
+  const int wn = (wave & 3) * 64;
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  const int m0 = tm * kDBM, n0 = tn * kDBN;
+
+  // Wave instruction q of a stage covers bytes [q KB, q KB + 1 KB) of the A (or B)
+  // slab: flattened chunk q*64 + lane -> (k row, chunk).  This lane's k row and
+  // source pointer at k = 0 for each of its instructions.
+  const T* pa[AI];
+  const T* pb[BI];
+  int ra[AI], rb[BI];
+#pragma unroll
+  for (int j = 0; j < AI; ++j) {
+    const int flat = (wave + 8 * j) * 64 + lane;
+    ra[j] = flat / CPRA;
+    int m = m0 + (flat % CPRA) * CH;
+    m = m < g.M ? m : g.M - CH;
+    pa[j] = g.A + (long long)ra[j] * g.lda + m;
+  }
+#pragma unroll
+  for (int j = 0; j < BI; ++j) {
+    const int flat = (wave + 8 * j) * 64 + lane;
+    rb[j] = flat / CPRB;
+    int n = n0 + (flat % CPRB) * CH;
+    n = n < g.N ? n : g.N - CH;
+    pb[j] = g.B + (long long)rb[j] * g.ldb + n;
+  }
+  auto issue = [&](int kt) {
+    unsigned char* st = lds + (kt % kDStages) * STAGE;
+    const long long ka = (long long)kt * BK * g.lda, kb = (long long)kt * BK * g.ldb;
+#pragma unroll
+    for (int j = 0; j < AI; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(pa[j] + ka),
+                                       (lds_void*)(st + (wave + 8 * j) * 1024), 16, 0, 0);
+#pragma unroll
+    for (int j = 0; j < BI; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(pb[j] + kb),
+                                       (lds_void*)(st + A_BYTES + (wave + 8 * j) * 1024), 16, 0, 0);
+  };
+  // Ragged last K-step: the same LDS image through registers, k rows >= K zero.
+  auto issue_tail = [&](int kt) {
+    unsigned char* st = lds + (kt % kDStages) * STAGE;
+    const int k0 = kt * BK;
+    const long long ka = (long long)k0 * g.lda, kb = (long long)k0 * g.ldb;
+#pragma unroll
+    for (int j = 0; j < AI; ++j) {
+      Chunk c = {};
+      if (k0 + ra[j] < g.K) c = *reinterpret_cast<const Chunk*>(pa[j] + ka);
+      *reinterpret_cast<Chunk*>(st + (wave + 8 * j) * 1024 + 16 * lane) = c;
+    }
+#pragma unroll
+    for (int j = 0; j < BI; ++j) {
+      Chunk c = {};
+      if (k0 + rb[j] < g.K) c = *reinterpret_cast<const Chunk*>(pb[j] + kb);
+      *reinterpret_cast<Chunk*>(st + A_BYTES + (wave + 8 * j) * 1024 + 16 * lane) = c;
+    }
+    __builtin_amdgcn_s_waitcnt(0xF | (7 << 4) | (3 << 14));  // lgkmcnt(0): the LDS writes landed
+  };
+
+  Acc acc[4][4];
+  f64x4 acc64[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = Acc{0, 0, 0, 0};
+      acc64[i][j] = f64x4{0, 0, 0, 0};
+    }
+
+  // fragment reads: k row (lane / 16) of each 4-deep MFMA step, wave row/column
+  // pos(., lane % 16) of the four blocks
+  const int kr = lane >> 4;
+  const int r16 = lane & 15;
+  const int offa = (wm + (CH == 4 ? 4 * r16 : 2 * r16)) * (int)sizeof(T);
+  const int offb = (wn + (CH == 4 ? 4 * r16 : 2 * r16)) * (int)sizeof(T);
+  const int nk = (g.K + BK - 1) / BK;
+  const int nkf = g.K / BK;
+  auto stage_in = [&](int kt) {
+    if (kt < nkf)
+      issue(kt);
+    else
+      issue_tail(kt);
+  };
+  stage_in(0);
+  if (nk > 1) stage_in(1);
+  for (int k0 = 0; k0 < nk;) {
+    const int kend = (Tr::kDrain && k0 + g.drain_steps < nk) ? k0 + g.drain_steps : nk;
+    for (int kt = k0; kt < kend; ++kt) {
+      d_wait_vm(kt + 1 < nkf ? LOADS : 0);
+      __builtin_amdgcn_s_barrier();
+      if (kt + 2 < nk) stage_in(kt + 2);
+      const unsigned char* st = lds + (kt % kDStages) * STAGE;
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const unsigned char* ra_ = st + (4 * kk + kr) * ROWA + offa;
+        const unsigned char* rb_ = st + A_BYTES + (4 * kk + kr) * ROWB + offb;
+        T fa[4], fb[4];
+        if constexpr (CH == 4) {
+          const Chunk a = *reinterpret_cast<const Chunk*>(ra_);
+          const Chunk b = *reinterpret_cast<const Chunk*>(rb_);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            fa[i] = a[i];
+            fb[i] = b[i];
+          }
+        } else {
+          const Chunk a0 = *reinterpret_cast<const Chunk*>(ra_);
+          const Chunk a1 = *reinterpret_cast<const Chunk*>(ra_ + 32 * sizeof(T));
+          const Chunk b0 = *reinterpret_cast<const Chunk*>(rb_);
+          const Chunk b1 = *reinterpret_cast<const Chunk*>(rb_ + 32 * sizeof(T));
+          fa[0] = a0[0]; fa[1] = a0[1]; fa[2] = a1[0]; fa[3] = a1[1];
+          fb[0] = b0[0]; fb[1] = b0[1]; fb[2] = b1[0]; fb[3] = b1[1];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i], fb[j], acc[i][j]);
+      }
+    }
+    if (Tr::kDrain) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc64[i][j][r] += static_cast<double>(acc[i][j][r]);
+            acc[i][j][r] = 0;
+          }
+    }
+    k0 = kend;
+  }
+
+  // epilogue: column groups of CH adjacent n (blocks j = CH*h .. CH*h + CH - 1)
+  const long long v = g.v;
+  const bool vec = (g.v % CH) == 0;
+  constexpr int NG = 4 / CH;  // column groups per lane: 1 (float32) or 2 (float64)
+#pragma unroll
+  for (int h = 0; h < NG; ++h) {
+    const int nb = n0 + wn + rc_pos<Tr>(CH * h, r16);  // first column of the group
+    if (nb >= g.N) continue;                            // N % CH == 0: whole group out
+    const int y = nb / g.v, d = nb - y * g.v;
+    const long long coff = (long long)y * v * v + d;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + rc_pos<Tr>(i, Tr::row_of(lane, r));
+        if (m >= g.M) continue;
+        const int a = m / g.v, x = m - a * g.v;
+        T* dst = static_cast<T*>(g.C) + (long long)a * g.N * v + coff + (long long)x * v;
+        Chunk val;
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+          const double s = Tr::kDrain ? acc64[i][CH * h + e][r]
+                                      : static_cast<double>(acc[i][CH * h + e][r]);
+          val[e] = static_cast<T>(s);
+        }
+        if (vec) {
+          *reinterpret_cast<Chunk*>(dst) = val;
+        } else {
+          // the group may cross a y boundary: element-wise addresses
+#pragma unroll
+          for (int e = 0; e < CH; ++e) {
+            const int n = nb + e;
+            const int ye = n / g.v, de = n - ye * g.v;
+            static_cast<T*>(g.C)[(long long)a * g.N * v + (long long)ye * v * v + de +
+                                 (long long)x * v] = val[e];
+          }
+        }
+      }
+  }
+}
+
+}  // namespace ccl
