@@ -157,8 +157,11 @@ struct SplitArgs {
 // lane l of a wave writes 16 bytes at the wave's LDS base + 16*l), three K-steps
 // in flight in a ring of LDS stages, one barrier per K-step.  A 16-row slab of a
 // slice is one load instruction: lane l takes row l/4 and physical 16-byte slot
-// l%4, which holds the logical k-chunk (l%4) ^ ((row/4)%4); fragment reads undo the
-// XOR, so the 16 rows read by 16 lanes fall on 16 distinct 4-bank groups.
+// l%4, which holds the logical k-chunk (l%4) ^ ((row/2)%4); fragment reads undo the
+// XOR.  Keying on row/2 (pairs of 64-byte rows share a key) makes the 16-byte
+// fragment reads free of bank conflicts on gfx950; keying on row/4, or no
+// swizzle, costs one extra LDS cycle per read (measured with the hardware's
+// bank-conflict counter on a read-pattern probe).
 constexpr int kStages = 3;
 constexpr int kRowBytes = kSBK * 2;  // 64 bytes: one 32-deep row of bf16 digits
 
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs g) {
 
   // this lane's element offset inside any 16-row slab (row lane/4, swizzled chunk)
   const int lrow = lane >> 2;
-  const int lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+  const int lchunk = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
   const long long loff = (long long)lrow * g.Kp + lchunk * 8;
   const __bf16* pa = g.A + (long long)(m0 + 16 * wave) * g.Kp + loff;
   const __bf16* pb = g.B + (long long)(n0 + 16 * wave) * g.Kp + loff;
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs g) {
     for (int j = 0; j < 4; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
 
   // fragment read: row (lane & 15) of a 16-row block, logical chunk lane >> 4
-  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 2) & 3)) * 16);
+  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
   const int nk = g.Kp / kSBK;
   issue(0);
   if (nk > 1) issue(1);
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
   const int m0 = tm * kSBM, n0 = tn * kSBN;
 
   const int lrow = lane >> 2;
-  const int lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+  const int lchunk = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
   const long long loff = (long long)lrow * g.Kp + lchunk * 8;
   auto issue = [&](int kt) {
     unsigned char* st = lds + (kt % kStages) * STAGE;
@@ -393,7 +396,7 @@ __global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
 
-  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 2) & 3)) * 16);
+  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
   const int nk = g.Kp / kSBK;
 
   // One exact chunk of this wave's anti-diagonals [LO, HI) (slices < SL needed).
@@ -468,14 +471,15 @@ __global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
 
   // add the upper anti-diagonals' sums (waves 4..7) into waves 0..3
   __builtin_amdgcn_s_barrier();  // every wave is done reading the operand stages
-  double* red = reinterpret_cast<double*>(lds) + (sub * 64 + lane) * 32;
+  // lane-contiguous: each store or load of the 64 lanes touches 512 consecutive bytes
+  double* red = reinterpret_cast<double*>(lds) + sub * 64 * 32 + lane;
   if (half == 1) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[(i * 4 + j) * 4 + r] = acc64[i][j][r];
+        for (int r = 0; r < 4; ++r) red[((i * 4 + j) * 4 + r) * 64] = acc64[i][j][r];
   }
   __syncthreads();
   if (half == 1) return;
@@ -484,7 +488,7 @@ __global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[i][j][r] += red[(i * 4 + j) * 4 + r];
+      for (int r = 0; r < 4; ++r) acc64[i][j][r] += red[((i * 4 + j) * 4 + r) * 64];
 
   const long long v = g.v;
 #pragma unroll
