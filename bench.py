@@ -26,6 +26,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -103,6 +104,26 @@ def read_traffic(kernel: str, form: str):
         return None
 
 
+def read_mfma_busy(kernel: str, form: str):
+    """MFMA-busy fraction (SQ_VALU_MFMA_BUSY_CYCLES over the SIMDs' active cycles)
+    of a kernel from the committed rocprofv3 summary, or None when absent or
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "mfma_busy_c3.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_src_sha256_16") != kernel_src_hash():
+        return None
+    try:
+        return float(kv[f"{kernel}_{form}"])
+    except (KeyError, ValueError):
+        return None
+
+
 class PhaseTimer:
     """Records a HIP event pair on the call's stream around each traced phase."""
 
@@ -168,19 +189,21 @@ def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
         step()
     torch.cuda.synchronize()
     timer.reset()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps on the call's stream: per-step times
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
+    evs[0].record(stream)
+    for k in range(steps):
         step()
-    e1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1) / steps
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
     phases = timer.summary()
     del ws
-    return {"ms_per_step": ms, "wall_s": wall, "a_block": n_a, "workspace_bytes": nbytes,
-            "phases": phases}
+    return {"ms_per_step": ms, "ms_std": statistics.pstdev(per), "ms_min": min(per),
+            "wall_s": wall, "a_block": n_a, "workspace_bytes": nbytes, "phases": phases}
 
 
 def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
@@ -397,7 +420,7 @@ def bench_intermediates(native, inp, steps, warmup, ws_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2,fp64_pairsym,"
@@ -486,6 +509,7 @@ def main():
                              "peak": PEAK_TFLOPS[form], "unit": "TFLOP/s",
                              "frac": achieved / PEAK_TFLOPS[form],
                              "traffic": read_traffic("contract", form),
+                             "mfma_busy_counter": read_mfma_busy("contract", form),
                              "flops_per_launch": mfma_products(form) * launch_flops,
                              "nominal_tflops": launch_flops / (c["ms_avg"] * 1e-3) / 1e12}
         b = r["phases"].get("build")
@@ -493,7 +517,8 @@ def main():
             bflops = 2.0 * P * float(v) ** 4 * executed_fraction(form, v) / (b["launches"] / args.steps)
             r["build_tflops"] = bflops / (b["ms_avg"] * 1e-3) / 1e12
         forms[form] = r
-        log(f"{form}: {r['ms_per_step']:.1f} ms/step {r['tflops']:.2f} TFLOP/s err {err:.2e} "
+        log(f"{form}: {r['ms_per_step']:.1f} +- {r['ms_std']:.1f} (min {r['ms_min']:.1f}) ms/step "
+            f"{r['tflops']:.2f} TFLOP/s err {err:.2e} "
             f"a_block {n_a} phases {json.dumps(r['phases'])}")
         R.zero_()
 
@@ -509,6 +534,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
+        "ms_per_step_std": head["ms_std"],
+        "ms_per_step_min": head["ms_min"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -43,7 +43,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_loss",
+__all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_row", "ladder_loss",
            "exchange_forward", "exchange_backward", "intermediate_ijkl", "intermediate_ijbk",
            "hole_ladder",
            "reduce_dot", "eri_slice", "nominal_flops_forward", "nominal_flops_backward",
@@ -252,6 +252,19 @@ def ladder_pairs(L, t, pairs) -> np.ndarray:
     for k, (a, b) in enumerate(pairs):
         Vab = L[:, a, :].T @ L[:, b, :]               # [c][d]
         out[k] = (T @ Vab.reshape(v * v)).reshape(o, o)
+    return out
+
+
+def ladder_row(L, t, i: int, j: int) -> np.ndarray:
+    """``R[i, j, :, :]`` of the ladder term for one occupied pair, from eq.
+    cholesky and eq. vfunction regrouped per Cholesky vector:
+    ``R[i,j,a,b] = sum_x sum_c L[x,a,c] sum_d t[i,j,c,d] L[x,b,d]``, i.e.
+    ``sum_x L_x t_ij L_x^T``.  Returns ``[v][v]``."""
+    L, t = _check(L, t)
+    T = t[i, j]
+    out = np.zeros((L.shape[1], L.shape[1]))
+    for x in range(L.shape[0]):
+        out += L[x] @ T @ L[x].T
     return out
 
 

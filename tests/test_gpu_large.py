@@ -1,7 +1,8 @@
 """The large single-GPU workload (o=60, v=600, P=1800): t and R are 10.4 GB
 each, L 5.2 GB, the integral-block size is chosen by the planner.  The oracle
-checks sampled R[:, :, a, b] columns; the adjoint is checked through identities
-that hold at any size and against the float64 adjoint."""
+checks sampled R[:, :, a, b] columns (43200 entries) and two complete rows
+R[i, j, :, :]; the adjoint is checked through identities that hold at any size
+and against the float64 adjoint."""
 import numpy as np
 import pytest
 import torch
@@ -30,10 +31,18 @@ def large(gpu_lib):
     rng = np.random.default_rng(5)
     pairs = sorted({(0, 0), (v - 1, v - 1), (0, v - 1)} |
                    {(int(rng.integers(0, v)), int(rng.integers(0, v))) for _ in range(9)})
+    announce("large-oracle-columns", len(pairs))
     ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
+    # complete rows R[i, j, :, :] for two occupied pairs
+    rows = [(0, 0), (o - 1, 3)]
+    ref_rows = []
+    for i, j in rows:
+        announce("large-oracle-row", i, j)
+        ref_rows.append(oracle.ladder_row(inp.L_vv, inp.t, i, j))
     lam = torch.from_numpy(inp.lam).cuda()
     del inp
-    return dict(L=L, t=t, lam=lam, pairs=pairs, ref=ref, o=o, v=v, P=P)
+    return dict(L=L, t=t, lam=lam, pairs=pairs, ref=ref, rows=rows, ref_rows=ref_rows, o=o, v=v,
+                P=P)
 
 
 def test_large_forward_fp64_and_split(gpu_lib, large):
@@ -48,6 +57,8 @@ def test_large_forward_fp64_and_split(gpu_lib, large):
         torch.cuda.synchronize()
         got = host(R[:, :, ia, ib].permute(2, 0, 1))
         assert rel_fro(got, ref) < tol, prec
+        for (i, j), want in zip(large["rows"], large["ref_rows"]):
+            assert rel_fro(host(R[i, j]), want) < tol, (prec, i, j)
     del R
 
 

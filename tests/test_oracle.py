@@ -566,3 +566,14 @@ def test_hole_ladder_pair_symmetry():
     inp = make_inputs(4, 6, 9, 106)
     R = oracle.hole_ladder(inp.L_oo, inp.t)
     assert rel_fro(R.transpose(1, 0, 3, 2), R) < 1e-15
+
+
+def test_ladder_row_equals_bruteforce_and_forward():
+    # one occupied pair's whole R[i,j,:,:] regrouped per Cholesky vector
+    L, t = integer_inputs(2, 4, 3, 107)
+    exact = np.array(_int_ladder(_to_int(L), _to_int(t)), dtype=np.float64)
+    for i, j in ((0, 0), (0, 1), (1, 0)):
+        assert np.array_equal(oracle.ladder_row(L, t, i, j), exact[i, j])
+    L, t, _ = random_general(3, 7, 5, 108)
+    R = oracle.ladder_forward(L, t)
+    assert rel_fro(oracle.ladder_row(L, t, 2, 1), R[2, 1]) < 1e-14
