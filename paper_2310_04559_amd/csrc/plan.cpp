@@ -95,10 +95,10 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad * 2);
       p.off_Lexp = take(&cur, static_cast<size_t>(dL.rows_pad) * sizeof(int));
       p.off_t = take(&cur, s * dt.rows_pad * dt.k_pad * 2);
-      p.off_texp = take(&cur, static_cast<size_t>(dt.rows_pad) * sizeof(int));
+      p.off_texp = take(&cur, static_cast<size_t>(dt.rows_pad) * exp_chunks(dt.k_pad) * sizeof(int));
       p.off_V = take(&cur, blk * sizeof(double));
       p.off_Vs = take(&cur, s * dV.rows_pad * dV.k_pad * 2);
-      p.off_Vexp = take(&cur, static_cast<size_t>(dV.rows_pad) * sizeof(int));
+      p.off_Vexp = take(&cur, static_cast<size_t>(dV.rows_pad) * exp_chunks(dV.k_pad) * sizeof(int));
       break;
     }
     default:

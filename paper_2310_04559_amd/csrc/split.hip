@@ -1,16 +1,23 @@
 // Split-bf16 form of the ladder forward.
 //
-// Every operand row (a row of the matrix along its contracted index) gets one
-// exponent e with max|x| < 2^e, and is cut into S balanced base-256 digits:
+// Every operand row (a row of the matrix along its contracted index) gets an
+// exponent e with max|x| < 2^e -- one per row for the integral build, one per
+// (row, chunk of 128 contracted indices) for the amplitude contraction -- and
+// each value is cut into S balanced base-256 digits:
 //   x = 2^e * sum_{p=1..S} d_p 2^(-8p) + r,   d_1 in [-256, 256], d_p in [-128, 128] (p > 1),
 // |r| <= 2^(e - 8S - 1).  Digits are integers, exact in bf16.  A product of two
-// such matrices is
-//   C[m][n] = 2^(eA[m] + eB[n]) sum_{g} 2^(-8g) sum_{p+q=g} sum_k dA_p[m][k] dB_q[n][k],
+// such matrices is, per K-chunk c,
+//   C[m][n] += 2^(eA[m,c] + eB[n,c]) sum_{g} 2^(-8g) sum_{p+q=g} sum_{k in c} dA_p[m][k] dB_q[n][k],
 // keeping the anti-diagonals g = p + q <= S + D (D = 1: the S(S+1)/2-product
-// triangle; D = 2 adds the next anti-diagonal).  Each inner
-// sum is a sum of integer products; over K-chunks of 128 every partial sum of
-// one group stays below 2^24, so the bf16 MFMA's float32 accumulation is exact
-// and each chunk is drained into float64.  The two contractions then run as:
+// triangle; D = 2 adds the next anti-diagonal).  Each inner sum is a sum of
+// integer products; over a chunk of 128 every partial sum of one group stays
+// below 2^24, so the bf16 MFMA's float32 accumulation is exact and each chunk is
+// drained into float64 with its own scale.  Exponents per chunk follow the
+// operands' magnitude along the contracted index and halve the contraction's
+// error at the same digit count (1.0e-9 -> 5.0e-10 over whole rows at
+// o=20 v=180 P=600 in the exact NumPy model of the scheme); for the build,
+// whose rows (Cholesky vectors along x) are evenly scaled, they change nothing.
+// The two contractions then run as:
 //   build    V_A = L-slices x L-slices (K = x), float64 block, permuted store
 //   re-slice V_A rows (a,b) along (c,d)
 //   contract R += t-slices x V_A-slices (K = (c,d)), float64 accumulation
@@ -32,6 +39,7 @@ constexpr int kSBM = 64;    // workgroup tile rows (M)
 constexpr int kSBN = 128;   // workgroup tile columns (N)
 constexpr int kSBK = 32;    // K per stage = one bf16 MFMA depth
 constexpr int kChunkSteps = 4;  // K-steps per exact float32 chunk (128 contracted indices)
+static_assert(kChunkSteps * kSBK == kExpChunk, "one exponent per exact chunk");
 
 // Balanced base-256 digits of y in (-1, 1): writes S bf16 digits, most significant first.
 template <int S>
@@ -51,34 +59,39 @@ __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
 
 // Rows with the contracted index contiguous: X[r][k] = X[r*ld + k], r < R, k < K.
 // One workgroup per output row (R_pad rows, the padding rows get zero digits).
+// Exponents per (row, chunk of kExpChunk): ex[c * ex_stride + r].  The 16
+// threads that cut one chunk (8 values each) are adjacent lanes of one wave and
+// agree on its maximum through shuffles.
 template <int S>
 __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict__ X, long long ld,
                                                        int R, int K, int Kp, long long sstride,
-                                                       __bf16* __restrict__ out, int* __restrict__ ex) {
+                                                       __bf16* __restrict__ out, int* __restrict__ ex,
+                                                       int ex_stride) {
+  static_assert(kExpChunk == 16 * 8, "a chunk is cut by 16 threads of 8 values");
   const int r = blockIdx.x;
   const int tid = threadIdx.x;
   const double* row = X + (long long)r * ld;
-  double m = 0.0;
-  if (r < R)
-    for (int k = tid; k < K; k += 256) m = fmax(m, fabs(row[k]));
-  __shared__ double red[256];
-  red[tid] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-    __syncthreads();
-  }
-  int e = 0;
-  if (red[0] > 0.0) (void)frexp(red[0], &e);  // max|x| < 2^e
-  if (tid == 0) ex[r] = e;
-  for (int k0 = tid * 8; k0 < Kp; k0 += 256 * 8) {
-    __bf16 d[8][S];
+  for (int base = 0; base < Kp; base += 256 * 8) {
+    const int k0 = base + tid * 8;
+    const int cstart = base + (tid & ~15) * 8;  // first index of this lane's chunk
+    if (cstart >= Kp) break;                    // the chunk's 16 lanes leave together
+    double x[8];
+    double m = 0.0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = k0 + j;
-      const double x = (r < R && k < K) ? row[k] : 0.0;
-      digits<S>(ldexp(x, -e), d[j]);
+      x[j] = (r < R && k < K) ? row[k] : 0.0;
+      m = fmax(m, fabs(x[j]));
     }
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, 16));
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);  // max|x| < 2^e over the chunk
+    if ((tid & 15) == 0) ex[(cstart / kExpChunk) * (long long)ex_stride + r] = e;
+    if (k0 >= Kp) continue;
+    __bf16 d[8][S];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) digits<S>(ldexp(x[j], -e), d[j]);
 #pragma unroll
     for (int p = 0; p < S; ++p) {
       bf16x8 v;
@@ -138,10 +151,12 @@ __global__ __launch_bounds__(256) void slice_rc_kernel(const double* __restrict_
 struct SplitArgs {
   const __bf16* A;   // [S][rows][Kp] digits, row 0 = this product's first row
   long long sa;      // slice stride of A
-  const int* ea;     // exponents of A's rows (same row origin)
+  const int* ea;     // exponents of A's rows (same row origin); with chunk exponents
+                     // ea[c * ea_stride + m] for K-chunk c
   const __bf16* B;
   long long sb;
   const int* eb;
+  int ea_stride, eb_stride;
   int M, N, Kp;
   void* C;           // EPI_ACC: float64 C[m*ldc + n] +=; EPI_PERM: float64 integral block
   long long ldc;
@@ -149,8 +164,8 @@ struct SplitArgs {
   int tiles_m, tiles_n, group_m;
 };
 
-// 256 threads = 4 waves in 2x2; wave tile 32 x 64 = 2 x 4 blocks of 16x16.
-// Slice products (p, q) (0-based) are kept when p + q < S + D - 1: D = 1 is the
+// Workgroup tile 64 x 128 (M x N), K-steps of 32 (one bf16 MFMA depth).  Slice
+// products (p, q) (0-based) are kept when p + q < S + D - 1: D = 1 is the
 // triangle p'+q' <= S+1 of 1-based slices, D = 2 adds its next anti-diagonal.
 //
 // Operand tiles go from global memory straight into LDS (global_load_lds_dwordx4:
@@ -174,196 +189,47 @@ __device__ __forceinline__ void wait_vm(int n) {
   case N:         \
     __builtin_amdgcn_s_waitcnt(((N)&15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14)); \
     break;
-    CCL_VM(0) CCL_VM(6) CCL_VM(9) CCL_VM(12)
+    CCL_VM(0) CCL_VM(3) CCL_VM(6) CCL_VM(9) CCL_VM(12)
 #undef CCL_VM
     default:
       __builtin_amdgcn_s_waitcnt(7 << 4 | 15 << 8);
   }
 }
 
-template <int S, int D, int EPI>
-__global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs g) {
-  constexpr int NG = S + D - 1;                          // anti-diagonals kept
-  constexpr int A_BYTES = S * kSBM * kRowBytes;          // one stage of A digits
-  constexpr int B_BYTES = S * kSBN * kRowBytes;
-  constexpr int STAGE = A_BYTES + B_BYTES;
-  constexpr int LOADS = 3 * S;                           // load instructions per wave per stage
-  static_assert(kStages * STAGE <= 160 * 1024, "LDS");
-  __shared__ __attribute__((aligned(1024))) unsigned char lds[kStages * STAGE];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = (wave >> 1) * 32;
-  const int wn = (wave & 1) * 64;
-  int tm, tn;
-  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
-  const int m0 = tm * kSBM, n0 = tn * kSBN;
-
-  // this lane's element offset inside any 16-row slab (row lane/4, swizzled chunk)
-  const int lrow = lane >> 2;
-  const int lchunk = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
-  const long long loff = (long long)lrow * g.Kp + lchunk * 8;
-  const __bf16* pa = g.A + (long long)(m0 + 16 * wave) * g.Kp + loff;
-  const __bf16* pb = g.B + (long long)(n0 + 16 * wave) * g.Kp + loff;
-  const long long b_half = 64LL * g.Kp;
-  // LDS byte offsets (wave-uniform) of this wave's slabs inside a stage
-  const int la = 16 * wave * kRowBytes;
-  const int lb = A_BYTES + 16 * wave * kRowBytes;
-
-  auto issue = [&](int kt) {
-    unsigned char* st = lds + (kt % kStages) * STAGE;
-    const int ko = kt * kSBK;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      __builtin_amdgcn_global_load_lds((const void*)(pa + s * g.sa + ko),
-                                       (lds_void_t*)(st + la + s * kSBM * kRowBytes), 16, 0, 0);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        __builtin_amdgcn_global_load_lds(
-            (const void*)(pb + s * g.sb + h * b_half + ko),
-            (lds_void_t*)(st + lb + (s * kSBN + 64 * h) * kRowBytes), 16, 0, 0);
-    }
-  };
-
-  f64x4 acc64[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
-
-  // fragment read: row (lane & 15) of a 16-row block, logical chunk lane >> 4
-  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
-  const int nk = g.Kp / kSBK;
-  issue(0);
-  if (nk > 1) issue(1);
-  // One exact chunk (kChunkSteps K-steps) per trip: its float32 anti-diagonal
-  // sums start at zero, stay in MFMA accumulators and are drained at its end.
-  for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
-    f32x4 acc[NG][2][4];
-#pragma unroll
-    for (int q = 0; q < NG; ++q)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[q][i][j] = f32x4{0, 0, 0, 0};
-#pragma unroll
-    for (int u = 0; u < kChunkSteps; ++u) {
-      const int kt = k0 + u;
-      if (kt < nk) {
-        wait_vm(kt + 1 < nk ? LOADS : 0);  // this wave's loads of step kt have landed
-        __builtin_amdgcn_s_barrier();      // ... and every wave's; step kt-1 is consumed
-        if (kt + 2 < nk) issue(kt + 2);
-        const unsigned char* st = lds + (kt % kStages) * STAGE;
-        bf16x8 fa[S][2], fb[S][4];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-            fa[s][i] = *reinterpret_cast<const bf16x8*>(
-                st + (s * kSBM + wm + 16 * i) * kRowBytes + frag_off);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            fb[s][j] = *reinterpret_cast<const bf16x8*>(
-                st + A_BYTES + (s * kSBN + wn + 16 * j) * kRowBytes + frag_off);
-        }
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-          for (int q = 0; q < S; ++q) {
-            if (p + q > NG - 1) continue;
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-              for (int j = 0; j < 4; ++j)
-                acc[p + q][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    fa[p][i], fb[q][j], acc[p + q][i][j], 0, 0, 0);
-          }
-      }
-    }
-    // exact float32 anti-diagonal sums -> float64, scaled by 2^(-8*(q+2))
-    double scale = 1.0 / 65536.0;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc64[i][j][r] = fma(static_cast<double>(acc[q][i][j][r]), scale, acc64[i][j][r]);
-      scale *= 1.0 / 256.0;
-    }
-  }
-
-  // Epilogue: lane holds column lane%16, rows 4*(lane/16)+r of each block.
-  const long long v = g.v;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int n = n0 + wn + 16 * j + (lane & 15);
-    if (n >= g.N) continue;
-    const int en = g.eb[n];
-    long long ncol = n;
-    if (EPI == EPI_PERM) {
-      const int y = n / g.v, d = n - y * g.v;
-      ncol = (long long)y * v * v + d;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-        if (m >= g.M) continue;
-        const double val = ldexp(acc64[i][j][r], g.ea[m] + en);
-        if (EPI == EPI_ACC) {
-          static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
-        } else {
-          const int a = m / g.v, x = m - a * g.v;
-          static_cast<double*>(g.C)[(long long)a * v * v * v + ncol + (long long)x * v] = val;
-        }
-      }
-  }
-}
-
-// Same product with 8 waves: waves w and w+4 own the same 32 x 64 sub-tile; wave
-// w accumulates the anti-diagonals [0, G0) (slices below G0 only), wave w+4 the
-// anti-diagonals [G0, NG).  Each half fits 256 registers, so two waves share a
-// SIMD and hide each other's LDS and memory latency; their float64 partial sums
-// are added through LDS before the epilogue.
-template <int S, int D>
-struct GroupSplit {
-  static constexpr int NG = S + D - 1;
-  static constexpr int pairs(int q) { return (q < S ? q + 1 : 2 * S - 1 - q); }
-  static constexpr int count(int lo, int hi) { return lo >= hi ? 0 : pairs(lo) + count(lo + 1, hi); }
-  static constexpr int larger(int g) { return count(0, g) > count(g, NG) ? count(0, g) : count(g, NG); }
-  // split point in [1, NG) that minimises the larger half's products
-  static constexpr int pick(int g, int best) {
-    return g >= NG ? best : pick(g + 1, larger(g) < larger(best) ? g : best);
-  }
-  static constexpr int G0 = pick(1, 1);
-  static_assert(G0 >= 1 && G0 < NG, "both halves hold products");
-};
-
-template <int S, int D, int EPI>
-__global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
+// Slice-pair GEMM.  Every wave owns a sub-tile and all NG anti-diagonal
+// accumulators of it: WAVES = 8 (two per SIMD, 32 x 32 sub-tiles of 2 x 2
+// blocks; S = 2 and 4) or WAVES = 4 (one per SIMD with up to 512 registers,
+// 64 x 32 sub-tiles of 4 x 2 blocks; S = 3, whose stage does not split 8 ways).
+// Per K-step a wave reads the S slices of its column blocks once and streams the
+// S slices of its row blocks; the exact float32 sums of a chunk are drained into
+// float64 with their scale 2^(-8g), and the epilogue applies 2^(eA + eB).
+// Measured at c3 (S = 4): 48% of the bf16 MFMA peak; with the operand loads
+// removed (a timing experiment) 67%, so a third of the time is the global->LDS
+// pipeline and the rest LDS reads, drains and barriers.  Splitting the products
+// of a sub-tile over two waves (fewer registers, larger sub-tiles) or one wave
+// per SIMD (64 x 32 sub-tiles) measured the same or slower.
+template <int S, int D, int EPI, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) {
+  constexpr bool CE = EPI == EPI_ACC;  // the contraction's operands carry chunk exponents
   constexpr int NG = S + D - 1;
-  constexpr int G0 = GroupSplit<S, D>::G0;
+  constexpr int MI = WAVES == 8 ? 2 : 4;   // row blocks per wave
+  constexpr int NJ = 2;                    // column blocks per wave
+  constexpr int WCOLS = kSBN / (16 * NJ);  // waves along N (4)
   constexpr int A_BYTES = S * kSBM * kRowBytes;
   constexpr int B_BYTES = S * kSBN * kRowBytes;
   constexpr int STAGE = A_BYTES + B_BYTES;
   constexpr int ASLABS = S * kSBM / 16, BSLABS = S * kSBN / 16;  // 16-row slabs per stage
-  constexpr int LOADS = (ASLABS + BSLABS) / 8;                    // per wave
-  static_assert((ASLABS % 8) == 0 && (BSLABS % 8) == 0, "slab split");
+  constexpr int LOADS = (ASLABS + BSLABS) / WAVES;                // per wave
+  static_assert((ASLABS % WAVES) == 0 && (BSLABS % WAVES) == 0, "slab split");
+  static_assert(WCOLS * (WAVES / WCOLS) == WAVES && (WAVES / WCOLS) * MI * 16 == kSBM, "wave grid");
   static_assert(kStages * STAGE <= 160 * 1024, "LDS");
-  static_assert(4 * 64 * 32 * 8 <= kStages * STAGE, "reduction buffer");
   __shared__ __attribute__((aligned(1024))) unsigned char lds[kStages * STAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int sub = wave & 3, half = wave >> 2;
-  const int wm = (sub >> 1) * 32;
-  const int wn = (sub & 1) * 64;
+  const int wm = (wave / WCOLS) * (16 * MI);
+  const int wn = (wave % WCOLS) * (16 * NJ);
   int tm, tn;
   tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   const int m0 = tm * kSBM, n0 = tn * kSBN;
@@ -375,41 +241,41 @@ __global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
     unsigned char* st = lds + (kt % kStages) * STAGE;
     const int ko = kt * kSBK;
 #pragma unroll
-    for (int j = 0; j < ASLABS / 8; ++j) {
-      const int ai = wave + 8 * j, s = ai / (kSBM / 16), r = ai % (kSBM / 16);
+    for (int j = 0; j < ASLABS / WAVES; ++j) {
+      const int ai = wave + WAVES * j, s = ai / (kSBM / 16), r = ai % (kSBM / 16);
       __builtin_amdgcn_global_load_lds(
           (const void*)(g.A + s * g.sa + (long long)(m0 + 16 * r) * g.Kp + loff + ko),
           (lds_void_t*)(st + (s * kSBM + 16 * r) * kRowBytes), 16, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < BSLABS / 8; ++j) {
-      const int bi = wave + 8 * j, s = bi / (kSBN / 16), r = bi % (kSBN / 16);
+    for (int j = 0; j < BSLABS / WAVES; ++j) {
+      const int bi = wave + WAVES * j, s = bi / (kSBN / 16), r = bi % (kSBN / 16);
       __builtin_amdgcn_global_load_lds(
           (const void*)(g.B + s * g.sb + (long long)(n0 + 16 * r) * g.Kp + loff + ko),
           (lds_void_t*)(st + A_BYTES + (s * kSBN + 16 * r) * kRowBytes), 16, 0, 0);
     }
   };
 
-  f64x4 acc64[2][4];
+  f64x4 acc64[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
+    for (int j = 0; j < NJ; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
 
   const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
   const int nk = g.Kp / kSBK;
 
-  // One exact chunk of this wave's anti-diagonals [LO, HI) (slices < SL needed).
-  auto run_chunk = [&](int k0, auto lo_c, auto hi_c) {
-    constexpr int LO = decltype(lo_c)::value, HI = decltype(hi_c)::value;
-    constexpr int SL = (HI - 1) < S ? HI : S;  // slices with index < SL can appear
-    f32x4 acc[HI - LO][2][4];
+  issue(0);
+  if (nk > 1) issue(1);
+  for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
+    // one exact chunk: float32 sums of every anti-diagonal
+    f32x4 acc[NG][MI][NJ];
 #pragma unroll
-    for (int q = 0; q < HI - LO; ++q)
+    for (int q = 0; q < NG; ++q)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[q][i][j] = f32x4{0, 0, 0, 0};
+        for (int j = 0; j < NJ; ++j) acc[q][i][j] = f32x4{0, 0, 0, 0};
 #pragma unroll
     for (int u = 0; u < kChunkSteps; ++u) {
       const int kt = k0 + u;
@@ -418,96 +284,95 @@ __global__ __launch_bounds__(512, 1) void split_gemm2_kernel(SplitArgs g) {
         __builtin_amdgcn_s_barrier();
         if (kt + 2 < nk) issue(kt + 2);
         const unsigned char* st = lds + (kt % kStages) * STAGE;
-        bf16x8 fa[SL][2], fb[SL][4];
+        bf16x8 fb[S][NJ];
 #pragma unroll
-        for (int sl = 0; sl < SL; ++sl) {
+        for (int q = 0; q < S; ++q)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
-            fa[sl][i] = *reinterpret_cast<const bf16x8*>(
-                st + (sl * kSBM + wm + 16 * i) * kRowBytes + frag_off);
+          for (int j = 0; j < NJ; ++j)
+            fb[q][j] = *reinterpret_cast<const bf16x8*>(
+                st + A_BYTES + (q * kSBN + wn + 16 * j) * kRowBytes + frag_off);
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            fb[sl][j] = *reinterpret_cast<const bf16x8*>(
-                st + A_BYTES + (sl * kSBN + wn + 16 * j) * kRowBytes + frag_off);
-        }
+        for (int p = 0; p < S; ++p) {
+          if (p >= NG) continue;
+          bf16x8 fa[MI];
 #pragma unroll
-        for (int p = 0; p < SL; ++p)
+          for (int i = 0; i < MI; ++i)
+            fa[i] = *reinterpret_cast<const bf16x8*>(st + (p * kSBM + wm + 16 * i) * kRowBytes +
+                                                     frag_off);
 #pragma unroll
-          for (int q = 0; q < SL; ++q) {
-            if (p + q < LO || p + q >= HI) continue;
+          for (int q = 0; q < S; ++q) {
+            if (p + q >= NG) continue;
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                acc[p + q - LO][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    fa[p][i], fb[q][j], acc[p + q - LO][i][j], 0, 0, 0);
+              for (int j = 0; j < NJ; ++j)
+                acc[p + q][i][j] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[q][j], acc[p + q][i][j], 0, 0, 0);
           }
+        }
       }
     }
-    double scale = 1.0 / 65536.0;
+    if constexpr (CE) {
+      // this chunk's row and column scales 2^eA, 2^eB; the groups are first
+      // combined at unit scale, then scaled once per element
+      const int c = k0 / kChunkSteps;
+      double sa[MI][4], sb[NJ];
 #pragma unroll
-    for (int q = 0; q < LO; ++q) scale *= 1.0 / 256.0;
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int q = 0; q < HI - LO; ++q) {
+        for (int r = 0; r < 4; ++r)
+          sa[i][r] = ldexp(1.0, g.ea[(long long)c * g.ea_stride + m0 + wm + 16 * i + 4 * (lane >> 4) + r]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < NJ; ++j)
+        sb[j] = ldexp(1.0, g.eb[(long long)c * g.eb_stride + n0 + wn + 16 * j + (lane & 15)]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc64[i][j][r] = fma(static_cast<double>(acc[q][i][j][r]), scale, acc64[i][j][r]);
-      scale *= 1.0 / 256.0;
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double u = 0.0, scale = 1.0 / 65536.0;
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+              u = fma(static_cast<double>(acc[q][i][j][r]), scale, u);
+              scale *= 1.0 / 256.0;
+            }
+            acc64[i][j][r] = fma(u, sa[i][r] * sb[j], acc64[i][j][r]);
+          }
+    } else {
+      double scale = 1.0 / 65536.0;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              acc64[i][j][r] = fma(static_cast<double>(acc[q][i][j][r]), scale, acc64[i][j][r]);
+        scale *= 1.0 / 256.0;
+      }
     }
-  };
-
-  issue(0);
-  if (nk > 1) issue(1);
-  for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
-    if (half == 0)
-      run_chunk(k0, std::integral_constant<int, 0>{}, std::integral_constant<int, G0>{});
-    else
-      run_chunk(k0, std::integral_constant<int, G0>{}, std::integral_constant<int, NG>{});
   }
-
-  // add the upper anti-diagonals' sums (waves 4..7) into waves 0..3
-  __builtin_amdgcn_s_barrier();  // every wave is done reading the operand stages
-  // lane-contiguous: each store or load of the 64 lanes touches 512 consecutive bytes
-  double* red = reinterpret_cast<double*>(lds) + sub * 64 * 32 + lane;
-  if (half == 1) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[((i * 4 + j) * 4 + r) * 64] = acc64[i][j][r];
-  }
-  __syncthreads();
-  if (half == 1) return;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[i][j][r] += red[((i * 4 + j) * 4 + r) * 64];
 
   const long long v = g.v;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NJ; ++j) {
     const int n = n0 + wn + 16 * j + (lane & 15);
     if (n >= g.N) continue;
-    const int en = g.eb[n];
+    const int en = CE ? 0 : g.eb[n];
     long long ncol = n;
     if (EPI == EPI_PERM) {
       const int y = n / g.v, d = n - y * g.v;
       ncol = (long long)y * v * v + d;
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         if (m >= g.M) continue;
-        const double val = ldexp(acc64[i][j][r], g.ea[m] + en);
+        const double val = CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], g.ea[m] + en);
         if (EPI == EPI_ACC) {
           static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
         } else {
@@ -527,12 +392,9 @@ int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
   const long long tiles = (long long)a.tiles_m * a.tiles_n;
   if (tiles > 0x7fffffffLL) return CC_LADDER_EINVAL;
   a.group_m = a.tiles_m < 16 ? a.tiles_m : 16;
-  if constexpr (S == 4)  // enough products for both halves of the 8-wave kernel
-    hipLaunchKernelGGL((split_gemm2_kernel<S, D, EPI>), dim3(static_cast<unsigned>(tiles)),
-                       dim3(512), 0, s, a);
-  else
-    hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI>), dim3(static_cast<unsigned>(tiles)),
-                       dim3(256), 0, s, a);
+  constexpr int W = (S == 3) ? 4 : 8;  // 8 waves need the slabs of a stage to split 8 ways
+  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, W>), dim3(static_cast<unsigned>(tiles)),
+                     dim3(64 * W), 0, s, a);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -540,7 +402,7 @@ template <int S>
 int slice_kc(const double* X, long long ld, int R, int K, const SliceDims& d, __bf16* out, int* ex,
              hipStream_t s) {
   hipLaunchKernelGGL((slice_kc_kernel<S>), dim3(d.rows_pad), dim3(256), 0, s, X, ld, R, K, d.k_pad,
-                     (long long)d.rows_pad * d.k_pad, out, ex);
+                     (long long)d.rows_pad * d.k_pad, out, ex, d.rows_pad);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -586,6 +448,7 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
     SplitArgs b{};
     b.A = Ls + r0 * dL.k_pad; b.sa = sL; b.ea = Le + r0;
     b.B = Ls; b.sb = sL; b.eb = Le;
+    b.ea_stride = b.eb_stride = 0;  // one exponent per row
     b.M = na * v; b.N = static_cast<int>(v2); b.Kp = dL.k_pad;
     b.C = V; b.ldc = 0; b.v = v;
     tr(CC_LADDER_PHASE_BUILD, blk, 0);
@@ -599,6 +462,8 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
     SplitArgs c{};
     c.A = ts; c.sa = st; c.ea = te;
     c.B = Vs; c.sb = sV; c.eb = Ve;
+    c.ea_stride = dt.rows_pad;  // exponents per (row, chunk)
+    c.eb_stride = dV.rows_pad;
     c.M = o * o; c.N = na * v; c.Kp = dt.k_pad;
     c.C = R + r0; c.ldc = v2; c.v = v;
     tr(CC_LADDER_PHASE_CONTRACT, blk, 0);

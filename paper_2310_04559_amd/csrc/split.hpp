@@ -16,6 +16,11 @@ struct SliceDims {
   int k_pad;
 };
 
+// Contracted indices per exponent of the contraction's digit rows (one exact
+// float32 chunk of the slice-pair GEMM).
+constexpr int kExpChunk = 128;
+inline int exp_chunks(int k_pad) { return (k_pad + kExpChunk - 1) / kExpChunk; }
+
 inline SliceDims slice_dims(long long rows, int K) {
   SliceDims d;
   d.rows_pad = static_cast<int>((rows + 127) / 128 * 128 + 128);

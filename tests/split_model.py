@@ -1,13 +1,34 @@
 """NumPy model of the split-bf16 digit arithmetic (test-side reference for the
-scheme, not for the ladder): per-row exponents, balanced base-256 digits,
-slice products (p, q) kept when p + q <= S + D (1-based), exact integer sums.
-Used to check that the GPU kernels implement exactly this scheme; the scheme's
-own error is measured against the float64 oracle."""
+scheme, not for the ladder): exponents per row (the integral build) or per
+(row, chunk of 128 contracted indices) (the amplitude contraction), balanced
+base-256 digits, slice products (p, q) kept when p + q <= S + D (1-based),
+exact integer sums per chunk.  Used to check that the GPU kernels implement
+exactly this scheme; the scheme's own error is measured against the float64
+oracle."""
 import numpy as np
 
 
-def digits(X, S):
-    """Rows of X along axis 1 -> (list of S digit arrays, row exponents)."""
+CHUNK = 128
+
+
+def digits(X, S, chunk=0):
+    """Rows of X along axis 1 -> (list of S digit arrays, exponents): one
+    exponent per row, or with ``chunk`` one per (row, chunk) as ``e[row][c]``."""
+    if chunk:
+        R, K = X.shape
+        nc = (K + chunk - 1) // chunk
+        Xp = np.zeros((R, nc * chunk))
+        Xp[:, :K] = X
+        m = np.max(np.abs(Xp.reshape(R, nc, chunk)), axis=2)
+        e = np.where(m > 0, np.frexp(m)[1], 0)
+        y = np.ldexp(Xp.reshape(R, nc, chunk), -e[:, :, None]).reshape(R, nc * chunk)[:, :K]
+        D = []
+        for _ in range(S):
+            y = y * 256.0
+            q = np.rint(y)
+            y = y - q
+            D.append(q)
+        return D, e
     m = np.max(np.abs(X), axis=1)
     e = np.where(m > 0, np.frexp(m)[1], 0)
     y = np.ldexp(X, -e[:, None])
@@ -20,11 +41,22 @@ def digits(X, S):
     return D, e
 
 
-def product(A, B, S, depth):
+def product(A, B, S, depth, chunk=0):
     """C = A @ B.T through the digit scheme (integer digit sums are exact in float64)."""
-    Da, ea = digits(A, S)
-    Db, eb = digits(B, S)
+    Da, ea = digits(A, S, chunk)
+    Db, eb = digits(B, S, chunk)
     C = np.zeros((A.shape[0], B.shape[0]))
+    if chunk:
+        K = A.shape[1]
+        for c in range((K + chunk - 1) // chunk):
+            sl = slice(c * chunk, min(K, (c + 1) * chunk))
+            Cc = np.zeros_like(C)
+            for p in range(S):
+                for q in range(S):
+                    if (p + 1) + (q + 1) <= S + depth:
+                        Cc += (Da[p][:, sl] @ Db[q][:, sl].T) * 2.0 ** (-8 * (p + q + 2))
+            C += Cc * np.ldexp(1.0, ea[:, c][:, None] + eb[:, c][None, :])
+        return C
     for p in range(S):
         for q in range(S):
             if (p + 1) + (q + 1) <= S + depth:
@@ -39,7 +71,7 @@ def ladder(L, t, S, depth):
     Lr = L.reshape(P, v * v).T                           # rows (p,q) along x
     V = product(Lr, Lr, S, depth)                         # [(a,c)][(b,d)]
     V = V.reshape(v, v, v, v).transpose(0, 2, 1, 3).reshape(v * v, v * v)  # [(a,b)][(c,d)]
-    R = product(t.reshape(o * o, v * v), V, S, depth)     # [(i,j)][(a,b)]
+    R = product(t.reshape(o * o, v * v), V, S, depth, CHUNK)  # [(i,j)][(a,b)]
     return R.reshape(o, o, v, v)
 
 

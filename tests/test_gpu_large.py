@@ -1,8 +1,9 @@
 """The large single-GPU workload (o=60, v=600, P=1800): t and R are 10.4 GB
 each, L 5.2 GB, the integral-block size is chosen by the planner.  The oracle
 checks sampled R[:, :, a, b] columns (43200 entries) and two complete rows
-R[i, j, :, :]; the adjoint is checked through identities that hold at any size
-and against the float64 adjoint."""
+R[i, j, :, :]; the split form is also held to its tolerance over the whole
+tensor against the float64 path; the adjoint is checked through identities that
+hold at any size and against the float64 adjoint."""
 import numpy as np
 import pytest
 import torch
@@ -50,16 +51,25 @@ def test_large_forward_fp64_and_split(gpu_lib, large):
     ia = torch.tensor([a for a, _ in pairs], device="cuda")
     ib = torch.tensor([b for _, b in pairs], device="cuda")
     R = torch.zeros_like(t)
+    R64 = None
     for prec, tol in ((0, TOL[0]), (2, TOL_SPLIT_WORKLOAD[4])):
         announce("large-forward", prec)
         R.zero_()
         gpu_lib.cc_ladder_residual(L, t, R, prec)
         torch.cuda.synchronize()
+        if prec == 0:
+            R64 = R.clone()
+        else:
+            whole = _tnorm(R - R64) / _tnorm(R64)
+            print("CASE large-forward whole-tensor error vs float64 path", prec, whole, flush=True)
+            assert whole < tol, (prec, whole)
         got = host(R[:, :, ia, ib].permute(2, 0, 1))
+        errs = [rel_fro(host(R[i, j]), want) for (i, j), want in zip(large["rows"], large["ref_rows"])]
+        print("CASE large-forward errors", prec, rel_fro(got, ref), errs, flush=True)
         assert rel_fro(got, ref) < tol, prec
-        for (i, j), want in zip(large["rows"], large["ref_rows"]):
-            assert rel_fro(host(R[i, j]), want) < tol, (prec, i, j)
-    del R
+        for (i, j), e in zip(large["rows"], errs):
+            assert e < tol, (prec, i, j, e)
+    del R, R64
 
 
 def test_large_adjoint_fp32_vs_fp64_and_euler(gpu_lib, large):

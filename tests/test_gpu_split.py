@@ -88,12 +88,22 @@ def test_split_full_size_sampled_entries(gpu_lib, name):
     ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
     ia = torch.tensor([a for a, _ in pairs], device="cuda")
     ib = torch.tensor([b for _, b in pairs], device="cuda")
+    # the whole tensor against the float64 path (itself checked against the
+    # oracle on the same columns)
+    R64 = torch.zeros_like(td)
+    gpu_lib.cc_ladder_residual(Ld, td, R64, 0)
+    torch.cuda.synchronize()
+    assert rel_fro(host(R64[:, :, ia, ib].permute(2, 0, 1)), ref) < 1e-12
+    n64 = float(torch.linalg.vector_norm(R64))
     for slices in (2, 4):
         R = torch.zeros_like(td)
         gpu_lib.cc_ladder_residual(Ld, td, R, SPLIT, opts=gpu_lib.make_opts(split_slices=slices))
         torch.cuda.synchronize()
         got = host(R[:, :, ia, ib].permute(2, 0, 1))
+        whole = float(torch.linalg.vector_norm(R - R64)) / n64
+        print("CASE split-full errors", name, slices, rel_fro(got, ref), whole, flush=True)
         assert rel_fro(got, ref) < TOL_SPLIT_WORKLOAD[slices], (name, slices)
+        assert whole < TOL_SPLIT_WORKLOAD[slices], (name, slices, whole)
         del R
 
 
