@@ -119,6 +119,7 @@ def test_full_size_sampled_entries(gpu_lib, name):
     ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
     idx_a = torch.tensor([a for a, _ in pairs], device="cuda")
     idx_b = torch.tensor([b for _, b in pairs], device="cuda")
+    R64 = None
     for precision in (0, 1):
         R = torch.zeros_like(td)
         gpu_lib.cc_ladder_residual(Ld, td, R, precision)
@@ -129,7 +130,14 @@ def test_full_size_sampled_entries(gpu_lib, name):
         Rt = R.permute(1, 0, 3, 2)
         asym = float(torch.linalg.vector_norm(R - Rt) / torch.linalg.vector_norm(R))
         assert asym < 10 * TOL[precision]
-        del R
+        if precision == 0:
+            R64 = R
+        else:
+            # the whole tensor against the float64 path checked above
+            whole = float(torch.linalg.vector_norm(R - R64) / torch.linalg.vector_norm(R64))
+            print("CASE forward-full whole-tensor error", name, precision, whole, flush=True)
+            assert whole < TOL[precision], (name, precision, whole)
+            del R
 
 
 def test_reduce_matches_oracle(gpu_lib):
