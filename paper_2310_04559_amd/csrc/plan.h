@@ -36,13 +36,12 @@ struct Plan {
   int k_splits = 1;     // intermediates: K ranges of the contraction (split K when its tile
                         // grid alone leaves compute units idle)
   size_t off_part = 0;  // float64 partials of the split contraction [k_splits][o^2][n_a*o]
-  size_t off_Lexp = 0, off_texp = 0, off_lamexp = 0;
+  size_t off_Lexp = 0, off_texp = 0;
   // per-block buffers
   size_t off_V = 0;     // float64 or float32 integral block [n_a][v][v][v]
   size_t off_W = 0;     // adjoint block W'[n_a][v][v][v] (backward)
   size_t off_Vs = 0;    // bf16 slices of the integral block
-  size_t off_Vexp = 0;  // per-row exponents of the integral block
-  size_t off_Ws = 0, off_Wexp = 0;
+  size_t off_Vexp = 0;  // exponents of the integral block's digit rows, per (row, chunk)
   size_t off_tiles = 0; // packed build: first tile of every tile row (int32, tiles_m + 1)
   size_t bytes = 0;     // total scratch
 };
