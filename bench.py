@@ -263,11 +263,14 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32")):
     flops = (6.0 * P + 4.0 * o * o) * float(v) ** 4
     res = {"workload": f"o={o},v={v},P={P}", "nominal_tflop": flops / 1e12}
     ref = None
+    stream = torch.cuda.current_stream()
     for form in forms:
         prec = native.PRECISIONS[form]
+        timer = PhaseTimer(native, stream)
+        opts = native.make_opts(trace=timer.fn)
         dL = torch.zeros_like(L)
         dt = torch.zeros_like(t)
-        native.cc_ladder_backward(L, t, lam, dL, dt, prec)  # warm-up, also the result
+        native.cc_ladder_backward(L, t, lam, dL, dt, prec, opts=opts)  # warm-up, also the result
         torch.cuda.synchronize()
         if ref is None:
             ref = (dL.clone(), dt.clone())
@@ -275,15 +278,19 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32")):
         else:
             err = max(float(torch.linalg.vector_norm(dL - ref[0]) / torch.linalg.vector_norm(ref[0])),
                       float(torch.linalg.vector_norm(dt - ref[1]) / torch.linalg.vector_norm(ref[1])))
+        timer.reset()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(stream)
         for _ in range(steps):
-            native.cc_ladder_backward(L, t, lam, dL, dt, prec)
-        e1.record()
+            native.cc_ladder_backward(L, t, lam, dL, dt, prec, opts=opts)
+        e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res[form] = {"ms_per_step": ms, "tflops": flops / (ms * 1e-3) / 1e12,
-                     "rel_err_vs_fp64_gpu": err}
+                     "rel_err_vs_fp64_gpu": err,
+                     "phases_ms_per_step": {k: d["ms_total"] / steps for k, d in timer.summary().items()}}
+        log(f"adjoint {form}: {ms:.1f} ms {res[form]['tflops']:.1f} TFLOP/s "
+            f"phases {json.dumps(res[form]['phases_ms_per_step'])}")
         del dL, dt
     return res
 

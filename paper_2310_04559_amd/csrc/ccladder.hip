@@ -114,6 +114,24 @@ bool launch_rc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   return true;
 }
 
+// K-contiguous A times row-contiguous B, float64 accumulation: the mixed
+// direct-to-LDS kernel when rows are aligned and N is whole 16-byte chunks.
+template <class Tr>
+bool launch_kr_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, int* rc) {
+  if (!vec_ok(g0.A, g0.lda) || !vec_ok(g0.B, g0.ldb)) return false;
+  if (g0.N % Tr::CH != 0 || g0.K <= 0) return false;
+  GemmArgs<typename Tr::T> g = g0;
+  g.tiles_m = (g.M + kDBM - 1) / kDBM;
+  g.tiles_n = (g.N + kDBN - 1) / kDBN;
+  const long long tiles = (long long)g.tiles_m * g.tiles_n;
+  if (tiles > 0x7fffffffLL) return false;
+  g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
+  hipLaunchKernelGGL((gemm_kr_direct_kernel<Tr>), dim3(static_cast<unsigned>(tiles)),
+                     dim3(kDThreads), 0, stream, g);
+  *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+  return true;
+}
+
 // Offsets of the packed build's compact grid: row_tiles[tm] = number of needed
 // tiles in tile rows before tm (one thread; a few thousand rows at most).
 __global__ void pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v) {
@@ -166,6 +184,10 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   if constexpr (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
     int rc = CC_LADDER_OK;
     if (launch_kc_direct<Tr, EPI>(g, stream, &rc)) return rc;
+  }
+  if constexpr (LA == KC && LB == RC && EPI == EPI_ACC && Tr::kDirectKR) {
+    int rc = CC_LADDER_OK;
+    if (launch_kr_direct<Tr>(g, stream, &rc)) return rc;
   }
   if constexpr (LA == RC && LB == RC && EPI == EPI_PERM && Tr::kDirectRC) {
     int rc = CC_LADDER_OK;

@@ -440,3 +440,196 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
 }
 
 }  // namespace ccl
+
+namespace ccl {
+
+// Mixed-layout GEMM with direct global->LDS loads (gfx950): A K-contiguous, B
+// row-contiguous, float64 accumulation into C:
+//
+//   C[m*ldc + n] += sum_k A[m*lda + k] B[k*ldb + n]
+//
+// (the adjoint's dt and second dL term, the hole-hole ladder's contraction).  A is
+// staged like the K-contiguous kernel (8-row slabs of 128-byte rows, XOR-swizzled
+// chunks), B like the row-contiguous kernel (BK rows of 256 contiguous n, columns
+// of a wave's four blocks interleaved).  In MFMA step e of k-group gi, slot j of
+// both operands carries k = gi*4*CH + CH*j + e: A's lane reads its CH consecutive
+// k once per group, B's lane reads that k row's four (float32) or two-plus-two
+// (float64) interleaved columns once per step.  Needs 16-byte aligned rows, N a
+// multiple of the 16-byte chunk; rows past M are clamped, columns past N clamped
+// onto the last chunk (never stored), a ragged last K-step goes through registers
+// with zero fill.
+template <class Tr>
+__global__ __launch_bounds__(kDThreads, 1) void gemm_kr_direct_kernel(GemmArgs<typename Tr::T> g) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  using Chunk = typename Tr::Chunk;
+  constexpr int CH = Tr::CH;
+  constexpr int BK = kDRow / sizeof(T);          // 16 float64 / 32 float32
+  constexpr int ROWB = kDBN * sizeof(T);         // bytes of one k row of B (256 n)
+  constexpr int A_BYTES = kDBM * kDRow;          // 16 KB
+  constexpr int B_BYTES = BK * ROWB;             // 32 KB
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int AL = kDBM / 8 / 8;               // A: 8-row slabs per wave (2)
+  constexpr int BI = B_BYTES / 1024 / 8;         // B: 1 KB instructions per wave (4)
+  constexpr int LOADS = AL + BI;
+  constexpr int CPRB = kDBN / CH;                // 16-byte chunks per B row
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[kDStages * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = (wave >> 2) * 64;
+  const int wn = (wave & 3) * 64;
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  const int m0 = tm * kDBM, n0 = tn * kDBN;
+
+  // A: slabs of 8 rows, lane -> row lane/8, physical chunk lane%8 holding
+  // logical chunk (lane%8) ^ ((row/2)%8)
+  const int lrow = lane >> 3;
+  const int sw_even = ((lane & 7) ^ ((lane >> 4) & 7)) * CH;
+  const int sw_odd = ((lane & 7) ^ ((4 + (lane >> 4)) & 7)) * CH;
+  const int my_sw = (wave & 1) ? sw_odd : sw_even;
+  const T* pa[AL];
+#pragma unroll
+  for (int j = 0; j < AL; ++j) {
+    int row = m0 + 8 * (wave + 8 * j) + lrow;
+    row = row < g.M ? row : g.M - 1;
+    pa[j] = g.A + (long long)row * g.lda + my_sw;
+  }
+  // B: wave instruction q covers the 1 KB [q KB, q KB + 1 KB) of the stage's B slab
+  const T* pb[BI];
+  int rb[BI];
+#pragma unroll
+  for (int j = 0; j < BI; ++j) {
+    const int flat = (wave + 8 * j) * 64 + lane;
+    rb[j] = flat / CPRB;
+    int n = n0 + (flat % CPRB) * CH;
+    n = n < g.N ? n : g.N - CH;
+    pb[j] = g.B + (long long)rb[j] * g.ldb + n;
+  }
+  auto issue = [&](int kt) {
+    unsigned char* st = lds + (kt % kDStages) * STAGE;
+    const int ko = kt * BK;
+    const long long kb = (long long)ko * g.ldb;
+#pragma unroll
+    for (int j = 0; j < AL; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(pa[j] + ko),
+                                       (lds_void*)(st + 8 * (wave + 8 * j) * kDRow), 16, 0, 0);
+#pragma unroll
+    for (int j = 0; j < BI; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(pb[j] + kb),
+                                       (lds_void*)(st + A_BYTES + (wave + 8 * j) * 1024), 16, 0, 0);
+  };
+  auto issue_tail = [&](int kt) {
+    unsigned char* st = lds + (kt % kDStages) * STAGE;
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int j = 0; j < AL; ++j) {
+      const int kk = k0 + my_sw;  // this lane's first k
+      Chunk c;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) c[e] = (kk + e < g.K) ? pa[j][k0 + e] : T(0);
+      *reinterpret_cast<Chunk*>(st + 8 * (wave + 8 * j) * kDRow + 16 * lane) = c;
+    }
+    const long long kb = (long long)k0 * g.ldb;
+#pragma unroll
+    for (int j = 0; j < BI; ++j) {
+      Chunk c = {};
+      if (k0 + rb[j] < g.K) c = *reinterpret_cast<const Chunk*>(pb[j] + kb);
+      *reinterpret_cast<Chunk*>(st + A_BYTES + (wave + 8 * j) * 1024 + 16 * lane) = c;
+    }
+    __builtin_amdgcn_s_waitcnt(0xF | (7 << 4) | (3 << 14));  // lgkmcnt(0): the LDS writes landed
+  };
+
+  Acc acc[4][4];
+  f64x4 acc64[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = Acc{0, 0, 0, 0};
+      acc64[i][j] = f64x4{0, 0, 0, 0};
+    }
+
+  const int frow = (lane & 15) * kDRow;
+  const int fsw = (lane & 15) >> 1;
+  const int slot = lane >> 4;
+  const int r16 = lane & 15;
+  const int offb = (wn + (CH == 4 ? 4 * r16 : 2 * r16)) * (int)sizeof(T);
+  const int nk = (g.K + BK - 1) / BK;
+  const int nkf = g.K / BK;
+  auto stage_in = [&](int kt) {
+    if (kt < nkf)
+      issue(kt);
+    else
+      issue_tail(kt);
+  };
+  stage_in(0);
+  if (nk > 1) stage_in(1);
+  for (int k0 = 0; k0 < nk;) {
+    const int kend = (Tr::kDrain && k0 + g.drain_steps < nk) ? k0 + g.drain_steps : nk;
+    for (int kt = k0; kt < kend; ++kt) {
+      d_wait_vm(kt + 1 < nkf ? LOADS : 0);
+      __builtin_amdgcn_s_barrier();
+      if (kt + 2 < nk) stage_in(kt + 2);
+      const unsigned char* st = lds + (kt % kDStages) * STAGE;
+#pragma unroll
+      for (int gi = 0; gi < 2; ++gi) {
+        const int chunk = ((4 * gi + slot) ^ fsw) * 16;
+        Chunk fa[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          fa[i] = *reinterpret_cast<const Chunk*>(st + (wm + 16 * i) * kDRow + frow + chunk);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+          // k row gi*4*CH + CH*slot + e of B, this lane's interleaved columns
+          const unsigned char* rb_ = st + A_BYTES + (4 * CH * gi + CH * slot + e) * ROWB + offb;
+          T fb[4];
+          if constexpr (CH == 4) {
+            const Chunk b = *reinterpret_cast<const Chunk*>(rb_);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fb[j] = b[j];
+          } else {
+            const Chunk b0 = *reinterpret_cast<const Chunk*>(rb_);
+            const Chunk b1 = *reinterpret_cast<const Chunk*>(rb_ + 32 * sizeof(T));
+            fb[0] = b0[0]; fb[1] = b0[1]; fb[2] = b1[0]; fb[3] = b1[1];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][e], fb[j], acc[i][j]);
+        }
+      }
+    }
+    if (Tr::kDrain) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc64[i][j][r] += static_cast<double>(acc[i][j][r]);
+            acc[i][j][r] = 0;
+          }
+    }
+    k0 = kend;
+  }
+
+  double* C = static_cast<double*>(g.C);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn + rc_pos<Tr>(j, r16);
+    if (n >= g.N) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);
+        if (m >= g.M) continue;
+        C[(long long)m * g.ldc + n] += Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]);
+      }
+  }
+}
+
+}  // namespace ccl
