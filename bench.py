@@ -45,6 +45,7 @@ FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16_s2": ("split_bf16", 2, False, False),
          "split_bf16_s3": ("split_bf16", 3, False, False),
          "fp64_pairsym": ("fp64", 0, True, False), "fp32_pairsym": ("fp32", 0, True, False),
+         "split_bf16_pairsym": ("split_bf16", 4, True, False),
          "fp64_exchange": ("fp64", 0, False, True), "fp32_exchange": ("fp32", 0, False, True),
          "split_bf16_exchange": ("split_bf16", 4, False, True)}
 _PEAK = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}  # dense MFMA, TFLOP/s
@@ -431,7 +432,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2,fp64_pairsym,"
-                                       "fp64_exchange")
+                                       "split_bf16_pairsym,fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-intermediates", action="store_true")

@@ -70,8 +70,8 @@ typedef enum {
                                         doubles amplitudes).  The integral then enters only through
                                         its rows (a,b) with a <= b, stored packed, and each result
                                         is added at both R[i][j][a][b] and R[j][i][b][a]: half the
-                                        build and half the contraction.  FP64 and FP32 forward only;
-                                        ignored by the adjoint; EUNSUPPORTED with SPLIT_BF16. */
+                                        build and half the contraction.  Forward, every form; ignored
+                                        by the adjoint. */
 
 #define CC_LADDER_EXCHANGE 2u        /* evaluate the exchange partner instead (eq. vfunction2):
                                         R[i][j][a][b] += sum_{c,d} (ad|bc) t[i][j][c][d], i.e. the

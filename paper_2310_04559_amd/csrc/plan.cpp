@@ -58,7 +58,6 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   const size_t v2 = static_cast<size_t>(v) * v;
   const size_t o2 = static_cast<size_t>(o) * o;
   p.pairsym = (pairsym && !backward) ? 1 : 0;
-  if (p.pairsym && precision == CC_LADDER_SPLIT_BF16) return CC_LADDER_EUNSUPPORTED;
   // entries of one integral block: n_a*v rows (a,b); packed rows a <= b when the
   // amplitudes are pair-symmetric (the first block holds the most)
   const size_t rows = p.pairsym ? static_cast<size_t>(pair_prefix(n_a, v)) : static_cast<size_t>(n_a) * v;
@@ -91,7 +90,7 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       const size_t s = static_cast<size_t>(p.slices);
       const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
       const SliceDims dt = slice_dims(static_cast<long long>(o2), static_cast<int>(v2));
-      const SliceDims dV = slice_dims(static_cast<long long>(n_a) * v, static_cast<int>(v2));
+      const SliceDims dV = slice_dims(static_cast<long long>(rows), static_cast<int>(v2));
       p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad * 2);
       p.off_Lexp = take(&cur, static_cast<size_t>(dL.rows_pad) * sizeof(int));
       p.off_t = take(&cur, s * dt.rows_pad * dt.k_pad * 2);
@@ -105,8 +104,10 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       return CC_LADDER_EINVAL;
   }
   if (p.pairsym) {
-    // tile-row offsets of the packed build's compact grid (128-row tiles)
-    const size_t tiles_m = (static_cast<size_t>(n_a) * v + 127) / 128;
+    // tile-row offsets of the packed build's compact grid (128-row tiles; 64 rows
+    // in the split form)
+    const size_t bm = precision == CC_LADDER_SPLIT_BF16 ? 64 : 128;
+    const size_t tiles_m = (static_cast<size_t>(n_a) * v + bm - 1) / bm;
     p.off_tiles = take(&cur, (tiles_m + 1) * sizeof(int));
   }
   p.bytes = cur;

@@ -158,9 +158,13 @@ struct SplitArgs {
   const int* eb;
   int ea_stride, eb_stride;
   int M, N, Kp;
-  void* C;           // EPI_ACC: float64 C[m*ldc + n] +=; EPI_PERM: float64 integral block
+  void* C;           // EPI_ACC: float64 C[m*ldc + n] +=; EPI_PERM: float64 integral block;
+                     // EPI_PACK: packed rows a <= b of the block; EPI_PAIR: R (both mirrors)
   long long ldc;
   int v;
+  int o;             // EPI_PAIR: occupied count (rows are (i,j))
+  int a0;            // EPI_PACK/PAIR: first virtual of the integral block
+  const int* row_tiles;  // EPI_PACK compact grid: first linear tile of each tile row
   int tiles_m, tiles_n, group_m;
 };
 
@@ -210,7 +214,8 @@ __device__ __forceinline__ void wait_vm(int n) {
 // per SIMD (64 x 32 sub-tiles) measured the same or slower.
 template <int S, int D, int EPI, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) {
-  constexpr bool CE = EPI == EPI_ACC;  // the contraction's operands carry chunk exponents
+  // the contraction's operands carry chunk exponents
+  constexpr bool CE = EPI == EPI_ACC || EPI == EPI_PAIR;
   constexpr int NG = S + D - 1;
   constexpr int MI = WAVES == 8 ? 2 : 4;   // row blocks per wave
   constexpr int NJ = 2;                    // column blocks per wave
@@ -231,7 +236,19 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   const int wm = (wave / WCOLS) * (16 * MI);
   const int wn = (wave % WCOLS) * (16 * NJ);
   int tm, tn;
-  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  if (EPI == EPI_PACK) {
+    // compact grid over the tiles on or above the a = b diagonal
+    const int id = blockIdx.x;
+    int lo = 0, hi = g.tiles_m - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (g.row_tiles[mid] <= id) lo = mid; else hi = mid - 1;
+    }
+    tm = lo;
+    tn = pack_first_tile(tm, kSBM, kSBN, g.v) + (id - g.row_tiles[tm]);
+  } else {
+    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  }
   const int m0 = tm * kSBM, n0 = tn * kSBN;
 
   const int lrow = lane >> 2;
@@ -362,9 +379,17 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     if (n >= g.N) continue;
     const int en = CE ? 0 : g.eb[n];
     long long ncol = n;
+    int pa = 0, pb = 0;  // EPI_PACK: b - a0 and d; EPI_PAIR: a and b
     if (EPI == EPI_PERM) {
       const int y = n / g.v, d = n - y * g.v;
       ncol = (long long)y * v * v + d;
+    } else if (EPI == EPI_PACK) {
+      pa = n / g.v;
+      pb = n - pa * g.v;
+    } else if (EPI == EPI_PAIR) {
+      const long long q = pair_prefix_d(g.a0, v) + n;
+      pa = pair_row(q, g.v);
+      pb = pa + static_cast<int>(q - pair_prefix_d(pa, v));
     }
 #pragma unroll
     for (int i = 0; i < MI; ++i)
@@ -373,14 +398,40 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         if (m >= g.M) continue;
         const double val = CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], g.ea[m] + en);
+        double* C = static_cast<double*>(g.C);
         if (EPI == EPI_ACC) {
-          static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
-        } else {
+          C[(long long)m * g.ldc + n] += val;
+        } else if (EPI == EPI_PERM) {
           const int a = m / g.v, x = m - a * g.v;
-          static_cast<double*>(g.C)[(long long)a * v * v * v + ncol + (long long)x * v] = val;
+          C[(long long)a * v * v * v + ncol + (long long)x * v] = val;
+        } else if (EPI == EPI_PACK) {
+          // rows (a, c) of the block, columns (b, d) from b = a0; keep b >= a
+          const int al = m / g.v, c = m - al * g.v;
+          if (pa < al) continue;
+          const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (pa - al);
+          C[row * v * v + (long long)c * v + pb] = val;
+        } else {  // EPI_PAIR: R[i][j][a][b] and, for a != b, R[j][i][b][a]
+          C[(long long)m * g.ldc + (long long)pa * v + pb] += val;
+          if (pa != pb) {
+            const int ii = m / g.o, jj = m - ii * g.o;
+            C[(long long)(jj * g.o + ii) * g.ldc + (long long)pb * v + pa] += val;
+          }
         }
       }
   }
+}
+
+// Tile-row offsets of the packed build's compact grid (one thread; a few
+// thousand tile rows at most).
+__global__ void split_pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int acc = 0;
+  for (int tm = 0; tm < tiles_m; ++tm) {
+    row_tiles[tm] = acc;
+    const int first = pack_first_tile(tm, kSBM, kSBN, v);
+    acc += first < tiles_n ? tiles_n - first : 0;
+  }
+  row_tiles[tiles_m] = acc;
 }
 
 template <int S, int D, int EPI>
@@ -392,8 +443,21 @@ int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
   const long long tiles = (long long)a.tiles_m * a.tiles_n;
   if (tiles > 0x7fffffffLL) return CC_LADDER_EINVAL;
   a.group_m = a.tiles_m < 16 ? a.tiles_m : 16;
+  long long grid = tiles;
+  if (EPI == EPI_PACK) {
+    if (!a.row_tiles) return CC_LADDER_EINVAL;
+    long long needed = 0;
+    for (int tm = 0; tm < a.tiles_m; ++tm) {
+      const int first = pack_first_tile(tm, kSBM, kSBN, a.v);
+      needed += first < a.tiles_n ? a.tiles_n - first : 0;
+    }
+    if (needed <= 0) return CC_LADDER_OK;
+    hipLaunchKernelGGL(split_pack_rows_kernel, dim3(1), dim3(1), 0, s,
+                       const_cast<int*>(a.row_tiles), a.tiles_m, a.tiles_n, a.v);
+    grid = needed;
+  }
   constexpr int W = (S == 3) ? 4 : 8;  // 8 waves need the slabs of a stage to split 8 ways
-  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, W>), dim3(static_cast<unsigned>(tiles)),
+  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, W>), dim3(static_cast<unsigned>(grid)),
                      dim3(64 * W), 0, s, a);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
@@ -425,7 +489,9 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
   const long long v2 = (long long)v * v;
   const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
   const SliceDims dt = slice_dims((long long)o * o, static_cast<int>(v2));
-  const SliceDims dV = slice_dims((long long)pl.n_a * v, static_cast<int>(v2));
+  // integral rows of the largest block: n_a*v, or its packed rows a <= b
+  const SliceDims dV = slice_dims(pl.pairsym ? pair_prefix(pl.n_a, v) : (long long)pl.n_a * v,
+                                  static_cast<int>(v2));
   __bf16* Ls = reinterpret_cast<__bf16*>(ws + pl.off_L);
   int* Le = reinterpret_cast<int*>(ws + pl.off_Lexp);
   __bf16* ts = reinterpret_cast<__bf16*>(ws + pl.off_t);
@@ -445,6 +511,37 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
   for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
     const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
     const long long r0 = (long long)a0 * v;  // first (a,c) row of this block
+    if (pl.pairsym) {
+      // packed rows (a,b), b >= a: columns (b,d) from b = a0 on
+      const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
+      SplitArgs b{};
+      b.A = Ls + r0 * dL.k_pad; b.sa = sL; b.ea = Le + r0;
+      b.B = Ls + r0 * dL.k_pad; b.sb = sL; b.eb = Le + r0;
+      b.ea_stride = b.eb_stride = 0;
+      b.M = na * v; b.N = static_cast<int>((long long)(v - a0) * v); b.Kp = dL.k_pad;
+      b.C = V; b.ldc = 0; b.v = v; b.a0 = a0;
+      b.row_tiles = reinterpret_cast<const int*>(ws + pl.off_tiles);
+      tr(CC_LADDER_PHASE_BUILD, blk, 0);
+      rc = launch_split_gemm<S, D, EPI_PACK>(b, s);
+      tr(CC_LADDER_PHASE_BUILD, blk, 1);
+      if (rc) return rc;
+      tr(CC_LADDER_PHASE_SLICE, blk, 0);
+      rc = slice_kc<S>(V, v2, static_cast<int>(npairs), static_cast<int>(v2), dV, Vs, Ve, s);
+      tr(CC_LADDER_PHASE_SLICE, blk, 1);
+      if (rc) return rc;
+      SplitArgs c{};
+      c.A = ts; c.sa = st; c.ea = te;
+      c.B = Vs; c.sb = sV; c.eb = Ve;
+      c.ea_stride = dt.rows_pad;
+      c.eb_stride = dV.rows_pad;
+      c.M = o * o; c.N = static_cast<int>(npairs); c.Kp = dt.k_pad;
+      c.C = R; c.ldc = v2; c.v = v; c.o = o; c.a0 = a0;
+      tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
+      rc = launch_split_gemm<S, D, EPI_PAIR>(c, s);
+      tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
+      if (rc) return rc;
+      continue;
+    }
     SplitArgs b{};
     b.A = Ls + r0 * dL.k_pad; b.sa = sL; b.ea = Le + r0;
     b.B = Ls; b.sb = sL; b.eb = Le;

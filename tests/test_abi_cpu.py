@@ -90,9 +90,19 @@ def test_planner_pair_symmetric_footprint(native):
     tiles_m = (v * v + 127) // 128             # plus the compact build grid's row table
     assert half == rnd((v * (v + 1) // 2) * v * v * 8) + rnd((tiles_m + 1) * 4)
     assert full == rnd(v ** 4 * 8)
-    with pytest.raises(native.LadderError) as e:
-        native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(pair_symmetric=True))
-    assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+    # the split form: packed float64 block and packed digit rows, row table of
+    # its 64-row tiles
+    sfull, _ = native.cc_ladder_workspace_query(o, v, P, "split_bf16")
+    shalf, n3 = native.cc_ladder_workspace_query(o, v, P, "split_bf16",
+                                                 opts=native.make_opts(pair_symmetric=True))
+    assert n3 == v and shalf < sfull
+    rows_pad = lambda r: (r + 127) // 128 * 128 + 128
+    kp, npk = (v * v + 63) // 64 * 64, v * (v + 1) // 2
+    chunks = (kp + 127) // 128
+    packed = (rnd(npk * v * v * 8) + rnd(4 * rows_pad(npk) * kp * 2) + rnd(rows_pad(npk) * chunks * 4)
+              + rnd(((v * v + 63) // 64 + 1) * 4))
+    dense = rnd(v ** 4 * 8) + rnd(4 * rows_pad(v * v) * kp * 2) + rnd(rows_pad(v * v) * chunks * 4)
+    assert sfull - shalf == dense - packed
 
 
 def test_planner_exchange_footprint(native):

@@ -114,3 +114,55 @@ def test_split_backward_is_unsupported(gpu_lib):
         gpu_lib.cc_ladder_backward(dev(L), dev(t), dev(lam), dev(np.zeros_like(L)),
                                    dev(np.zeros_like(t)), SPLIT)
     assert e.value.code == gpu_lib.CC_LADDER_EUNSUPPORTED
+
+
+def _pair_symmetric(t):
+    return 0.5 * (t + t.transpose(1, 0, 3, 2))
+
+
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (4, 44, 131, 13),
+                                           (3, 130, 17, 40), (2, 3, 2, 0), (16, 64, 200, 1)])
+def test_split_pair_symmetric_path(gpu_lib, o, v, P, a_block):
+    # packed integral rows a <= b with the digit scheme: entries a <= b are the
+    # scheme's values for those rows (model at 1e-12), entries a > b their exact
+    # mirrors, and the whole is within the scheme's tolerance of the oracle
+    announce("split-pairsym", o, v, P, "a_block", a_block)
+    L, t, _ = random_general(o, v, P, 710 + o + v)
+    t = _pair_symmetric(t)
+    R0 = np.random.default_rng(9).standard_normal(t.shape)
+    got = run_split(gpu_lib, L, t, R0, 4, a_block=a_block, pair_symmetric=True) - R0
+    upper = np.triu(np.ones((v, v), dtype=bool))[None, None]
+    model = split_model.ladder(L, t, 4, 2)
+    assert rel_fro(np.where(upper, got, 0.0), np.where(upper, model, 0.0)) < 1e-12
+    off = ~np.eye(v, dtype=bool)[None, None]
+    # exact mirrors (one computed value stored twice), seen on a zero start
+    got0 = run_split(gpu_lib, L, t, np.zeros_like(t), 4, a_block=a_block, pair_symmetric=True)
+    assert np.array_equal(np.where(off, got0, 0.0), np.where(off, got0.transpose(1, 0, 3, 2), 0.0))
+    assert rel_fro(got, oracle.ladder_forward(L, t)) < TOL_SPLIT[4]
+
+
+def test_split_pair_symmetric_integer_exact(gpu_lib):
+    announce("split-pairsym-int")
+    L, t = integer_inputs(3, 10, 5, 77)
+    t = t + t.transpose(1, 0, 3, 2)  # pair-symmetric, still small integers
+    ref = oracle.ladder_forward(L, t)
+    for slices in (2, 4):
+        got = run_split(gpu_lib, L, t, np.zeros_like(t), slices, pair_symmetric=True)
+        assert np.array_equal(got, ref), slices
+
+
+def test_split_pair_symmetric_full_size(gpu_lib):
+    # the 40/360/1200 workload (pair-symmetric MP2-like amplitudes): the whole
+    # tensor against the general float64 path
+    o, v, P = CONFIGS["c3"]
+    announce("split-pairsym-full", "c3")
+    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    Ld, td = dev(inp.L_vv), dev(inp.t)
+    R64 = torch.zeros_like(td)
+    gpu_lib.cc_ladder_residual(Ld, td, R64, 0)
+    R = torch.zeros_like(td)
+    gpu_lib.cc_ladder_residual(Ld, td, R, SPLIT, opts=gpu_lib.make_opts(pair_symmetric=True))
+    torch.cuda.synchronize()
+    whole = float(torch.linalg.vector_norm(R - R64) / torch.linalg.vector_norm(R64))
+    print("CASE split-pairsym-full whole-tensor error", whole, flush=True)
+    assert whole < TOL_SPLIT_WORKLOAD[4], whole
