@@ -95,9 +95,22 @@ bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   return true;
 }
 
-// Integral builds (both operands row-contiguous, permuted store) take the
-// direct-to-LDS RC kernel when rows are whole 16-byte chunks and aligned.
-template <class Tr>
+// Offsets of the packed build's compact grid: row_tiles[tm] = number of needed
+// tiles in tile rows before tm (one thread; a few thousand rows at most).
+__global__ void pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v, int bm, int bn) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int acc = 0;
+  for (int tm = 0; tm < tiles_m; ++tm) {
+    row_tiles[tm] = acc;
+    const int first = pack_first_tile(tm, bm, bn, v);
+    acc += first < tiles_n ? tiles_n - first : 0;
+  }
+  row_tiles[tiles_m] = acc;
+}
+
+// Integral builds (both operands row-contiguous, permuted or packed store) take
+// the direct-to-LDS RC kernel when rows are whole 16-byte chunks and aligned.
+template <class Tr, int EPI>
 bool launch_rc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, int* rc) {
   constexpr int CH = Tr::CH;
   if (!vec_ok(g0.A, g0.lda) || !vec_ok(g0.B, g0.ldb)) return false;
@@ -105,10 +118,25 @@ bool launch_rc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   GemmArgs<typename Tr::T> g = g0;
   g.tiles_m = (g.M + kDBM - 1) / kDBM;
   g.tiles_n = (g.N + kDBN - 1) / kDBN;
-  const long long tiles = (long long)g.tiles_m * g.tiles_n;
-  if (tiles > 0x7fffffffLL) return false;
+  long long grid = (long long)g.tiles_m * g.tiles_n;
+  if (grid > 0x7fffffffLL) return false;
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
-  hipLaunchKernelGGL((gemm_rc_direct_kernel<Tr>), dim3(static_cast<unsigned>(tiles)),
+  if (EPI == EPI_PACK) {
+    if (!g.row_tiles) return false;
+    long long needed = 0;
+    for (int tm = 0; tm < g.tiles_m; ++tm) {
+      const int first = pack_first_tile(tm, kDBM, kDBN, g.v);
+      needed += first < g.tiles_n ? g.tiles_n - first : 0;
+    }
+    if (needed <= 0) {
+      *rc = CC_LADDER_OK;
+      return true;
+    }
+    hipLaunchKernelGGL(pack_rows_kernel, dim3(1), dim3(1), 0, stream,
+                       const_cast<int*>(g.row_tiles), g.tiles_m, g.tiles_n, g.v, kDBM, kDBN);
+    grid = needed;
+  }
+  hipLaunchKernelGGL((gemm_rc_direct_kernel<Tr, EPI>), dim3(static_cast<unsigned>(grid)),
                      dim3(kDThreads), 0, stream, g);
   *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
   return true;
@@ -132,19 +160,6 @@ bool launch_kr_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   return true;
 }
 
-// Offsets of the packed build's compact grid: row_tiles[tm] = number of needed
-// tiles in tile rows before tm (one thread; a few thousand rows at most).
-__global__ void pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int acc = 0;
-  for (int tm = 0; tm < tiles_m; ++tm) {
-    row_tiles[tm] = acc;
-    const int first = pack_first_tile(tm, kBM, kBN, v);
-    acc += first < tiles_n ? tiles_n - first : 0;
-  }
-  row_tiles[tiles_m] = acc;
-}
-
 template <class Tr, int LA, int LB, int EPI>
 int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
                 void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
@@ -159,6 +174,11 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   g.o = o;
   g.a0 = a0;
   g.row_tiles = row_tiles;
+  g.drain_steps = drain_steps > 0 ? drain_steps : 1;
+  if constexpr (LA == RC && LB == RC && (EPI == EPI_PERM || EPI == EPI_PACK) && Tr::kDirectRC) {
+    int rc = CC_LADDER_OK;
+    if (launch_rc_direct<Tr, EPI>(g, stream, &rc)) return rc;
+  }
   g.tiles_m = (M + kBM - 1) / kBM;
   g.tiles_n = (N + kBN - 1) / kBN;
   const long long tiles = (long long)g.tiles_m * g.tiles_n;
@@ -166,7 +186,6 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   // Bands of up to 16 tile rows: co-resident tiles of one XCD then share
   // both their row panels and a few column panels.
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
-  g.drain_steps = drain_steps > 0 ? drain_steps : 1;
   dim3 grid(static_cast<unsigned>(tiles));
   if (EPI == EPI_PACK) {
     if (!row_tiles) return CC_LADDER_EINVAL;
@@ -178,7 +197,7 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
     }
     if (needed <= 0) return CC_LADDER_OK;
     hipLaunchKernelGGL(pack_rows_kernel, dim3(1), dim3(1), 0, stream, row_tiles, g.tiles_m,
-                       g.tiles_n, v);
+                       g.tiles_n, v, kBM, kBN);
     grid = dim3(static_cast<unsigned>(needed));
   }
   if constexpr (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
@@ -188,10 +207,6 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   if constexpr (LA == KC && LB == RC && EPI == EPI_ACC && Tr::kDirectKR) {
     int rc = CC_LADDER_OK;
     if (launch_kr_direct<Tr>(g, stream, &rc)) return rc;
-  }
-  if constexpr (LA == RC && LB == RC && EPI == EPI_PERM && Tr::kDirectRC) {
-    int rc = CC_LADDER_OK;
-    if (launch_rc_direct<Tr>(g, stream, &rc)) return rc;
   }
   const dim3 block(kThreads);
   if (vec_ok(A, lda) && vec_ok(B, ldb))

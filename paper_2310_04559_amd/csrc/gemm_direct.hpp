@@ -242,8 +242,9 @@ __device__ __forceinline__ int rc_pos(int i, int r) {
     return 32 * (i >> 1) + 2 * r + (i & 1);
 }
 
-template <class Tr>
+template <class Tr, int EPI>
 __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<typename Tr::T> g) {
+  static_assert(EPI == EPI_PERM || EPI == EPI_PACK, "integral-block stores");
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using Chunk = typename Tr::Chunk;
@@ -267,7 +268,19 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
   const int wm = (wave >> 2) * 64;
   const int wn = (wave & 3) * 64;
   int tm, tn;
-  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  if (EPI == EPI_PACK) {
+    // compact grid over the tiles on or above the a = b diagonal
+    const int id = blockIdx.x;
+    int lo = 0, hi = g.tiles_m - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (g.row_tiles[mid] <= id) lo = mid; else hi = mid - 1;
+    }
+    tm = lo;
+    tn = pack_first_tile(tm, kDBM, kDBN, g.v) + (id - g.row_tiles[tm]);
+  } else {
+    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  }
   const int m0 = tm * kDBM, n0 = tn * kDBN;
 
   // Wave instruction q of a stage covers bytes [q KB, q KB + 1 KB) of the A (or B)
@@ -398,24 +411,31 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
     k0 = kend;
   }
 
-  // epilogue: column groups of CH adjacent n (blocks j = CH*h .. CH*h + CH - 1)
+  // epilogue: column groups of CH adjacent n (blocks j = CH*h .. CH*h + CH - 1).
+  // EPI_PERM: m = (a, x), n = (y, d) -> C[a*N*v + y*v^2 + x*v + d];
+  // EPI_PACK: m = (a - a0, c), n = (b - a0, d), kept for b >= a, at packed row
+  // pair(a, b) - pair(a0, a0): C[row*v^2 + c*v + d].
   const long long v = g.v;
   const bool vec = (g.v % CH) == 0;
   constexpr int NG = 4 / CH;  // column groups per lane: 1 (float32) or 2 (float64)
+  auto dst_of = [&](int m, int n) -> long long {  // -1: not stored
+    const int a = m / g.v, x = m - a * g.v;
+    const int y = n / g.v, d = n - y * g.v;
+    if (EPI == EPI_PERM) return (long long)a * g.N * v + (long long)y * v * v + (long long)x * v + d;
+    if (y < a) return -1;
+    const long long row = pair_prefix_d(g.a0 + a, v) - pair_prefix_d(g.a0, v) + (y - a);
+    return row * v * v + (long long)x * v + d;
+  };
 #pragma unroll
   for (int h = 0; h < NG; ++h) {
     const int nb = n0 + wn + rc_pos<Tr>(CH * h, r16);  // first column of the group
     if (nb >= g.N) continue;                            // N % CH == 0: whole group out
-    const int y = nb / g.v, d = nb - y * g.v;
-    const long long coff = (long long)y * v * v + d;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + rc_pos<Tr>(i, Tr::row_of(lane, r));
         if (m >= g.M) continue;
-        const int a = m / g.v, x = m - a * g.v;
-        T* dst = static_cast<T*>(g.C) + (long long)a * g.N * v + coff + (long long)x * v;
         Chunk val;
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
@@ -423,16 +443,16 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
                                       : static_cast<double>(acc[i][CH * h + e][r]);
           val[e] = static_cast<T>(s);
         }
+        T* C = static_cast<T*>(g.C);
         if (vec) {
-          *reinterpret_cast<Chunk*>(dst) = val;
+          // the group's CH columns share (y) and are adjacent in d
+          const long long o0 = dst_of(m, nb);
+          if (o0 >= 0) *reinterpret_cast<Chunk*>(C + o0) = val;
         } else {
-          // the group may cross a y boundary: element-wise addresses
 #pragma unroll
           for (int e = 0; e < CH; ++e) {
-            const int n = nb + e;
-            const int ye = n / g.v, de = n - ye * g.v;
-            static_cast<T*>(g.C)[(long long)a * g.N * v + (long long)ye * v * v + de +
-                                 (long long)x * v] = val[e];
+            const long long oe = dst_of(m, nb + e);
+            if (oe >= 0) C[oe] = val[e];
           }
         }
       }

@@ -190,6 +190,13 @@ def test_forward_pair_symmetric_full_size(gpu_lib):
     Rt = R.permute(1, 0, 3, 2)
     assert torch.equal(torch.where(off, R, 0.0), torch.where(off, Rt, 0.0))
     assert float(torch.linalg.vector_norm(R - Rt) / torch.linalg.vector_norm(R)) < 1e-14
+    # the float32 packed path over the whole tensor against the float64 one
+    R32 = torch.zeros_like(td)
+    gpu_lib.cc_ladder_residual(Ld, td, R32, 1, opts=gpu_lib.make_opts(pair_symmetric=True))
+    torch.cuda.synchronize()
+    whole = float(torch.linalg.vector_norm(R32 - R) / torch.linalg.vector_norm(R))
+    assert whole < TOL[1], whole
+    assert torch.equal(torch.where(off, R32, 0.0), torch.where(off, R32.permute(1, 0, 3, 2), 0.0))
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
