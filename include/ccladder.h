@@ -70,8 +70,10 @@ typedef enum {
                                         doubles amplitudes).  The integral then enters only through
                                         its rows (a,b) with a <= b, stored packed, and each result
                                         is added at both R[i][j][a][b] and R[j][i][b][a]: half the
-                                        build and half the contraction.  Forward, every form; ignored
-                                        by the adjoint. */
+                                        build and half the contraction.  Forward, every form.  In
+                                        the adjoint the caller asserts that lam is pair-symmetric
+                                        too; the two dL terms are then equal and one is computed
+                                        and added twice (one product fewer of five). */
 
 #define CC_LADDER_EXCHANGE 2u        /* evaluate the exchange partner instead (eq. vfunction2):
                                         R[i][j][a][b] += sum_{c,d} (ad|bc) t[i][j][c][d], i.e. the

@@ -163,9 +163,11 @@ bool launch_kr_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
 template <class Tr, int LA, int LB, int EPI>
 int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
                 void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
-                hipStream_t stream, int o = 0, int a0 = 0, int* row_tiles = nullptr) {
+                hipStream_t stream, int o = 0, int a0 = 0, int* row_tiles = nullptr,
+                double alpha = 1.0) {
   if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
   GemmArgs<typename Tr::T> g;
+  g.alpha = alpha;
   g.A = A; g.lda = lda;
   g.B = B; g.ldb = ldb;
   g.C = C; g.ldc = ldc;
@@ -243,6 +245,7 @@ int launch_contract_split(const typename Tr::T* A, long long lda, const typename
   if (splits <= 1 || !part || !vec_ok(A, lda) || !vec_ok(B, ldb))
     return launch_gemm<Tr, KC, KC, EPI_ACC>(A, lda, B, ldb, C, ldc, M, N, K, 0, drain_steps, stream);
   GemmArgs<typename Tr::T> g;
+  g.alpha = 1.0;
   g.A = A; g.lda = lda;
   g.B = B; g.ldb = ldb;
   g.C = part; g.ldc = N;
@@ -516,11 +519,14 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     tr(CC_LADDER_PHASE_W, blk, 1);
     if (rc) return rc;
     tr(CC_LADDER_PHASE_DL, blk, 0);
-    // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]
+    // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]; with pair-symmetric t
+    // and lam, W[b,a,d,c] = W[a,b,c,d] and the second term equals the first:
+    // it is added twice instead
     rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
-                                          static_cast<int>(v2), v, drain, s);
+                                          static_cast<int>(v2), v, drain, s, 0, 0, nullptr,
+                                          pl.pairsym_adj ? 2.0 : 1.0);
     // dL[x][(bd)] += L[x][a0*v + (ac)] . W'_A[(ac)][(bd)]
-    if (!rc)
+    if (!rc && !pl.pairsym_adj)
       rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
                                             na * v, v, drain, s);
     tr(CC_LADDER_PHASE_DL, blk, 1);

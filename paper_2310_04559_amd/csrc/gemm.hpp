@@ -13,7 +13,7 @@
 // contiguous (KC), and so on.
 //
 // Epilogues:
-//   EPI_ACC : C[m*ldc + n] += acc                         (float64 accumulation)
+//   EPI_ACC : C[m*ldc + n] += alpha * acc                 (float64 accumulation)
 //   EPI_PERM: m = (a, x), n = (y, d) with x, d < v and y < N/v:
 //             C[a*N*v + y*v^2 + x*v + d] = acc            (stores, in the operand type, an
 //                                                          integral-shaped block with its
@@ -113,6 +113,7 @@ struct GemmArgs {
   const int* row_tiles;  // EPI_PACK compact grid: first linear tile of each tile row
   int split_steps;       // EPI_PART: K-steps per split
   long long part_stride; // EPI_PART: elements between consecutive splits' partials
+  double alpha;          // EPI_ACC: C += alpha * acc (1, or 2 for a term counted twice)
 };
 
 // First needed tile column of tile row tm in the packed build: columns whose
@@ -174,7 +175,7 @@ __device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, co
                                           double val) {
   const long long v = g.v;
   if (EPI == EPI_ACC) {
-    static_cast<double*>(g.C)[(long long)m * g.ldc + n] += val;
+    static_cast<double*>(g.C)[(long long)m * g.ldc + n] += g.alpha * val;
   } else if (EPI == EPI_PART) {
     static_cast<double*>(g.C)[(long long)m * g.ldc + n] = val;
   } else if (EPI == EPI_PERM) {

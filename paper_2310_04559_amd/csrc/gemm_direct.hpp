@@ -647,7 +647,8 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kr_direct_kernel(GemmArgs<t
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);
         if (m >= g.M) continue;
-        C[(long long)m * g.ldc + n] += Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]);
+        C[(long long)m * g.ldc + n] +=
+            g.alpha * (Tr::kDrain ? acc64[i][j][r] : static_cast<double>(acc[i][j][r]));
       }
   }
 }

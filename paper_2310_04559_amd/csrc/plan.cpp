@@ -58,6 +58,7 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   const size_t v2 = static_cast<size_t>(v) * v;
   const size_t o2 = static_cast<size_t>(o) * o;
   p.pairsym = (pairsym && !backward) ? 1 : 0;
+  p.pairsym_adj = (pairsym && backward) ? 1 : 0;
   // entries of one integral block: n_a*v rows (a,b); packed rows a <= b when the
   // amplitudes are pair-symmetric (the first block holds the most)
   const size_t rows = p.pairsym ? static_cast<size_t>(pair_prefix(n_a, v)) : static_cast<size_t>(n_a) * v;

@@ -26,6 +26,7 @@ struct Plan {
   int slices = 0;       // split-bf16 slice count (0 for the other forms)
   int split_depth = 0;  // split-bf16 anti-diagonals kept beyond the slice triangle (1 or 2)
   int pairsym = 0;      // forward over packed integral rows a <= b (pair-symmetric amplitudes)
+  int pairsym_adj = 0;  // adjoint with pair-symmetric t and lam: one dL term, added twice
   int exchange = 0;     // exchange partner: amplitudes (and dt) with c,d swapped
   size_t off_tx = 0;    // exchange: t with its last two indices swapped (float64; not in FP32)
   size_t off_dtx = 0;   // exchange adjoint: dt of the swapped amplitudes (float64)

@@ -6,7 +6,9 @@ vfunction); its backward calls the library's hand-written adjoint, which
 rebuilds the integral blocks instead of storing them.  Gradients are
 entrywise in L (no symmetrisation) and need no pair symmetry of the upstream
 gradient.  Options carrying the exchange flag give the exchange partner
-(eq. vfunction2) and its gradients instead.
+(eq. vfunction2) and its gradients instead.  The pair-symmetric flag serves the
+forward only: the backward clears it, since an upstream gradient need not be
+pair-symmetric.
 """
 from __future__ import annotations
 
@@ -34,9 +36,13 @@ class LadderFn(torch.autograd.Function):
         if precision == native.CC_LADDER_SPLIT_BF16 or precision == "split_bf16":
             # the slice form is forward-only; its adjoint runs in float32
             precision = native.CC_LADDER_FP32
+        opts = ctx.opts
+        if opts is not None and opts.flags & native.CC_LADDER_PAIR_SYMMETRIC:
+            opts = type(opts).from_buffer_copy(opts)
+            opts.flags &= ~native.CC_LADDER_PAIR_SYMMETRIC
         dL = torch.zeros_like(L)
         dt = torch.zeros_like(t)
-        native.cc_ladder_backward(L, t, gR.contiguous(), dL, dt, precision, opts=ctx.opts)
+        native.cc_ladder_backward(L, t, gR.contiguous(), dL, dt, precision, opts=opts)
         return (dL if ctx.needs_input_grad[0] else None,
                 dt if ctx.needs_input_grad[1] else None, None, None)
 

@@ -152,3 +152,59 @@ def test_autograd_function_exchange(gpu_lib):
     assert rel_fro(host(R), oracle.exchange_forward(L, t)) < 1e-12
     assert rel_fro(host(gL), dL_ref) < 1e-12
     assert rel_fro(host(gt), dt_ref) < 1e-12
+
+
+def _pair_symmetric(x):
+    return 0.5 * (x + x.transpose(1, 0, 3, 2))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("exchange", [False, True])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 23, 37, 5), (9, 37, 101, 0), (3, 130, 17, 40)])
+def test_backward_pair_symmetric(gpu_lib, o, v, P, a_block, precision, exchange):
+    # t and lam pair-symmetric: the one dL term added twice gives both terms
+    announce("backward-pairsym", o, v, P, "a_block", a_block, "precision", precision, exchange)
+    L, t, lam = random_general(o, v, P, 650 + o + v)
+    t, lam = _pair_symmetric(t), _pair_symmetric(lam)
+    dL0 = np.random.default_rng(5).standard_normal(L.shape)
+    dt0 = np.random.default_rng(6).standard_normal(t.shape)
+    ref = oracle.exchange_backward(L, t, lam) if exchange else oracle.ladder_backward(L, t, lam)
+    dL, dt = run_backward(gpu_lib, L, t, lam, precision, dL0, dt0, a_block=a_block,
+                          pair_symmetric=True, exchange=exchange)
+    assert rel_fro(dL - dL0, ref[0]) < TOL_BWD[precision]
+    assert rel_fro(dt - dt0, ref[1]) < TOL_BWD[precision]
+
+
+def test_backward_pair_symmetric_gradient_workload(gpu_lib):
+    # the gradient workload's lam and t are pair-symmetric: the symmetric adjoint
+    # against the general one over the whole tensors
+    o, v, P = CONFIGS["c4"]
+    announce("backward-pairsym-c4")
+    inp = make_inputs(o, v, P, seed_for("c4"), with_lambda=True, device="cuda")
+    Ld, td, lamd = dev(inp.L_vv), dev(inp.t), dev(inp.lam)
+    out = {}
+    for sym in (False, True):
+        dL = torch.zeros_like(Ld)
+        dt = torch.zeros_like(td)
+        gpu_lib.cc_ladder_backward(Ld, td, lamd, dL, dt, 0, opts=gpu_lib.make_opts(pair_symmetric=sym))
+        torch.cuda.synchronize()
+        out[sym] = (dL, dt)
+    for k in (0, 1):
+        den = float(torch.linalg.vector_norm(out[False][k]))
+        assert float(torch.linalg.vector_norm(out[True][k] - out[False][k])) / den < 1e-12
+
+
+def test_autograd_clears_pair_symmetry_for_the_backward(gpu_lib):
+    # a pair-symmetric forward with an unsymmetric upstream gradient
+    announce("autograd-pairsym")
+    from paper_2310_04559_amd.ladder import ladder
+
+    L, t, lam = random_general(4, 18, 25, 33)
+    t = _pair_symmetric(t)
+    Ld = dev(L).requires_grad_(True)
+    td = dev(t).requires_grad_(True)
+    R = ladder(Ld, td, opts=gpu_lib.make_opts(pair_symmetric=True))
+    gL, gt = torch.autograd.grad((R * dev(lam)).sum(), (Ld, td))
+    dL_ref, dt_ref = oracle.ladder_backward(L, t, lam)
+    assert rel_fro(host(gL), dL_ref) < 1e-12
+    assert rel_fro(host(gt), dt_ref) < 1e-12
