@@ -33,8 +33,10 @@
  *   return without a host synchronisation.  Kernel faults surface at the
  *   caller's next synchronisation of that stream.
  * - Return value: 0 on success, else one of the negative CC_LADDER_E* codes.
- *   Nothing throws across the ABI.  On an error return no kernel has been
- *   enqueued and the outputs are untouched.
+ *   Nothing throws across the ABI.  Argument, planning, device and scratch
+ *   allocation errors are found before any kernel is enqueued: the outputs are
+ *   then untouched.  A kernel launch the runtime rejects part-way (CC_LADDER_EHIP)
+ *   can leave the outputs partly updated.
  * - Internal scratch: taken from opts->workspace when given, otherwise
  *   allocated with hipMallocAsync on `stream` and released with hipFreeAsync
  *   on the same stream before return.
