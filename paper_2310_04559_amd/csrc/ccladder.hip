@@ -336,6 +336,81 @@ int swap_cd(const double* x, Out* y, int o, int v, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
+__global__ __launch_bounds__(256) void fill_zero_kernel(double* __restrict__ x, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 0.0;
+}
+
+int fill_zero(double* x, long long n, hipStream_t s) {
+  if (n <= 0) return CC_LADDER_OK;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x, n);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+// Pair-symmetric adjoint, per block: lamP[(ij)][q] = w lam[(ij)][(a,b)] for the
+// block's packed pairs q -> (a, b) (a in the block, b >= a), w = 1/2 when a == b,
+// row stride ldp.
+template <typename T>
+__global__ __launch_bounds__(256) void gather_pairs_kernel(const T* __restrict__ lam,
+                                                           T* __restrict__ lamP, int o2, int v,
+                                                           int a0, long long npairs, long long ldp) {
+  const long long n = (long long)o2 * npairs;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long v2 = (long long)v * v;
+  const long long base = pair_prefix_d(a0, v);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const long long row = e / npairs, q = e - row * npairs;
+    const int a = pair_row(base + q, v);
+    const int b = a + static_cast<int>(base + q - pair_prefix_d(a, v));
+    const T x = lam[row * v2 + (long long)a * v + b];
+    lamP[row * ldp + q] = (a == b) ? x * T(0.5) : x;
+  }
+}
+
+// dt[i][j][c][d] += B[i][j][c][d] + B[j][i][d][c], the mirror read through a
+// 32 x 32 LDS tile so that both reads and the update are coalesced.
+__global__ __launch_bounds__(256) void mirror_add_kernel(const double* __restrict__ B,
+                                                         double* __restrict__ dt, int o, int v,
+                                                         int tiles) {
+  __shared__ double tile[kSwapTile][kSwapTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const long long per_mat = (long long)tiles * tiles;
+  const long long nmat = (long long)o * o;
+  const long long v2 = (long long)v * v;
+  for (long long w = blockIdx.x; w < nmat * per_mat; w += gridDim.x) {
+    const long long m = w / per_mat;
+    const int i = static_cast<int>(m / o), j = static_cast<int>(m - (long long)i * o);
+    const long long mp = (long long)j * o + i;
+    const int r = static_cast<int>(w - m * per_mat);
+    const int c0 = (r / tiles) * kSwapTile, d0 = (r % tiles) * kSwapTile;
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {  // rows d, columns c of the mirror matrix
+      const int d = d0 + k, c = c0 + tx;
+      if (c < v && d < v) tile[k][tx] = B[mp * v2 + (long long)d * v + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {  // rows c, columns d of this matrix
+      const int c = c0 + k, d = d0 + tx;
+      if (c < v && d < v) {
+        const long long e = m * v2 + (long long)c * v + d;
+        dt[e] += B[e] + tile[tx][k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int mirror_add(const double* B, double* dt, int o, int v, hipStream_t s) {
+  const int tiles = (v + kSwapTile - 1) / kSwapTile;
+  const long long work = (long long)o * o * tiles * tiles;
+  const long long blocks = std::min<long long>(work, 16384);
+  hipLaunchKernelGGL(mirror_add_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, B, dt,
+                     o, v, tiles);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
 constexpr int kRedBlocks = 1024;
 
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const double* __restrict__ x,
@@ -493,25 +568,62 @@ int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T
 
 template <class Tr>
 int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t,
-                    const typename Tr::T* lam, double* dL, double* dt, typename Tr::T* V,
-                    typename Tr::T* W, const Tracer& tr, hipStream_t s) {
+                    const typename Tr::T* lam, double* dL, double* dt, char* base,
+                    const Tracer& tr, hipStream_t s) {
+  using T = typename Tr::T;
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  T* V = reinterpret_cast<T*>(base + pl.off_V);
+  T* W = reinterpret_cast<T*>(base + pl.off_W);
+  const bool sym = pl.pairsym_adj != 0;
+  // pair-symmetric t and lam: dt = B + mirror(B) with B over the packed rows a <= b
+  double* Bacc = sym ? reinterpret_cast<double*>(base + pl.off_B) : nullptr;
+  T* lamP = sym ? reinterpret_cast<T*>(base + pl.off_lamP) : nullptr;
+  int* row_tiles = sym ? reinterpret_cast<int*>(base + pl.off_tiles) : nullptr;
+  if (sym) {
+    const int rc = fill_zero(Bacc, (long long)o * o * v2, s);
+    if (rc) return rc;
+  }
   for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
     const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
     const long long off = (long long)a0 * v;
-    tr(CC_LADDER_PHASE_BUILD, blk, 0);
-    int rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + off, v2, L, v2, V, 0, na * v,
-                                               static_cast<int>(v2), P, v, drain, s);
-    tr(CC_LADDER_PHASE_BUILD, blk, 1);
-    if (rc) return rc;
-    // dt[(ij)][(cd)] += lam[(ij)][a0*v + (ab)] . V_A[(ab)][(cd)]
-    tr(CC_LADDER_PHASE_DT, blk, 0);
-    rc = launch_gemm<Tr, KC, RC, EPI_ACC>(lam + off, v2, V, v2, dt, v2, o * o,
-                                          static_cast<int>(v2), na * v, v, drain, s);
-    tr(CC_LADDER_PHASE_DT, blk, 1);
-    if (rc) return rc;
+    int rc;
+    if (sym) {
+      const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
+      const long long ldp = (npairs + 3) / 4 * 4;
+      tr(CC_LADDER_PHASE_BUILD, blk, 0);
+      rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
+                                             static_cast<int>((long long)(v - a0) * v), P, v,
+                                             drain, s, o, a0, row_tiles);
+      tr(CC_LADDER_PHASE_BUILD, blk, 1);
+      if (rc) return rc;
+      // B[(ij)][(cd)] += sum_(ab packed) w lam[(ij)][(ab)] V_A[pair(a,b)][(cd)]
+      tr(CC_LADDER_PHASE_DT, blk, 0);
+      const long long n = (long long)o * o * npairs;
+      const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+      hipLaunchKernelGGL((gather_pairs_kernel<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                         s, lam, lamP, o * o, v, a0, npairs, ldp);
+      rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+      if (!rc)
+        rc = launch_gemm<Tr, KC, RC, EPI_ACC>(lamP, ldp, V, v2, Bacc, v2, o * o,
+                                              static_cast<int>(v2), static_cast<int>(npairs), v,
+                                              drain, s);
+      tr(CC_LADDER_PHASE_DT, blk, 1);
+      if (rc) return rc;
+    } else {
+      tr(CC_LADDER_PHASE_BUILD, blk, 0);
+      rc = launch_gemm<Tr, RC, RC, EPI_PERM>(L + off, v2, L, v2, V, 0, na * v,
+                                             static_cast<int>(v2), P, v, drain, s);
+      tr(CC_LADDER_PHASE_BUILD, blk, 1);
+      if (rc) return rc;
+      // dt[(ij)][(cd)] += lam[(ij)][a0*v + (ab)] . V_A[(ab)][(cd)]
+      tr(CC_LADDER_PHASE_DT, blk, 0);
+      rc = launch_gemm<Tr, KC, RC, EPI_ACC>(lam + off, v2, V, v2, dt, v2, o * o,
+                                            static_cast<int>(v2), na * v, v, drain, s);
+      tr(CC_LADDER_PHASE_DT, blk, 1);
+      if (rc) return rc;
+    }
     // W'_A[a][c][b][d] = sum_(ij) lam[(ij)][a0*v + (ab)] t[(ij)][(cd)]
     tr(CC_LADDER_PHASE_W, blk, 0);
     rc = launch_gemm<Tr, RC, RC, EPI_PERM>(lam + off, v2, t, v2, W, 0, na * v,
@@ -524,12 +636,19 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     // it is added twice instead
     rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
                                           static_cast<int>(v2), v, drain, s, 0, 0, nullptr,
-                                          pl.pairsym_adj ? 2.0 : 1.0);
+                                          sym ? 2.0 : 1.0);
     // dL[x][(bd)] += L[x][a0*v + (ac)] . W'_A[(ac)][(bd)]
-    if (!rc && !pl.pairsym_adj)
+    if (!rc && !sym)
       rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
                                             na * v, v, drain, s);
     tr(CC_LADDER_PHASE_DL, blk, 1);
+    if (rc) return rc;
+  }
+  if (sym) {
+    // dt[i][j][c][d] += B[i][j][c][d] + B[j][i][d][c]
+    tr(CC_LADDER_PHASE_DT, pl.nblocks, 0);
+    const int rc = mirror_add(Bacc, dt, o, v, s);
+    tr(CC_LADDER_PHASE_DT, pl.nblocks, 1);
     if (rc) return rc;
   }
   return CC_LADDER_OK;
@@ -761,8 +880,7 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
     if (rc) return rc;
   }
   if (precision == CC_LADDER_FP64) {
-    rc = backward_blocks<TrF64>(pl, L, t, lam, dL, dtx, reinterpret_cast<double*>(base + pl.off_V),
-                                reinterpret_cast<double*>(base + pl.off_W), tr, stream);
+    rc = backward_blocks<TrF64>(pl, L, t, lam, dL, dtx, base, tr, stream);
   } else {
     float* L32 = reinterpret_cast<float*>(base + pl.off_L);
     float* t32 = reinterpret_cast<float*>(base + pl.off_t);
@@ -774,9 +892,7 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
     if (!rc) rc = to_f32(lam, lam32, (size_t)o * o * v * v, stream);
     tr(CC_LADDER_PHASE_PREP, 0, 1);
     if (rc) return rc;
-    rc = backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dtx,
-                                reinterpret_cast<float*>(base + pl.off_V),
-                                reinterpret_cast<float*>(base + pl.off_W), tr, stream);
+    rc = backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dtx, base, tr, stream);
   }
   if (rc || !pl.exchange) return rc;
   tr(CC_LADDER_PHASE_PREP, 1, 0);

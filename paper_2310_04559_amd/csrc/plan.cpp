@@ -60,9 +60,13 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   p.pairsym = (pairsym && !backward) ? 1 : 0;
   p.pairsym_adj = (pairsym && backward) ? 1 : 0;
   // entries of one integral block: n_a*v rows (a,b); packed rows a <= b when the
-  // amplitudes are pair-symmetric (the first block holds the most)
-  const size_t rows = p.pairsym ? static_cast<size_t>(pair_prefix(n_a, v)) : static_cast<size_t>(n_a) * v;
+  // amplitudes are pair-symmetric (the first block holds the most).  The adjoint's
+  // W block always has n_a*v rows.
+  const size_t npk = static_cast<size_t>(pair_prefix(n_a, v));
+  const size_t npk_ld = (npk + 3) / 4 * 4;  // row stride of the adjoint's gathered lam
+  const size_t rows = (p.pairsym || p.pairsym_adj) ? npk : static_cast<size_t>(n_a) * v;
   const size_t blk = rows * v2;
+  const size_t blk_w = static_cast<size_t>(n_a) * v * v2;
   size_t cur = 0;
   p.exchange = (flags & CC_LADDER_EXCHANGE) ? 1 : 0;
   if (p.exchange) {
@@ -73,7 +77,8 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   switch (precision) {
     case CC_LADDER_FP64:
       p.off_V = take(&cur, blk * sizeof(double));
-      if (p.backward) p.off_W = take(&cur, blk * sizeof(double));
+      if (p.backward) p.off_W = take(&cur, blk_w * sizeof(double));
+      if (p.pairsym_adj) p.off_lamP = take(&cur, o2 * npk_ld * sizeof(double));
       break;
     case CC_LADDER_FP32:
       p.k_chunk = k_chunk ? k_chunk : 512;
@@ -81,7 +86,8 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       p.off_t = take(&cur, o2 * v2 * sizeof(float));
       if (p.backward) p.off_lam = take(&cur, o2 * v2 * sizeof(float));
       p.off_V = take(&cur, blk * sizeof(float));
-      if (p.backward) p.off_W = take(&cur, blk * sizeof(float));
+      if (p.backward) p.off_W = take(&cur, blk_w * sizeof(float));
+      if (p.pairsym_adj) p.off_lamP = take(&cur, o2 * npk_ld * sizeof(float));
       break;
     case CC_LADDER_SPLIT_BF16: {
       if (p.backward) return CC_LADDER_EUNSUPPORTED;
@@ -104,7 +110,11 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
     default:
       return CC_LADDER_EINVAL;
   }
-  if (p.pairsym) {
+  if (p.pairsym_adj) {
+    // the adjoint's dt accumulates B[(ij)][(cd)] over packed rows; dt += B + mirror(B)
+    p.off_B = take(&cur, o2 * v2 * sizeof(double));
+  }
+  if (p.pairsym || p.pairsym_adj) {
     // tile-row offsets of the packed build's compact grid (128-row tiles; 64 rows
     // in the split form)
     const size_t bm = precision == CC_LADDER_SPLIT_BF16 ? 64 : 128;

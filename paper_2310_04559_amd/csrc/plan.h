@@ -26,7 +26,10 @@ struct Plan {
   int slices = 0;       // split-bf16 slice count (0 for the other forms)
   int split_depth = 0;  // split-bf16 anti-diagonals kept beyond the slice triangle (1 or 2)
   int pairsym = 0;      // forward over packed integral rows a <= b (pair-symmetric amplitudes)
-  int pairsym_adj = 0;  // adjoint with pair-symmetric t and lam: one dL term, added twice
+  int pairsym_adj = 0;  // adjoint with pair-symmetric t and lam: packed integral rows for dt,
+                        // one dL term added twice
+  size_t off_lamP = 0;  // pair-symmetric adjoint: lam at the block's packed pairs, weighted
+  size_t off_B = 0;     // pair-symmetric adjoint: float64 B[(ij)][(cd)], dt += B + mirror(B)
   int exchange = 0;     // exchange partner: amplitudes (and dt) with c,d swapped
   size_t off_tx = 0;    // exchange: t with its last two indices swapped (float64; not in FP32)
   size_t off_dtx = 0;   // exchange adjoint: dt of the swapped amplitudes (float64)
@@ -39,7 +42,7 @@ struct Plan {
   size_t off_part = 0;  // float64 partials of the split contraction [k_splits][o^2][n_a*o]
   size_t off_Lexp = 0, off_texp = 0;
   // per-block buffers
-  size_t off_V = 0;     // float64 or float32 integral block [n_a][v][v][v]
+  size_t off_V = 0;     // float64 or float32 integral block [n_a][v][v][v] (or packed rows)
   size_t off_W = 0;     // adjoint block W'[n_a][v][v][v] (backward)
   size_t off_Vs = 0;    // bf16 slices of the integral block
   size_t off_Vexp = 0;  // exponents of the integral block's digit rows, per (row, chunk)
