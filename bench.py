@@ -258,8 +258,8 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
 
     from paper_2310_04559_amd.inputs import CONFIGS, make_inputs, seed_for
 
-    o, v, P = CONFIGS["c4"]
-    inp = make_inputs(o, v, P, seed_for("c4"), with_lambda=True, device="cuda")
+    o, v, P = CONFIGS["o30_v300_P900"]
+    inp = make_inputs(o, v, P, seed_for("o30_v300_P900"), with_lambda=True, device="cuda")
     L = torch.from_numpy(inp.L_vv).cuda()
     t = torch.from_numpy(inp.t).cuda()
     lam = torch.from_numpy(inp.lam).cuda()
@@ -316,8 +316,8 @@ def bench_large(native):
     import oracle
     from paper_2310_04559_amd.inputs import CONFIGS, make_inputs, seed_for
 
-    o, v, P = CONFIGS["c5"]
-    inp = make_inputs(o, v, P, seed_for("c5"), with_lambda=True, device="cuda")
+    o, v, P = CONFIGS["o60_v600_P1800"]
+    inp = make_inputs(o, v, P, seed_for("o60_v600_P1800"), with_lambda=True, device="cuda")
     pairs = sampled_pairs(v, 8, 5)
     ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
     L = torch.from_numpy(inp.L_vv).cuda()
@@ -457,7 +457,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         msg = ("bench.py measures one GPU only: the ladder library runs on a single MI355X and "
-               "this build has no multi-GPU path (--gpus must be 1).")
+               "the library has no multi-GPU path (--gpus must be 1).")
         print(json.dumps({"error": msg, "n_gpus": args.gpus}), flush=True)
         log(msg)
         sys.exit(2)
@@ -482,9 +482,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
         del src, dst
-    o, v, P = CONFIGS["c3"]
+    o, v, P = CONFIGS["o40_v360_P1200"]
     t0 = time.perf_counter()
-    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    inp = make_inputs(o, v, P, seed_for("o40_v360_P1200"), device="cuda")
     log(f"inputs o={o} v={v} P={P} drawn in {time.perf_counter() - t0:.1f} s")
     L = torch.from_numpy(inp.L_vv).cuda()
     t = torch.from_numpy(inp.t).cuda()

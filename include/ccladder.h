@@ -57,7 +57,7 @@ extern "C" {
 #define CC_LADDER_ENOMEM       -2   /* not even a one-virtual block fits the budget / workspace too small */
 #define CC_LADDER_ENODEV       -3   /* no gfx950 device is current */
 #define CC_LADDER_EHIP         -4   /* a HIP runtime call failed */
-#define CC_LADDER_EUNSUPPORTED -5   /* valid request this build does not implement */
+#define CC_LADDER_EUNSUPPORTED -5   /* valid request the library does not implement */
 
 /* Arithmetic of the two contractions.  Sources and results are always float64. */
 typedef enum {

@@ -976,7 +976,7 @@ extern "C" const char* cc_ladder_strerror(int code) {
     case CC_LADDER_ENOMEM: return "scratch does not fit the budget or the workspace";
     case CC_LADDER_ENODEV: return "no gfx950 device is current";
     case CC_LADDER_EHIP: return "HIP runtime error";
-    case CC_LADDER_EUNSUPPORTED: return "request not supported by this build";
+    case CC_LADDER_EUNSUPPORTED: return "request not supported by the library";
     default: return "unknown error code";
   }
 }

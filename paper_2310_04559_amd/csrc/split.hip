@@ -207,7 +207,7 @@ __device__ __forceinline__ void wait_vm(int n) {
 // Per K-step a wave reads the S slices of its column blocks once and streams the
 // S slices of its row blocks; the exact float32 sums of a chunk are drained into
 // float64 with their scale 2^(-8g), and the epilogue applies 2^(eA + eB).
-// Measured at c3 (S = 4): 48% of the bf16 MFMA peak; with the operand loads
+// Measured at o=40 v=360 P=1200 (S = 4): 48% of the bf16 MFMA peak; with the operand loads
 // removed (a timing experiment) 67%, so a third of the time is the global->LDS
 // pipeline and the rest LDS reads, drains and barriers.  Splitting the products
 // of a sub-tile over two waves (fewer registers, larger sub-tiles) or one wave

@@ -57,21 +57,26 @@ class LadderInputs:
     L_oo: Optional[np.ndarray] = None  # [P][o][o]
 
 
-# Workload shapes: (o, v, P).  c1 is the brute-force tier, c2 the first GPU
-# parity tier, c3 the throughput workload, c4 the adjoint workload and c5 the
-# large single-GPU case.
+# Workload shapes: (o, v, P), named by their sizes: the brute-force tier
+# (5/20/75), the first GPU parity tier (20/180/600), the throughput workload
+# (40/360/1200), the adjoint workload (30/300/900) and the large single-GPU case
+# (60/600/1800).
 CONFIGS = {
-    "c1": (5, 20, 75),
-    "c2": (20, 180, 600),
-    "c3": (40, 360, 1200),
-    "c4": (30, 300, 900),
-    "c5": (60, 600, 1800),
+    "o5_v20_P75": (5, 20, 75),
+    "o20_v180_P600": (20, 180, 600),
+    "o40_v360_P1200": (40, 360, 1200),
+    "o30_v300_P900": (30, 300, 900),
+    "o60_v600_P1800": (60, 600, 1800),
 }
 
 
+# One seed per workload, in the order above.
+SEEDS = {name: 1001 + k for k, name in enumerate(CONFIGS)}
+
+
 def seed_for(name: str) -> int:
-    """Seed convention: 1000 + the workload's index (c1 -> 1001, ...)."""
-    return 1000 + int(name[1:])
+    """The workload's seed (1001 ... 1005 in the order of CONFIGS)."""
+    return SEEDS[name]
 
 
 def paper_shape(K: int):

@@ -26,7 +26,7 @@ def run_backward(native, L, t, lam, precision, dL0=None, dt0=None, **kw):
 def test_backward_oracle_gradient_small(gpu_lib, precision):
     # the gradient workload's oracle size: o=4, v=12, P=40
     announce("backward-small", precision)
-    inp = make_inputs(4, 12, 40, seed_for("c4"), with_lambda=True)
+    inp = make_inputs(4, 12, 40, seed_for("o30_v300_P900"), with_lambda=True)
     dL_ref, dt_ref = oracle.ladder_backward(inp.L_vv, inp.t, inp.lam)
     dL, dt = run_backward(gpu_lib, inp.L_vv, inp.t, inp.lam, precision)
     assert rel_fro(dL, dL_ref) < TOL_BWD[precision]
@@ -69,15 +69,15 @@ def test_central_differences_gradient_workload(gpu_lib):
     # the GPU forward; central differences with h = 1e-6 are exact up to rounding
     # (Loss is quadratic in L and linear in t).  L entries are drawn among the
     # leading vectors, where the gradient stands above the rounding floor.
-    o, v, P = CONFIGS["c4"]
+    o, v, P = CONFIGS["o30_v300_P900"]
     announce("backward-fd", o, v, P)
-    inp = make_inputs(o, v, P, seed_for("c4"), with_lambda=True, device="cuda")
+    inp = make_inputs(o, v, P, seed_for("o30_v300_P900"), with_lambda=True, device="cuda")
     Ld, td, lamd = dev(inp.L_vv), dev(inp.t), dev(inp.lam)
     dL = torch.zeros_like(Ld)
     dt = torch.zeros_like(td)
     gpu_lib.cc_ladder_backward(Ld, td, lamd, dL, dt, 0)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(seed_for("c4") + 1)
+    rng = np.random.default_rng(seed_for("o30_v300_P900") + 1)
     h = 1e-6
     R = torch.empty_like(td)
     out = torch.empty(2, dtype=torch.float64, device="cuda")
@@ -178,9 +178,9 @@ def test_backward_pair_symmetric(gpu_lib, o, v, P, a_block, precision, exchange)
 def test_backward_pair_symmetric_gradient_workload(gpu_lib):
     # the gradient workload's lam and t are pair-symmetric: the symmetric adjoint
     # against the general one over the whole tensors
-    o, v, P = CONFIGS["c4"]
-    announce("backward-pairsym-c4")
-    inp = make_inputs(o, v, P, seed_for("c4"), with_lambda=True, device="cuda")
+    o, v, P = CONFIGS["o30_v300_P900"]
+    announce("backward-pairsym-o30-v300-P900")
+    inp = make_inputs(o, v, P, seed_for("o30_v300_P900"), with_lambda=True, device="cuda")
     Ld, td, lamd = dev(inp.L_vv), dev(inp.t), dev(inp.lam)
     out = {}
     for sym in (False, True):

@@ -47,9 +47,9 @@ def test_forward_integer_inputs_exact(gpu_lib, precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_forward_c1_workload(gpu_lib, precision):
-    o, v, P = CONFIGS["c1"]
-    announce("forward-c1", precision)
-    inp = make_inputs(o, v, P, seed_for("c1"))
+    o, v, P = CONFIGS["o5_v20_P75"]
+    announce("forward-o5-v20-P75", precision)
+    inp = make_inputs(o, v, P, seed_for("o5_v20_P75"))
     ref = oracle.ladder_forward(inp.L_vv, inp.t)
     got = run_forward(gpu_lib, inp.L_vv, inp.t, np.zeros_like(inp.t), precision)
     assert rel_fro(got, ref) < TOL[precision]
@@ -107,7 +107,7 @@ def _sampled_pairs(v, n, seed):
     return sorted(pairs)
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("name", ["o20_v180_P600", "o40_v360_P1200"])
 def test_full_size_sampled_entries(gpu_lib, name):
     # the throughput launch configuration (default options) at the workload's
     # real shape; the oracle computes whole R[:, :, a, b] columns one by one
@@ -172,9 +172,9 @@ def test_forward_pair_symmetric_path(gpu_lib, o, v, P, a_block, precision):
 
 
 def test_forward_pair_symmetric_full_size(gpu_lib):
-    o, v, P = CONFIGS["c3"]
-    announce("forward-pairsym-full", "c3")
-    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    o, v, P = CONFIGS["o40_v360_P1200"]
+    announce("forward-pairsym-full", "o40_v360_P1200")
+    inp = make_inputs(o, v, P, seed_for("o40_v360_P1200"), device="cuda")
     Ld, td = dev(inp.L_vv), dev(inp.t)
     pairs = _sampled_pairs(v, 24, 3)
     ref = oracle.ladder_pairs(inp.L_vv, inp.t, pairs)
@@ -239,9 +239,9 @@ def test_forward_exchange_full_size_sampled(gpu_lib):
     # the exchange partner at the 40/360/1200 workload, default options; the
     # oracle's columns come from the ladder of the swapped amplitudes, whose
     # identity with the exchange term is pinned on the CPU
-    o, v, P = CONFIGS["c3"]
-    announce("forward-exchange-full", "c3")
-    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    o, v, P = CONFIGS["o40_v360_P1200"]
+    announce("forward-exchange-full", "o40_v360_P1200")
+    inp = make_inputs(o, v, P, seed_for("o40_v360_P1200"), device="cuda")
     Ld, td = dev(inp.L_vv), dev(inp.t)
     pairs = _sampled_pairs(v, 16, 4)
     ref = oracle.ladder_pairs(inp.L_vv, np.ascontiguousarray(inp.t.transpose(0, 1, 3, 2)), pairs)

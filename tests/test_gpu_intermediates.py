@@ -80,7 +80,7 @@ def test_intermediate_bitwise_independent_of_block_size(gpu_lib, which, o, v, P)
 
 
 @pytest.mark.parametrize("which", ["ijkl", "ijbk"])
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["o5_v20_P75", "o20_v180_P600"])
 def test_intermediate_workloads(gpu_lib, which, name):
     # the generator's own vectors: L_ov is the occupied-virtual block of the
     # same symmetric Cholesky vectors, t the MP2-like amplitudes
@@ -100,9 +100,9 @@ def test_intermediate_workloads(gpu_lib, which, name):
 def test_intermediate_full_size_sampled(gpu_lib, which):
     # the 40/360/1200 workload with default options; the oracle computes whole
     # slices X[:, :, k, :] or Y[:, :, b, :] for a few first indices
-    o, v, P = CONFIGS["c3"]
+    o, v, P = CONFIGS["o40_v360_P1200"]
     announce("intermediate-full", which)
-    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    inp = make_inputs(o, v, P, seed_for("o40_v360_P1200"), device="cuda")
     firsts = [0, o // 2, o - 1] if which == "ijkl" else [0, 17, v // 2, v - 1]
     ref = np.zeros(out_shape(which, o, v))
     for p in firsts:
@@ -192,14 +192,14 @@ def test_hole_ladder_integer_exact_and_deterministic(gpu_lib):
         assert np.array_equal(run_hole(gpu_lib, Loo, t, z, 0, a_block=block), base)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["o5_v20_P75", "o20_v180_P600", "o40_v360_P1200"])
 def test_hole_ladder_workloads(gpu_lib, name):
     # the generator's own occupied-occupied vectors; at 40/360/1200 the oracle
     # computes the rows of a few occupied i
     o, v, P = CONFIGS[name]
     announce("hole-workload", name)
-    inp = make_inputs(o, v, P, seed_for(name), device="cuda" if name == "c3" else None)
-    rows = list(range(o)) if name != "c3" else [0, o // 2, o - 1]
+    inp = make_inputs(o, v, P, seed_for(name), device="cuda" if name == "o40_v360_P1200" else None)
+    rows = list(range(o)) if name != "o40_v360_P1200" else [0, o // 2, o - 1]
     ref = np.zeros_like(inp.t)
     for i in rows:
         oracle.hole_ladder(inp.L_oo, inp.t, ref, i, i + 1)

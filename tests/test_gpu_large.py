@@ -21,12 +21,12 @@ def _tnorm(x):
 
 @pytest.fixture(scope="module")
 def large(gpu_lib):
-    o, v, P = CONFIGS["c5"]
+    o, v, P = CONFIGS["o60_v600_P1800"]
     free, _ = torch.cuda.mem_get_info()
     if free < 120 << 30:
         pytest.skip("needs ~120 GB of free device memory")
     announce("large-inputs", o, v, P)
-    inp = make_inputs(o, v, P, seed_for("c5"), with_lambda=True, device="cuda")
+    inp = make_inputs(o, v, P, seed_for("o60_v600_P1800"), with_lambda=True, device="cuda")
     L = torch.from_numpy(inp.L_vv).cuda()
     t = torch.from_numpy(inp.t).cuda()
     rng = np.random.default_rng(5)

@@ -58,9 +58,9 @@ def test_split_general_inputs(gpu_lib, o, v, P, a_block, slices):
 
 @pytest.mark.parametrize("slices", [2, 4])
 def test_split_c1_workload(gpu_lib, slices):
-    o, v, P = CONFIGS["c1"]
-    announce("split-c1", slices)
-    inp = make_inputs(o, v, P, seed_for("c1"))
+    o, v, P = CONFIGS["o5_v20_P75"]
+    announce("split-o5-v20-P75", slices)
+    inp = make_inputs(o, v, P, seed_for("o5_v20_P75"))
     ref = oracle.ladder_forward(inp.L_vv, inp.t)
     got = run_split(gpu_lib, inp.L_vv, inp.t, np.zeros_like(inp.t), slices)
     assert rel_fro(got, ref) < TOL_SPLIT_WORKLOAD[slices]
@@ -76,7 +76,7 @@ def test_split_bitwise_independent_of_block_size(gpu_lib):
         assert np.array_equal(run_split(gpu_lib, L, t, z, 4, a_block=a_block), ref)
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("name", ["o20_v180_P600", "o40_v360_P1200"])
 def test_split_full_size_sampled_entries(gpu_lib, name):
     o, v, P = CONFIGS[name]
     announce("split-full", name)
@@ -154,9 +154,9 @@ def test_split_pair_symmetric_integer_exact(gpu_lib):
 def test_split_pair_symmetric_full_size(gpu_lib):
     # the 40/360/1200 workload (pair-symmetric MP2-like amplitudes): the whole
     # tensor against the general float64 path
-    o, v, P = CONFIGS["c3"]
-    announce("split-pairsym-full", "c3")
-    inp = make_inputs(o, v, P, seed_for("c3"), device="cuda")
+    o, v, P = CONFIGS["o40_v360_P1200"]
+    announce("split-pairsym-full", "o40_v360_P1200")
+    inp = make_inputs(o, v, P, seed_for("o40_v360_P1200"), device="cuda")
     Ld, td = dev(inp.L_vv), dev(inp.t)
     R64 = torch.zeros_like(td)
     gpu_lib.cc_ladder_residual(Ld, td, R64, 0)

@@ -125,12 +125,12 @@ def test_rank_one_amplitudes_closed_form():
 
 
 def test_explicit_eri_of_all_orbitals_c1():
-    # The c1 workload evaluated through an explicitly stored four-index integral:
+    # The 5/20/75 workload evaluated through an explicitly stored four-index integral:
     # the generator's full L over n = o+v orbitals is rebuilt, the n^4 tensor is
     # formed, and its virtual block is contracted one (i,j,a,b) at a time.
-    o, v, P = CONFIGS["c1"]
-    inp = make_inputs(o, v, P, seed_for("c1"))
-    rng = np.random.default_rng(seed_for("c1"))
+    o, v, P = CONFIGS["o5_v20_P75"]
+    inp = make_inputs(o, v, P, seed_for("o5_v20_P75"))
+    rng = np.random.default_rng(seed_for("o5_v20_P75"))
     n = o + v
     X = rng.standard_normal((P, n, n))
     Lfull = np.triu(X) + np.transpose(np.triu(X, 1), (0, 2, 1))
@@ -148,8 +148,8 @@ def test_explicit_eri_of_all_orbitals_c1():
 def test_papers_one_shot_formulation_c1():
     # The paper's one-shot form keeps amplitudes as t[i,c,j,d] and writes
     # t_new[i,a,j,b] (Sec. "einsum and opt_einsum").
-    o, v, P = CONFIGS["c1"]
-    inp = make_inputs(o, v, P, seed_for("c1"))
+    o, v, P = CONFIGS["o5_v20_P75"]
+    inp = make_inputs(o, v, P, seed_for("o5_v20_P75"))
     t_paper = inp.t.transpose(0, 2, 1, 3)
     out_paper = np.einsum("xac,xbd,icjd->iajb", inp.L_vv, inp.L_vv, t_paper, optimize=True)
     got = oracle.ladder_forward(inp.L_vv, inp.t)
