@@ -254,3 +254,43 @@ def test_forward_exchange_full_size_sampled(gpu_lib):
         tol = TOL_SPLIT_WORKLOAD[4] if precision == 2 else TOL[precision]
         assert rel_fro(host(R[:, :, ia, ib].permute(2, 0, 1)), ref) < tol, precision
         del R
+
+
+def test_trace_hook_and_budget(gpu_lib):
+    # the phase hook sees each phase of each integral block, in order, and a
+    # budget that forces several blocks gives the planner's block count
+    announce("forward-trace-budget")
+    o, v, P = 6, 40, 50
+    L, t, _ = random_general(o, v, P, 21)
+    budget = 9 * v ** 3 * 4 + 4 * (P * v * v + o * o * v * v) + (1 << 16)
+    nbytes, n_a = gpu_lib.cc_ladder_workspace_query(o, v, P, 1, hbm_budget=budget)
+    assert 1 < n_a < v
+    seen = []
+
+    def hook(user, phase, block, end, stream):
+        seen.append((phase, block, end))
+
+    fn = gpu_lib.TRACE_FN(hook)
+    R = dev(np.zeros_like(t))
+    gpu_lib.cc_ladder_residual(dev(L), dev(t), R, 1, opts=gpu_lib.make_opts(hbm_budget=budget, trace=fn))
+    torch.cuda.synchronize()
+    assert rel_fro(host(R), oracle.ladder_forward(L, t)) < TOL[1]
+    nb = -(-v // n_a)
+    PREP, BUILD, CONTRACT = 0, 1, 2
+    want = [(PREP, 0, 0), (PREP, 0, 1)]
+    for b in range(nb):
+        want += [(BUILD, b, 0), (BUILD, b, 1), (CONTRACT, b, 0), (CONTRACT, b, 1)]
+    assert seen == want
+
+
+def test_misaligned_workspace_is_rejected(gpu_lib):
+    announce("forward-workspace-align")
+    L, t, _ = random_general(3, 12, 10, 22)
+    nbytes, _ = gpu_lib.cc_ladder_workspace_query(3, 12, 10, 0)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    R = dev(np.zeros_like(t))
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_residual(dev(L), dev(t), R, 0, opts=gpu_lib.make_opts(workspace=ws[8:]))
+    assert e.value.code == gpu_lib.CC_LADDER_EINVAL
+    torch.cuda.synchronize()
+    assert not torch.any(R)  # nothing enqueued
