@@ -53,6 +53,15 @@ __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
   }
 }
 
+// Digit buffers are [rows][k_pad / 32][S][32]: for each 32-deep K-step the S
+// slices of one row are adjacent, so the loads of a K-step read whole 128-byte
+// lines (two slices per line).  Offset of slice 0 of indices k .. k+7 of row r
+// (k a multiple of 8); slice p is kSBK elements further.
+template <int S>
+__device__ __forceinline__ long long digit_offset(long long r, int k, int Kp) {
+  return r * Kp * S + (long long)(k / kSBK) * (S * kSBK) + (k % kSBK);
+}
+
 // ---------------------------------------------------------------------------
 // slicing
 // ---------------------------------------------------------------------------
@@ -64,7 +73,7 @@ __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
 // agree on its maximum through shuffles.
 template <int S>
 __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict__ X, long long ld,
-                                                       int R, int K, int Kp, long long sstride,
+                                                       int R, int K, int Kp,
                                                        __bf16* __restrict__ out, int* __restrict__ ex,
                                                        int ex_stride) {
   static_assert(kExpChunk == 16 * 8, "a chunk is cut by 16 threads of 8 values");
@@ -97,7 +106,7 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
       bf16x8 v;
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = d[j][p];
-      *reinterpret_cast<bf16x8*>(out + p * sstride + (long long)r * Kp + k0) = v;
+      *reinterpret_cast<bf16x8*>(out + digit_offset<S>(r, k0, Kp) + p * kSBK) = v;
     }
   }
 }
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(256) void rc_rowmax_kernel(const double* __restrict
 // Digits: thread per (row, 8 consecutive k); consecutive threads take consecutive rows.
 template <int S>
 __global__ __launch_bounds__(256) void slice_rc_kernel(const double* __restrict__ X, long long ld,
-                                                       int R, int Rp, int K, int Kp, long long sstride,
+                                                       int R, int Rp, int K, int Kp,
                                                        const int* __restrict__ ex,
                                                        __bf16* __restrict__ out) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -140,7 +149,7 @@ __global__ __launch_bounds__(256) void slice_rc_kernel(const double* __restrict_
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = d[j][p];
-    *reinterpret_cast<bf16x8*>(out + p * sstride + (long long)r * Kp + k0) = v;
+    *reinterpret_cast<bf16x8*>(out + digit_offset<S>(r, k0, Kp) + p * kSBK) = v;
   }
 }
 
@@ -149,12 +158,10 @@ __global__ __launch_bounds__(256) void slice_rc_kernel(const double* __restrict_
 // ---------------------------------------------------------------------------
 
 struct SplitArgs {
-  const __bf16* A;   // [S][rows][Kp] digits, row 0 = this product's first row
-  long long sa;      // slice stride of A
+  const __bf16* A;   // [rows][Kp/32][S][32] digits, row 0 = this product's first row
   const int* ea;     // exponents of A's rows (same row origin); with chunk exponents
                      // ea[c * ea_stride + m] for K-chunk c
   const __bf16* B;
-  long long sb;
   const int* eb;
   int ea_stride, eb_stride;
   int M, N, Kp;
@@ -207,13 +214,12 @@ __device__ __forceinline__ void wait_vm(int n) {
 // Per K-step a wave reads the S slices of its column blocks once and streams the
 // S slices of its row blocks; the exact float32 sums of a chunk are drained into
 // float64 with their scale 2^(-8g), and the epilogue applies 2^(eA + eB).
-// Measured at o=40 v=360 P=1200 (S = 4): 48% of the bf16 MFMA peak; with the operand loads
-// removed (a timing experiment) 67%, so a third of the time is the global->LDS
-// pipeline and the rest LDS reads, drains and barriers.  Splitting the products
-// of a sub-tile over two waves (fewer registers, larger sub-tiles) or one wave
-// per SIMD (64 x 32 sub-tiles) measured the same or slower.  Raising the wave
-// priority over the product loop gains 2-3%; the same in the float64 and
-// float32 contraction loses 2%.
+// Measured at o=40 v=360 P=1200 (S = 4): the MFMA units busy 54% of the time;
+// the global->LDS pipeline is the largest loss, then LDS reads, drains and
+// barriers.  Splitting the products of a sub-tile over two waves (fewer
+// registers, larger sub-tiles) or one wave per SIMD (64 x 32 sub-tiles)
+// measured the same or slower.  Raising the wave priority over the product loop
+// gains 2-3%; the same in the float64 and float32 contraction loses 2%.
 template <int S, int D, int EPI, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) {
   // the contraction's operands carry chunk exponents
@@ -255,22 +261,26 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
 
   const int lrow = lane >> 2;
   const int lchunk = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
-  const long long loff = (long long)lrow * g.Kp + lchunk * 8;
+  const long long row_len = (long long)g.Kp * S;  // digits of one row, all slices
+  const long long loff = (long long)lrow * row_len + lchunk * 8;
+  // a wave loads slab after slab of the same 16 rows (consecutive slices), so
+  // its instructions of a K-step cover whole lines
   auto issue = [&](int kt) {
     unsigned char* st = lds + (kt % kStages) * STAGE;
-    const int ko = kt * kSBK;
+    const long long ko = (long long)kt * (S * kSBK);
+    constexpr int NA = ASLABS / WAVES, NB = BSLABS / WAVES;
 #pragma unroll
-    for (int j = 0; j < ASLABS / WAVES; ++j) {
-      const int ai = wave + WAVES * j, s = ai / (kSBM / 16), r = ai % (kSBM / 16);
+    for (int j = 0; j < NA; ++j) {
+      const int ai = wave * NA + j, r = ai / S, s = ai % S;
       __builtin_amdgcn_global_load_lds(
-          (const void*)(g.A + s * g.sa + (long long)(m0 + 16 * r) * g.Kp + loff + ko),
+          (const void*)(g.A + (long long)(m0 + 16 * r) * row_len + loff + ko + s * kSBK),
           (lds_void_t*)(st + (s * kSBM + 16 * r) * kRowBytes), 16, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < BSLABS / WAVES; ++j) {
-      const int bi = wave + WAVES * j, s = bi / (kSBN / 16), r = bi % (kSBN / 16);
+    for (int j = 0; j < NB; ++j) {
+      const int bi = wave * NB + j, r = bi / S, s = bi % S;
       __builtin_amdgcn_global_load_lds(
-          (const void*)(g.B + s * g.sb + (long long)(n0 + 16 * r) * g.Kp + loff + ko),
+          (const void*)(g.B + (long long)(n0 + 16 * r) * row_len + loff + ko + s * kSBK),
           (lds_void_t*)(st + A_BYTES + (s * kSBN + 16 * r) * kRowBytes), 16, 0, 0);
     }
   };
@@ -472,7 +482,7 @@ template <int S>
 int slice_kc(const double* X, long long ld, int R, int K, const SliceDims& d, __bf16* out, int* ex,
              hipStream_t s) {
   hipLaunchKernelGGL((slice_kc_kernel<S>), dim3(d.rows_pad), dim3(256), 0, s, X, ld, R, K, d.k_pad,
-                     (long long)d.rows_pad * d.k_pad, out, ex, d.rows_pad);
+                     out, ex, d.rows_pad);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -483,8 +493,7 @@ int slice_rc(const double* X, long long ld, int R, int K, const SliceDims& d, __
                      d.rows_pad, K, ex);
   const long long total = (long long)d.rows_pad * (d.k_pad / 8);
   hipLaunchKernelGGL((slice_rc_kernel<S>), dim3(static_cast<unsigned>((total + 255) / 256)),
-                     dim3(256), 0, s, X, ld, R, d.rows_pad, K, d.k_pad,
-                     (long long)d.rows_pad * d.k_pad, ex, out);
+                     dim3(256), 0, s, X, ld, R, d.rows_pad, K, d.k_pad, ex, out);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -505,9 +514,7 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
   double* V = reinterpret_cast<double*>(ws + pl.off_V);
   __bf16* Vs = reinterpret_cast<__bf16*>(ws + pl.off_Vs);
   int* Ve = reinterpret_cast<int*>(ws + pl.off_Vexp);
-  const long long sL = (long long)dL.rows_pad * dL.k_pad;
-  const long long st = (long long)dt.rows_pad * dt.k_pad;
-  const long long sV = (long long)dV.rows_pad * dV.k_pad;
+  const long long Lrow = (long long)dL.k_pad * S;  // digits per row of L's buffer
 
   tr(CC_LADDER_PHASE_PREP, 0, 0);
   int rc = slice_rc<S>(L, v2, static_cast<int>(v2), P, dL, Ls, Le, s);
@@ -521,8 +528,8 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
       // packed rows (a,b), b >= a: columns (b,d) from b = a0 on
       const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
       SplitArgs b{};
-      b.A = Ls + r0 * dL.k_pad; b.sa = sL; b.ea = Le + r0;
-      b.B = Ls + r0 * dL.k_pad; b.sb = sL; b.eb = Le + r0;
+      b.A = Ls + r0 * Lrow; b.ea = Le + r0;
+      b.B = Ls + r0 * Lrow; b.eb = Le + r0;
       b.ea_stride = b.eb_stride = 0;
       b.M = na * v; b.N = static_cast<int>((long long)(v - a0) * v); b.Kp = dL.k_pad;
       b.C = V; b.ldc = 0; b.v = v; b.a0 = a0;
@@ -536,8 +543,8 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
       tr(CC_LADDER_PHASE_SLICE, blk, 1);
       if (rc) return rc;
       SplitArgs c{};
-      c.A = ts; c.sa = st; c.ea = te;
-      c.B = Vs; c.sb = sV; c.eb = Ve;
+      c.A = ts; c.ea = te;
+      c.B = Vs; c.eb = Ve;
       c.ea_stride = dt.rows_pad;
       c.eb_stride = dV.rows_pad;
       c.M = o * o; c.N = static_cast<int>(npairs); c.Kp = dt.k_pad;
@@ -549,8 +556,8 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
       continue;
     }
     SplitArgs b{};
-    b.A = Ls + r0 * dL.k_pad; b.sa = sL; b.ea = Le + r0;
-    b.B = Ls; b.sb = sL; b.eb = Le;
+    b.A = Ls + r0 * Lrow; b.ea = Le + r0;
+    b.B = Ls; b.eb = Le;
     b.ea_stride = b.eb_stride = 0;  // one exponent per row
     b.M = na * v; b.N = static_cast<int>(v2); b.Kp = dL.k_pad;
     b.C = V; b.ldc = 0; b.v = v;
@@ -563,8 +570,8 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
     tr(CC_LADDER_PHASE_SLICE, blk, 1);
     if (rc) return rc;
     SplitArgs c{};
-    c.A = ts; c.sa = st; c.ea = te;
-    c.B = Vs; c.sb = sV; c.eb = Ve;
+    c.A = ts; c.ea = te;
+    c.B = Vs; c.eb = Ve;
     c.ea_stride = dt.rows_pad;  // exponents per (row, chunk)
     c.eb_stride = dV.rows_pad;
     c.M = o * o; c.N = na * v; c.Kp = dt.k_pad;

@@ -8,9 +8,10 @@
 
 namespace ccl {
 
-// Geometry of a digit buffer [S][rows_pad][k_pad]: rows padded so that every
-// workgroup tile of a product stays inside it, the contracted index to whole
-// 32-deep MFMA steps (zero digits in the padding).
+// Geometry of a digit buffer [rows_pad][k_pad / 32][S][32] (the S slices of a
+// row's 32-deep K-step adjacent): rows padded so that every workgroup tile of a
+// product stays inside it, the contracted index to whole 32-deep MFMA steps
+// (zero digits in the padding).
 struct SliceDims {
   int rows_pad;
   int k_pad;
