@@ -35,13 +35,14 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kSBM = 64;    // workgroup tile rows (M)
 constexpr int kSBN = 128;   // workgroup tile columns (N)
 constexpr int kSBK = 32;    // K per stage = one bf16 MFMA depth
 constexpr int kChunkSteps = 4;  // K-steps per exact float32 chunk (128 contracted indices)
 static_assert(kChunkSteps * kSBK == kExpChunk, "one exponent per exact chunk");
 
-// Balanced base-256 digits of y in (-1, 1): writes S bf16 digits, most significant first.
+// Balanced base-256 digits of y in (-1, 1): y = 2^-8 sum_p q_p 2^(-8p) with
+// integers |q_0| <= 256, |q_p| <= 128.  Slice p holds q_p 2^(-8p) (exact in
+// bf16), so the product of slices p and q carries its own scale 2^(-8(p+q)).
 template <int S>
 __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
 #pragma unroll
@@ -49,7 +50,7 @@ __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
     y *= 256.0;
     const double q = rint(y);
     y -= q;
-    d[p] = static_cast<__bf16>(static_cast<float>(q));
+    d[p] = static_cast<__bf16>(static_cast<float>(ldexp(q, -8 * p)));
   }
 }
 
@@ -175,20 +176,19 @@ struct SplitArgs {
   int tiles_m, tiles_n, group_m;
 };
 
-// Workgroup tile 64 x 128 (M x N), K-steps of 32 (one bf16 MFMA depth).  Slice
+// Workgroup tile BM x 128 (M x N), K-steps of 32 (one bf16 MFMA depth).  Slice
 // products (p, q) (0-based) are kept when p + q < S + D - 1: D = 1 is the
 // triangle p'+q' <= S+1 of 1-based slices, D = 2 adds its next anti-diagonal.
 //
 // Operand tiles go from global memory straight into LDS (global_load_lds_dwordx4:
-// lane l of a wave writes 16 bytes at the wave's LDS base + 16*l), three K-steps
-// in flight in a ring of LDS stages, one barrier per K-step.  A 16-row slab of a
+// lane l of a wave writes 16 bytes at the wave's LDS base + 16*l), STAGES - 1
+// K-steps loading ahead in a ring of LDS stages, one barrier per K-step.  A 16-row slab of a
 // slice is one load instruction: lane l takes row l/4 and physical 16-byte slot
 // l%4, which holds the logical k-chunk (l%4) ^ ((row/2)%4); fragment reads undo the
 // XOR.  Keying on row/2 (pairs of 64-byte rows share a key) makes the 16-byte
 // fragment reads free of bank conflicts on gfx950; keying on row/4, or no
 // swizzle, costs one extra LDS cycle per read (measured with the hardware's
 // bank-conflict counter on a read-pattern probe).
-constexpr int kStages = 3;
 constexpr int kRowBytes = kSBK * 2;  // 64 bytes: one 32-deep row of bf16 digits
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -200,43 +200,47 @@ __device__ __forceinline__ void wait_vm(int n) {
   case N:         \
     __builtin_amdgcn_s_waitcnt(((N)&15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14)); \
     break;
-    CCL_VM(0) CCL_VM(3) CCL_VM(6) CCL_VM(9) CCL_VM(12)
+    CCL_VM(0) CCL_VM(3) CCL_VM(4) CCL_VM(6) CCL_VM(8) CCL_VM(9) CCL_VM(12)
 #undef CCL_VM
     default:
       __builtin_amdgcn_s_waitcnt(7 << 4 | 15 << 8);
   }
 }
 
-// Slice-pair GEMM.  Every wave owns a sub-tile and all NG anti-diagonal
-// accumulators of it: WAVES = 8 (two per SIMD, 32 x 32 sub-tiles of 2 x 2
-// blocks; S = 2 and 4) or WAVES = 4 (one per SIMD with up to 512 registers,
-// 64 x 32 sub-tiles of 4 x 2 blocks; S = 3, whose stage does not split 8 ways).
+// Slice-pair GEMM.  Every wave owns a sub-tile of MI x NJ 16 x 16 blocks and
+// NACC anti-diagonal accumulators of it (shapes per slice count in SplitShape).
 // Per K-step a wave reads the S slices of its column blocks once and streams the
-// S slices of its row blocks; the exact float32 sums of a chunk are drained into
-// float64 with their scale 2^(-8g), and the epilogue applies 2^(eA + eB).
-// Measured at o=40 v=360 P=1200 (S = 4): the MFMA units busy 54% of the time;
-// the global->LDS pipeline is the largest loss, then LDS reads, drains and
-// barriers.  Splitting the products of a sub-tile over two waves (fewer
-// registers, larger sub-tiles) or one wave per SIMD (64 x 32 sub-tiles)
-// measured the same or slower.  Raising the wave priority over the product loop
-// gains 2-3%; the same in the float64 and float32 contraction loses 2%.
-template <int S, int D, int EPI, int WAVES>
+// S slices of its row blocks; the float32 sums of a chunk (exact for the first
+// NACC - 1 anti-diagonals, and for the last when it holds one) are drained into
+// float64, and the epilogue applies 2^(eA + eB).
+// Measured at o=40 v=360 P=1200 (S = 4): the MFMA units busy 62% of the time.
+// 128 x 128 tiles (two stages) against 64 x 128 (three stages): 15% faster
+// build, 4% faster contraction (whose 1600 rows waste 4% in 128-row tiles).
+// A third stage for B only (all 160 KB of LDS) measured 2% slower; splitting the
+// products of a sub-tile over two waves, or one wave per SIMD, the same or
+// slower.  Raising the wave priority over the product loop gains 2-3%; the same
+// in the float64 and float32 contraction loses 2%.
+template <int S, int D, int EPI, int WAVES, int BM, int STAGES, int NACC>
 __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) {
   // the contraction's operands carry chunk exponents
   constexpr bool CE = EPI == EPI_ACC || EPI == EPI_PAIR;
-  constexpr int NG = S + D - 1;
-  constexpr int MI = WAVES == 8 ? 2 : 4;   // row blocks per wave
+  constexpr int NG = S + D - 1;            // anti-diagonals kept
   constexpr int NJ = 2;                    // column blocks per wave
   constexpr int WCOLS = kSBN / (16 * NJ);  // waves along N (4)
-  constexpr int A_BYTES = S * kSBM * kRowBytes;
+  constexpr int MI = BM / (16 * (WAVES / WCOLS));  // row blocks per wave
+  constexpr int A_BYTES = S * BM * kRowBytes;
   constexpr int B_BYTES = S * kSBN * kRowBytes;
-  constexpr int STAGE = A_BYTES + B_BYTES;
-  constexpr int ASLABS = S * kSBM / 16, BSLABS = S * kSBN / 16;  // 16-row slabs per stage
-  constexpr int LOADS = (ASLABS + BSLABS) / WAVES;                // per wave
+  constexpr int ASLABS = S * BM / 16, BSLABS = S * kSBN / 16;  // 16-row slabs per stage
+  constexpr int LOADS = (ASLABS + BSLABS) / WAVES;              // per wave and stage
+  constexpr int NLA = ASLABS / WAVES, NLB = BSLABS / WAVES;     // loads per wave and stage
+  constexpr int AHEAD = STAGES - 1;                              // K-steps loading ahead
+  constexpr int LDS_BYTES = STAGES * (A_BYTES + B_BYTES);
   static_assert((ASLABS % WAVES) == 0 && (BSLABS % WAVES) == 0, "slab split");
-  static_assert(WCOLS * (WAVES / WCOLS) == WAVES && (WAVES / WCOLS) * MI * 16 == kSBM, "wave grid");
-  static_assert(kStages * STAGE <= 160 * 1024, "LDS");
-  __shared__ __attribute__((aligned(1024))) unsigned char lds[kStages * STAGE];
+  static_assert(WCOLS * (WAVES / WCOLS) == WAVES && (WAVES / WCOLS) * MI * 16 == BM, "wave grid");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+  static_assert(NACC >= 1 && NACC <= NG && (NACC == NG || NACC >= 3), "accumulator groups");
+  static_assert(AHEAD >= 1 && LOADS * (AHEAD - 1) <= 12, "vmcnt of the loads left in flight");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[LDS_BYTES];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -253,11 +257,11 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
       if (g.row_tiles[mid] <= id) lo = mid; else hi = mid - 1;
     }
     tm = lo;
-    tn = pack_first_tile(tm, kSBM, kSBN, g.v) + (id - g.row_tiles[tm]);
+    tn = pack_first_tile(tm, BM, kSBN, g.v) + (id - g.row_tiles[tm]);
   } else {
     tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   }
-  const int m0 = tm * kSBM, n0 = tn * kSBN;
+  const int m0 = tm * BM, n0 = tn * kSBN;
 
   const int lrow = lane >> 2;
   const int lchunk = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
@@ -265,23 +269,29 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   const long long loff = (long long)lrow * row_len + lchunk * 8;
   // a wave loads slab after slab of the same 16 rows (consecutive slices), so
   // its instructions of a K-step cover whole lines
-  auto issue = [&](int kt) {
-    unsigned char* st = lds + (kt % kStages) * STAGE;
+  // stage rings: A's STAGES stages, then B's
+  auto a_stage = [&](int kt) { return lds + (kt % STAGES) * A_BYTES; };
+  auto b_stage = [&](int kt) { return lds + STAGES * A_BYTES + (kt % STAGES) * B_BYTES; };
+  auto issue_a = [&](int kt) {
+    unsigned char* st = a_stage(kt);
     const long long ko = (long long)kt * (S * kSBK);
-    constexpr int NA = ASLABS / WAVES, NB = BSLABS / WAVES;
 #pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int ai = wave * NA + j, r = ai / S, s = ai % S;
+    for (int j = 0; j < NLA; ++j) {
+      const int ai = wave * NLA + j, r = ai / S, s = ai % S;
       __builtin_amdgcn_global_load_lds(
           (const void*)(g.A + (long long)(m0 + 16 * r) * row_len + loff + ko + s * kSBK),
-          (lds_void_t*)(st + (s * kSBM + 16 * r) * kRowBytes), 16, 0, 0);
+          (lds_void_t*)(st + (s * BM + 16 * r) * kRowBytes), 16, 0, 0);
     }
+  };
+  auto issue_b = [&](int kt) {
+    unsigned char* st = b_stage(kt);
+    const long long ko = (long long)kt * (S * kSBK);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int bi = wave * NB + j, r = bi / S, s = bi % S;
+    for (int j = 0; j < NLB; ++j) {
+      const int bi = wave * NLB + j, r = bi / S, s = bi % S;
       __builtin_amdgcn_global_load_lds(
           (const void*)(g.B + (long long)(n0 + 16 * r) * row_len + loff + ko + s * kSBK),
-          (lds_void_t*)(st + A_BYTES + (s * kSBN + 16 * r) * kRowBytes), 16, 0, 0);
+          (lds_void_t*)(st + (s * kSBN + 16 * r) * kRowBytes), 16, 0, 0);
     }
   };
 
@@ -294,13 +304,18 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
   const int nk = g.Kp / kSBK;
 
-  issue(0);
-  if (nk > 1) issue(1);
-  for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
-    // one exact chunk: float32 sums of every anti-diagonal
-    f32x4 acc[NG][MI][NJ];
+  // issue order: per K-step A then B; the wait counts below follow from it
 #pragma unroll
-    for (int q = 0; q < NG; ++q)
+  for (int k = 0; k < AHEAD; ++k) {
+    if (k < nk) issue_a(k);
+    if (k < nk) issue_b(k);
+  }
+  for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
+    // one chunk: float32 sums per anti-diagonal g = p + q (the last accumulator
+    // takes every g >= NACC - 1)
+    f32x4 acc[NACC][MI][NJ];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q)
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -309,17 +324,23 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     for (int u = 0; u < kChunkSteps; ++u) {
       const int kt = k0 + u;
       if (kt < nk) {
-        wait_vm(kt + 1 < nk ? LOADS : 0);
+        // this K-step's loads are done when at most the later K-steps' remain
+        const int later = (nk - 1 - kt) < (AHEAD - 1) ? (nk - 1 - kt) : (AHEAD - 1);
+        wait_vm(later * LOADS);
         __builtin_amdgcn_s_barrier();
-        if (kt + 2 < nk) issue(kt + 2);
-        const unsigned char* st = lds + (kt % kStages) * STAGE;
+        if (kt + AHEAD < nk) {
+          issue_a(kt + AHEAD);
+          issue_b(kt + AHEAD);
+        }
+        const unsigned char* sta = a_stage(kt);
+        const unsigned char* stb = b_stage(kt);
         bf16x8 fb[S][NJ];
 #pragma unroll
         for (int q = 0; q < S; ++q)
 #pragma unroll
           for (int j = 0; j < NJ; ++j)
             fb[q][j] = *reinterpret_cast<const bf16x8*>(
-                st + A_BYTES + (q * kSBN + wn + 16 * j) * kRowBytes + frag_off);
+                stb + (q * kSBN + wn + 16 * j) * kRowBytes + frag_off);
         // raised priority while this wave issues its products: the other wave
         // on the SIMD then takes its LDS reads and drains between them
         __builtin_amdgcn_s_setprio(1);
@@ -329,25 +350,26 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
           bf16x8 fa[MI];
 #pragma unroll
           for (int i = 0; i < MI; ++i)
-            fa[i] = *reinterpret_cast<const bf16x8*>(st + (p * kSBM + wm + 16 * i) * kRowBytes +
+            fa[i] = *reinterpret_cast<const bf16x8*>(sta + (p * BM + wm + 16 * i) * kRowBytes +
                                                      frag_off);
 #pragma unroll
           for (int q = 0; q < S; ++q) {
             if (p + q >= NG) continue;
+            const int gq = (p + q) < NACC - 1 ? (p + q) : NACC - 1;
 #pragma unroll
             for (int i = 0; i < MI; ++i)
 #pragma unroll
               for (int j = 0; j < NJ; ++j)
-                acc[p + q][i][j] =
-                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[q][j], acc[p + q][i][j], 0, 0, 0);
+                acc[gq][i][j] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[q][j], acc[gq][i][j], 0, 0, 0);
           }
         }
         __builtin_amdgcn_s_setprio(0);
       }
     }
     if constexpr (CE) {
-      // this chunk's row and column scales 2^eA, 2^eB; the groups are first
-      // combined at unit scale, then scaled once per element
+      // this chunk's row and column scales 2^eA, 2^eB; the groups (each with
+      // its own scale already) are first combined, then scaled once per element
       const int c = k0 / kChunkSteps;
       double sa[MI][4], sb[NJ];
 #pragma unroll
@@ -364,27 +386,22 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            double u = 0.0, scale = 1.0 / 65536.0;
+            double u = 0.0;
 #pragma unroll
-            for (int q = 0; q < NG; ++q) {
-              u = fma(static_cast<double>(acc[q][i][j][r]), scale, u);
-              scale *= 1.0 / 256.0;
-            }
-            acc64[i][j][r] = fma(u, sa[i][r] * sb[j], acc64[i][j][r]);
+            for (int q = 0; q < NACC; ++q) u += static_cast<double>(acc[q][i][j][r]);
+            acc64[i][j][r] = fma(u, sa[i][r] * sb[j] * (1.0 / 65536.0), acc64[i][j][r]);
           }
     } else {
-      double scale = 1.0 / 65536.0;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
+      for (int q = 0; q < NACC; ++q)
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              acc64[i][j][r] = fma(static_cast<double>(acc[q][i][j][r]), scale, acc64[i][j][r]);
-        scale *= 1.0 / 256.0;
-      }
+              acc64[i][j][r] =
+                  fma(static_cast<double>(acc[q][i][j][r]), 1.0 / 65536.0, acc64[i][j][r]);
     }
   }
 
@@ -439,22 +456,38 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
 
 // Tile-row offsets of the packed build's compact grid (one thread; a few
 // thousand tile rows at most).
-__global__ void split_pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v) {
+__global__ void split_pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, int v, int bm) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   int acc = 0;
   for (int tm = 0; tm < tiles_m; ++tm) {
     row_tiles[tm] = acc;
-    const int first = pack_first_tile(tm, kSBM, kSBN, v);
+    const int first = pack_first_tile(tm, bm, kSBN, v);
     acc += first < tiles_n ? tiles_n - first : 0;
   }
   row_tiles[tiles_m] = acc;
 }
 
+// Kernel shape per slice count.  S = 4: 128 x 128 tiles in two 64 KB stages,
+// 8 waves of 64 x 32 sub-tiles, anti-diagonals g >= 2 (scales <= 2^-16 of the
+// leading one) in one rounded float32 accumulator so that the sub-tile fits 256
+// registers; S = 2: 128 x 128 tiles in four 32 KB stages, every anti-diagonal
+// exact; S = 3: 64 x 128 tiles in three stages and 4 waves (its stage does not
+// split 8 ways) of 64 x 32 sub-tiles, exact.
+template <int S, int D>
+struct SplitShape {
+  static constexpr int NG = S + D - 1;
+  static constexpr int W = S == 3 ? 4 : 8;
+  static constexpr int BM = S == 3 ? 64 : 128;
+  static constexpr int STAGES = S == 4 ? 2 : (S == 2 ? 4 : 3);
+  static constexpr int NACC = S == 4 && NG > 3 ? 3 : NG;
+};
+
 template <int S, int D, int EPI>
 int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
+  using Sh = SplitShape<S, D>;
   SplitArgs a = a0;
   if (a.M <= 0 || a.N <= 0) return CC_LADDER_OK;
-  a.tiles_m = (a.M + kSBM - 1) / kSBM;
+  a.tiles_m = (a.M + Sh::BM - 1) / Sh::BM;
   a.tiles_n = (a.N + kSBN - 1) / kSBN;
   const long long tiles = (long long)a.tiles_m * a.tiles_n;
   if (tiles > 0x7fffffffLL) return CC_LADDER_EINVAL;
@@ -464,17 +497,16 @@ int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
     if (!a.row_tiles) return CC_LADDER_EINVAL;
     long long needed = 0;
     for (int tm = 0; tm < a.tiles_m; ++tm) {
-      const int first = pack_first_tile(tm, kSBM, kSBN, a.v);
+      const int first = pack_first_tile(tm, Sh::BM, kSBN, a.v);
       needed += first < a.tiles_n ? a.tiles_n - first : 0;
     }
     if (needed <= 0) return CC_LADDER_OK;
     hipLaunchKernelGGL(split_pack_rows_kernel, dim3(1), dim3(1), 0, s,
-                       const_cast<int*>(a.row_tiles), a.tiles_m, a.tiles_n, a.v);
+                       const_cast<int*>(a.row_tiles), a.tiles_m, a.tiles_n, a.v, Sh::BM);
     grid = needed;
   }
-  constexpr int W = (S == 3) ? 4 : 8;  // 8 waves need the slabs of a stage to split 8 ways
-  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, W>), dim3(static_cast<unsigned>(grid)),
-                     dim3(64 * W), 0, s, a);
+  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, Sh::W, Sh::BM, Sh::STAGES, Sh::NACC>),
+                     dim3(static_cast<unsigned>(grid)), dim3(64 * Sh::W), 0, s, a);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 

@@ -13,6 +13,20 @@ from tests.gpu_common import TOL_SPLIT, TOL_SPLIT_WORKLOAD, announce, dev, host,
 pytestmark = pytest.mark.gpu
 SPLIT = 2
 
+# Kernel against the NumPy model of the digit scheme.  Digit products and the
+# exact chunk sums agree on both sides, so only float64 rounding of the drains
+# separates them (1e-12) -- except that with four slices the kernel sums the
+# anti-diagonals p + q >= 2 (at most 2^-16 of the leading one) in one float32
+# accumulator: a float32 model of that rounding moves the small cases by 4e-11
+# to 7e-11, while dropping any single product of the last anti-diagonal moves
+# them by more than 5e-10, so 2e-10 still pins every product.
+TOL_MODEL_EXACT = 1e-12
+TOL_MODEL_MERGED = 2e-10
+
+
+def tol_model(slices, depth):
+    return TOL_MODEL_MERGED if slices == 4 and slices + depth - 1 > 3 else TOL_MODEL_EXACT
+
 
 def run_split(native, L, t, R0, slices, **kw):
     R = dev(R0)
@@ -25,13 +39,11 @@ def run_split(native, L, t, R0, slices, **kw):
 @pytest.mark.parametrize("slices,depth", [(2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)])
 @pytest.mark.parametrize("o,v,P", [(5, 20, 75), (9, 37, 101), (3, 44, 131)])
 def test_split_kernel_implements_the_digit_scheme(gpu_lib, o, v, P, slices, depth):
-    # digit products and chunk sums are exact on both sides: only float64
-    # rounding of the drains separates the kernel from the scheme
     announce("split-model", o, v, P, slices, depth)
     L, t, _ = random_general(o, v, P, 500 + o + v)
     model = split_model.ladder(L, t, slices, depth)
     got = run_split(gpu_lib, L, t, np.zeros_like(t), slices, split_depth=depth, a_block=7)
-    assert rel_fro(got, model) < 1e-12
+    assert rel_fro(got, model) < tol_model(slices, depth)
 
 
 @pytest.mark.parametrize("slices", [2, 3, 4])
@@ -124,8 +136,8 @@ def _pair_symmetric(t):
                                            (3, 130, 17, 40), (2, 3, 2, 0), (16, 64, 200, 1)])
 def test_split_pair_symmetric_path(gpu_lib, o, v, P, a_block):
     # packed integral rows a <= b with the digit scheme: entries a <= b are the
-    # scheme's values for those rows (model at 1e-12), entries a > b their exact
-    # mirrors, and the whole is within the scheme's tolerance of the oracle
+    # scheme's values for those rows, entries a > b their exact mirrors, and the
+    # whole is within the scheme's tolerance of the oracle
     announce("split-pairsym", o, v, P, "a_block", a_block)
     L, t, _ = random_general(o, v, P, 710 + o + v)
     t = _pair_symmetric(t)
@@ -133,7 +145,7 @@ def test_split_pair_symmetric_path(gpu_lib, o, v, P, a_block):
     got = run_split(gpu_lib, L, t, R0, 4, a_block=a_block, pair_symmetric=True) - R0
     upper = np.triu(np.ones((v, v), dtype=bool))[None, None]
     model = split_model.ladder(L, t, 4, 2)
-    assert rel_fro(np.where(upper, got, 0.0), np.where(upper, model, 0.0)) < 1e-12
+    assert rel_fro(np.where(upper, got, 0.0), np.where(upper, model, 0.0)) < tol_model(4, 2)
     off = ~np.eye(v, dtype=bool)[None, None]
     # exact mirrors (one computed value stored twice), seen on a zero start
     got0 = run_split(gpu_lib, L, t, np.zeros_like(t), 4, a_block=a_block, pair_symmetric=True)
