@@ -45,12 +45,16 @@ static_assert(kChunkSteps * kSBK == kExpChunk, "one exponent per exact chunk");
 // bf16), so the product of slices p and q carries its own scale 2^(-8(p+q)).
 template <int S>
 __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
+  static_assert(S <= 4, "slice scales 2^(-8p) as float constants");
 #pragma unroll
   for (int p = 0; p < S; ++p) {
     y *= 256.0;
     const double q = rint(y);
     y -= q;
-    d[p] = static_cast<__bf16>(static_cast<float>(ldexp(q, -8 * p)));
+    // |q| <= 256 is exact as an int and as a float, and so is q 2^(-8p); going
+    // through int keeps the bf16 conversion a plain exact one
+    const float scale = 1.0f / static_cast<float>(1u << (8 * p));
+    d[p] = static_cast<__bf16>(static_cast<float>(static_cast<int>(q)) * scale);
   }
 }
 
@@ -81,18 +85,30 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
   const int r = blockIdx.x;
   const int tid = threadIdx.x;
   const double* row = X + (long long)r * ld;
+  // rows starting on 16 bytes load 8 values as four 16-byte vectors
+  const bool vec = r < R && (reinterpret_cast<unsigned long long>(row) & 15) == 0;
   for (int base = 0; base < Kp; base += 256 * 8) {
     const int k0 = base + tid * 8;
     const int cstart = base + (tid & ~15) * 8;  // first index of this lane's chunk
     if (cstart >= Kp) break;                    // the chunk's 16 lanes leave together
     double x[8];
+    if (vec && k0 + 8 <= K) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 y = *reinterpret_cast<const double2*>(row + k0 + 2 * j);
+        x[2 * j] = y.x;
+        x[2 * j + 1] = y.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + j;
+        x[j] = (r < R && k < K) ? row[k] : 0.0;
+      }
+    }
     double m = 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = k0 + j;
-      x[j] = (r < R && k < K) ? row[k] : 0.0;
-      m = fmax(m, fabs(x[j]));
-    }
+    for (int j = 0; j < 8; ++j) m = fmax(m, fabs(x[j]));
 #pragma unroll
     for (int w = 8; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, 16));
     int e = 0;
