@@ -63,8 +63,12 @@ extern "C" {
 typedef enum {
   CC_LADDER_FP64 = 0,        /* float64 MFMA throughout */
   CC_LADDER_FP32 = 1,        /* float32 operands and MFMA, float32 partial sums drained to float64 */
-  CC_LADDER_SPLIT_BF16 = 2   /* operands cut into bf16 slices on shared per-row exponents; slice
-                                products on bf16 MFMA, exact float32 chunks drained to float64 */
+  CC_LADDER_SPLIT_BF16 = 2   /* operands cut into bf16 digit slices on shared exponents (per row
+                                for the integral build, per row and 128-index chunk for the
+                                contraction); slice products on bf16 MFMA, summed in float32
+                                over 128-index chunks (exactly, except that with 4 slices the
+                                products scaled by 2^-16 or less share one rounded sum) and
+                                drained to float64 */
 } cc_ladder_precision;
 
 /* opts.flags bits */

@@ -1,5 +1,6 @@
-"""GPU parity of the split-bf16 form (exponent-aligned bf16 digits, exact
-float32 chunks drained to float64) against the float64 oracle."""
+"""GPU parity of the split-bf16 form (exponent-aligned bf16 digits, float32
+chunk sums drained to float64) against the float64 oracle and the NumPy
+model of the digit scheme."""
 import numpy as np
 import pytest
 import torch
