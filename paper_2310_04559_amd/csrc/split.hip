@@ -75,22 +75,32 @@ __device__ __forceinline__ long long digit_offset(long long r, int k, int Kp) {
 // One workgroup per output row (R_pad rows, the padding rows get zero digits).
 // Exponents per (row, chunk of kExpChunk): ex[c * ex_stride + r].  The 16
 // threads that cut one chunk (8 values each) are adjacent lanes of one wave and
-// agree on its maximum through shuffles.
+// agree on its maximum through shuffles.  A wave's 512 indices are 16 K-steps,
+// whose digits are S KB of contiguous memory: the wave lays them out in a
+// private LDS block and stores them as whole 1 KB rows (a lane's own digits
+// would cover only 64 bytes of a line per store).
 template <int S>
 __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict__ X, long long ld,
                                                        int R, int K, int Kp,
                                                        __bf16* __restrict__ out, int* __restrict__ ex,
                                                        int ex_stride) {
   static_assert(kExpChunk == 16 * 8, "a chunk is cut by 16 threads of 8 values");
+  constexpr int STEP_BYTES = S * kSBK * 2;  // one K-step of one row, all slices
+  __shared__ __attribute__((aligned(16))) unsigned char stage[4][16 * STEP_BYTES];
   const int r = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  unsigned char* wl = stage[wave];
   const double* row = X + (long long)r * ld;
+  unsigned char* orow = reinterpret_cast<unsigned char*>(out + (long long)r * Kp * S);
   // rows starting on 16 bytes load 8 values as four 16-byte vectors
   const bool vec = r < R && (reinterpret_cast<unsigned long long>(row) & 15) == 0;
+  // every thread runs every iteration (indices past Kp are cut as zeros and not
+  // stored), so the wave-level exchange below always has the whole wave
   for (int base = 0; base < Kp; base += 256 * 8) {
     const int k0 = base + tid * 8;
     const int cstart = base + (tid & ~15) * 8;  // first index of this lane's chunk
-    if (cstart >= Kp) break;                    // the chunk's 16 lanes leave together
     double x[8];
     if (vec && k0 + 8 <= K) {
 #pragma unroll
@@ -113,18 +123,28 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
     for (int w = 8; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, 16));
     int e = 0;
     if (m > 0.0) (void)frexp(m, &e);  // max|x| < 2^e over the chunk
-    if ((tid & 15) == 0) ex[(cstart / kExpChunk) * (long long)ex_stride + r] = e;
-    if (k0 >= Kp) continue;
+    if ((tid & 15) == 0 && cstart < Kp) ex[(cstart / kExpChunk) * (long long)ex_stride + r] = e;
     __bf16 d[8][S];
 #pragma unroll
     for (int j = 0; j < 8; ++j) digits<S>(ldexp(x[j], -e), d[j]);
+    // memory image of the wave's 16 K-steps: step lane/4, slice p, piece lane%4
 #pragma unroll
     for (int p = 0; p < S; ++p) {
       bf16x8 v;
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = d[j][p];
-      *reinterpret_cast<bf16x8*>(out + digit_offset<S>(r, k0, Kp) + p * kSBK) = v;
+      *reinterpret_cast<bf16x8*>(wl + (lane >> 2) * STEP_BYTES + p * kSBK * 2 + (lane & 3) * 16) = v;
     }
+    __builtin_amdgcn_wave_barrier();
+    const int step0 = (base + wave * 512) / kSBK;  // first K-step of the wave's block
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const int byte = i * 1024 + lane * 16;
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(wl + byte);
+      if ((step0 + byte / STEP_BYTES) * kSBK < Kp)
+        *reinterpret_cast<bf16x8*>(orow + (long long)step0 * STEP_BYTES + byte) = v;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
