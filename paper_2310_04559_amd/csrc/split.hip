@@ -37,8 +37,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kSBN = 128;   // workgroup tile columns (N)
 constexpr int kSBK = 32;    // K per stage = one bf16 MFMA depth
-constexpr int kChunkSteps = 4;  // K-steps per exact float32 chunk (128 contracted indices)
-static_assert(kChunkSteps * kSBK == kExpChunk, "one exponent per exact chunk");
+constexpr int kChunkSteps = 4;  // K-steps per float32 chunk (128 contracted indices)
+static_assert(kChunkSteps * kSBK == kExpChunk, "one exponent per chunk");
 
 // Balanced base-256 digits of y in (-1, 1): y = 2^-8 sum_p q_p 2^(-8p) with
 // integers |q_0| <= 256, |q_p| <= 128.  Slice p holds q_p 2^(-8p) (exact in
