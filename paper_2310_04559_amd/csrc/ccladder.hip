@@ -84,11 +84,23 @@ template <class Tr, int EPI>
 bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, int* rc) {
   if (!vec_ok(g0.A, g0.lda) || !vec_ok(g0.B, g0.ldb)) return false;
   GemmArgs<typename Tr::T> g = g0;
-  g.tiles_m = (g.M + kDBM - 1) / kDBM;
+  // float64: 160-row tiles where their grid finishes first
+  constexpr bool kTall = !Tr::kDrain;
+  const bool tall = kTall && choose_kc_tile_rows(g.M, g.N) == 160;
+  const int bm = tall ? 160 : kDBM;
+  g.tiles_m = (g.M + bm - 1) / bm;
   g.tiles_n = (g.N + kDBN - 1) / kDBN;
   const long long tiles = (long long)g.tiles_m * g.tiles_n;
   if (tiles > 0x7fffffffLL) return false;
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
+  if constexpr (kTall) {
+    if (tall) {
+      hipLaunchKernelGGL((gemm_kc_direct_kernel<Tr, EPI, 160>), dim3(static_cast<unsigned>(tiles)),
+                         dim3(kDThreads), 0, stream, g);
+      *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+      return true;
+    }
+  }
   hipLaunchKernelGGL((gemm_kc_direct_kernel<Tr, EPI>), dim3(static_cast<unsigned>(tiles)),
                      dim3(kDThreads), 0, stream, g);
   *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;

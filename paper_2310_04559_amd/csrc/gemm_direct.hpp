@@ -33,32 +33,40 @@ __device__ __forceinline__ void d_wait_vm(int n) {
   case N:          \
     __builtin_amdgcn_s_waitcnt(((N)&15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14)); \
     break;
-    CCL_DVM(0) CCL_DVM(6)
+    CCL_DVM(0) CCL_DVM(6) CCL_DVM(7)
 #undef CCL_DVM
     default:
       __builtin_amdgcn_s_waitcnt(7 << 4 | 15 << 8);
   }
 }
 
-template <class Tr, int EPI>
+// BM = 128 (4 x 4 blocks per wave) or, for float64 without drains, 160 (5 x 4
+// blocks per wave, 156 KB of LDS): 160-row tiles divide o^2 = 1600 exactly and pad
+// 900 and 3600 less than 128-row ones.
+template <class Tr, int EPI, int BM = kDBM>
 __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<typename Tr::T> g) {
   static_assert(EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PART, "K-contiguous epilogues");
+  static_assert(BM == kDBM || (BM == 160 && !Tr::kDrain), "tile heights");
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using Chunk = typename Tr::Chunk;
   constexpr int CH = Tr::CH;                 // elements per 16 bytes
   constexpr int BK = kDRow / sizeof(T);      // K per step (16 float64 / 32 float32)
-  constexpr int A_BYTES = kDBM * kDRow;      // 16 KB
+  constexpr int MI = BM / 32;                // row blocks per wave (2 wave rows)
+  constexpr int A_BYTES = BM * kDRow;        // 16 or 20 KB
   constexpr int B_BYTES = kDBN * kDRow;      // 32 KB
   constexpr int STAGE = A_BYTES + B_BYTES;
-  constexpr int LOADS = (kDBM + kDBN) / 8 / 8;  // 8-row slabs per wave per stage (= 6)
+  constexpr int A_SLABS = BM / 8, JA = (A_SLABS + 7) / 8;  // 8-row slabs of A; per wave at most JA
+  static_assert(kDStages * STAGE <= 160 * 1024, "LDS");
   __shared__ __attribute__((aligned(1024))) unsigned char lds[kDStages * STAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = (wave >> 2) * 64;
+  const int wm = (wave >> 2) * (BM / 2);
   const int wn = (wave & 3) * 64;
+  // slabs this wave loads per stage: A slabs wave + 8j < A_SLABS, and 4 of B
+  const int LOADS = (A_SLABS - wave + 7) / 8 + 4;
   int tm, tn;
   const int nk_all = (g.K + BK - 1) / BK;
   int ks0 = 0, ks1 = nk_all;  // K-steps of this workgroup
@@ -74,18 +82,18 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
   } else {
     tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   }
-  const int m0 = tm * kDBM, n0 = tn * kDBN;
+  const int m0 = tm * BM, n0 = tn * kDBN;
 
-  // Slabs: A rows 8*(wave + 8*j), j < 2; B rows 8*(wave + 8*j), j < 4.  The
+  // Slabs: A rows 8*(wave + 8*j), j < JA; B rows 8*(wave + 8*j), j < 4.  The
   // swizzle of a lane depends on the slab's parity only (slab origin 8*s rows).
   const int lrow = lane >> 3;
   const int sw_even = ((lane & 7) ^ ((lane >> 4) & 7)) * CH;        // slab index even
   const int sw_odd = ((lane & 7) ^ ((4 + (lane >> 4)) & 7)) * CH;   // slab index odd
   const int my_sw = (wave & 1) ? sw_odd : sw_even;  // slabs wave + 8j share the wave's parity
-  const T* pa[2];
+  const T* pa[JA];
   const T* pb[4];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < JA; ++j) {
     int row = m0 + 8 * (wave + 8 * j) + lrow;
     row = row < g.M ? row : g.M - 1;
     pa[j] = g.A + (long long)row * g.lda + my_sw;
@@ -100,9 +108,10 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
     unsigned char* st = lds + (kt % kDStages) * STAGE;
     const int ko = kt * BK;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      __builtin_amdgcn_global_load_lds((const void*)(pa[j] + ko),
-                                       (lds_void*)(st + 8 * (wave + 8 * j) * kDRow), 16, 0, 0);
+    for (int j = 0; j < JA; ++j)
+      if (wave + 8 * j < A_SLABS)
+        __builtin_amdgcn_global_load_lds((const void*)(pa[j] + ko),
+                                         (lds_void*)(st + 8 * (wave + 8 * j) * kDRow), 16, 0, 0);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       __builtin_amdgcn_global_load_lds((const void*)(pb[j] + ko),
@@ -121,16 +130,17 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
       *reinterpret_cast<Chunk*>(dst + 16 * lane) = c;
     };
 #pragma unroll
-    for (int j = 0; j < 2; ++j) one(pa[j], st + 8 * (wave + 8 * j) * kDRow);
+    for (int j = 0; j < JA; ++j)
+      if (wave + 8 * j < A_SLABS) one(pa[j], st + 8 * (wave + 8 * j) * kDRow);
 #pragma unroll
     for (int j = 0; j < 4; ++j) one(pb[j], st + A_BYTES + 8 * (wave + 8 * j) * kDRow);
     __builtin_amdgcn_s_waitcnt(0xF | (7 << 4) | (3 << 14));  // lgkmcnt(0): the LDS writes landed
   };
 
-  Acc acc[4][4];
-  f64x4 acc64[4][4];
+  Acc acc[MI][4];
+  f64x4 acc64[MI][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       acc[i][j] = Acc{0, 0, 0, 0};
@@ -164,9 +174,9 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
 #pragma unroll
       for (int gi = 0; gi < 2; ++gi) {
         const int chunk = ((4 * gi + (lane >> 4)) ^ fsw) * 16;
-        Chunk fa[4], fb[4];
+        Chunk fa[MI], fb[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < MI; ++i)
           fa[i] = *reinterpret_cast<const Chunk*>(st + (wm + 16 * i) * kDRow + frow + chunk);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -174,14 +184,14 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
 #pragma unroll
         for (int e = 0; e < CH; ++e)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = Tr::mfma(fa[i][e], fb[j][e], acc[i][j]);
       }
     }
     if (Tr::kDrain) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -200,7 +210,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
     if (n >= g.N) continue;
     const EpiCol ec = epi_col<T, EPI>(g, n);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + Tr::row_of(lane, r);

@@ -184,6 +184,19 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   }, plan);
 }
 
+int choose_kc_tile_rows(long long M, long long N) {
+  constexpr long long kCUs = 256;  // compute units of one MI355X
+  constexpr long long kTN = 256;   // the K-contiguous kernel's tile width
+  const long long tn = (N + kTN - 1) / kTN;
+  // one workgroup per CU at a time: the launch lasts about (rounds of the grid
+  // over the CUs) x (one tile's time, proportional to its height)
+  auto span = [&](long long bm) {
+    const long long tiles = (M + bm - 1) / bm * tn;
+    return (tiles + kCUs - 1) / kCUs * bm;
+  };
+  return span(160) < span(128) ? 160 : 128;
+}
+
 int choose_k_splits(long long M, long long N, long long K, int bk) {
   constexpr long long kCUs = 256;           // compute units of one MI355X
   constexpr long long kTM = 128, kTN = 256;  // the K-contiguous kernel's tile

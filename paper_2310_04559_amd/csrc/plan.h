@@ -68,6 +68,10 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
 // occupied i for the hole-hole ladder), integral block [n_p][o][v][v]
 // ([n_p][o][o][o] for the hole-hole ladder).  Same search and return codes as
 // make_plan; flags are CC_LADDER_EUNSUPPORTED, SPLIT_BF16 too.
+// Tile height (128 or 160 rows) of the float64 K-contiguous product C[M][N]: the
+// one whose grid of M x N tiles finishes first on the device's compute units.
+int choose_kc_tile_rows(long long M, long long N);
+
 // K ranges for a K-contiguous product of M x N (tiles of 128 x 256) over K
 // elements in steps of `bk`: 1 when the tiles fill the chip, otherwise the count
 // that minimises the waves per unit of work (at least 64 K-steps per range).
