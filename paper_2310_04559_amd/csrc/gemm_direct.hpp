@@ -66,7 +66,9 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
   const int wm = (wave >> 2) * (BM / 2);
   const int wn = (wave & 3) * 64;
   // slabs this wave loads per stage: A slabs wave + 8j < A_SLABS, and 4 of B
-  const int LOADS = (A_SLABS - wave + 7) / 8 + 4;
+  // (compile-time 6 when the A slabs split evenly over the 8 waves)
+  constexpr bool A_EVEN = A_SLABS % 8 == 0;
+  const int LOADS = A_EVEN ? A_SLABS / 8 + 4 : (A_SLABS - wave + 7) / 8 + 4;
   int tm, tn;
   const int nk_all = (g.K + BK - 1) / BK;
   int ks0 = 0, ks1 = nk_all;  // K-steps of this workgroup
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
     const int ko = kt * BK;
 #pragma unroll
     for (int j = 0; j < JA; ++j)
-      if (wave + 8 * j < A_SLABS)
+      if (A_EVEN || wave + 8 * j < A_SLABS)
         __builtin_amdgcn_global_load_lds((const void*)(pa[j] + ko),
                                          (lds_void*)(st + 8 * (wave + 8 * j) * kDRow), 16, 0, 0);
 #pragma unroll
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
     };
 #pragma unroll
     for (int j = 0; j < JA; ++j)
-      if (wave + 8 * j < A_SLABS) one(pa[j], st + 8 * (wave + 8 * j) * kDRow);
+      if (A_EVEN || wave + 8 * j < A_SLABS) one(pa[j], st + 8 * (wave + 8 * j) * kDRow);
 #pragma unroll
     for (int j = 0; j < 4; ++j) one(pb[j], st + A_BYTES + 8 * (wave + 8 * j) * kDRow);
     __builtin_amdgcn_s_waitcnt(0xF | (7 << 4) | (3 << 14));  // lgkmcnt(0): the LDS writes landed
