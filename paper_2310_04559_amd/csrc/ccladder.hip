@@ -84,25 +84,36 @@ template <class Tr, int EPI>
 bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, int* rc) {
   if (!vec_ok(g0.A, g0.lda) || !vec_ok(g0.B, g0.ldb)) return false;
   GemmArgs<typename Tr::T> g = g0;
-  // float64: 160-row tiles where their grid finishes first
+  // the tiling whose grids finish first: 160-row tiles (float64), or 128-row
+  // tiles plus a 64-row launch over the remainder rows (plain accumulation,
+  // where the rows can be offset)
   constexpr bool kTall = !Tr::kDrain;
-  const bool tall = kTall && choose_kc_tile_rows(g.M, g.N) == 160;
-  const int bm = tall ? 160 : kDBM;
-  g.tiles_m = (g.M + bm - 1) / bm;
-  g.tiles_n = (g.N + kDBN - 1) / kDBN;
-  const long long tiles = (long long)g.tiles_m * g.tiles_n;
-  if (tiles > 0x7fffffffLL) return false;
-  g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
-  if constexpr (kTall) {
-    if (tall) {
-      hipLaunchKernelGGL((gemm_kc_direct_kernel<Tr, EPI, 160>), dim3(static_cast<unsigned>(tiles)),
-                         dim3(kDThreads), 0, stream, g);
-      *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
-      return true;
+  long long main_rows = g.M;
+  const int bm = choose_kc_tiling(g.M, g.N, kTall, EPI == EPI_ACC, &main_rows);
+  auto launch = [&](auto kernel, const GemmArgs<typename Tr::T>& a, int rows_per_tile) {
+    GemmArgs<typename Tr::T> b = a;
+    b.tiles_m = (b.M + rows_per_tile - 1) / rows_per_tile;
+    b.tiles_n = (b.N + kDBN - 1) / kDBN;
+    b.group_m = b.tiles_m < 16 ? b.tiles_m : 16;
+    const long long tiles = (long long)b.tiles_m * b.tiles_n;
+    hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(tiles)), dim3(kDThreads), 0, stream, b);
+  };
+  if ((long long)((g.M + 63) / 64) * ((g.N + kDBN - 1) / kDBN) > 0x7fffffffLL) return false;
+  if (bm == 160) {
+    if constexpr (kTall) launch(gemm_kc_direct_kernel<Tr, EPI, 160>, g, 160);
+  } else if (bm == 64) {
+    if constexpr (EPI == EPI_ACC) {
+      GemmArgs<typename Tr::T> rest = g;
+      g.M = static_cast<int>(main_rows);
+      rest.M -= g.M;
+      rest.A += main_rows * g.lda;
+      rest.C = static_cast<double*>(g.C) + main_rows * g.ldc;
+      launch(gemm_kc_direct_kernel<Tr, EPI>, g, kDBM);
+      launch(gemm_kc_direct_kernel<Tr, EPI, 64>, rest, 64);
     }
+  } else {
+    launch(gemm_kc_direct_kernel<Tr, EPI>, g, kDBM);
   }
-  hipLaunchKernelGGL((gemm_kc_direct_kernel<Tr, EPI>), dim3(static_cast<unsigned>(tiles)),
-                     dim3(kDThreads), 0, stream, g);
   *rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
   return true;
 }

@@ -33,27 +33,28 @@ __device__ __forceinline__ void d_wait_vm(int n) {
   case N:          \
     __builtin_amdgcn_s_waitcnt(((N)&15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14)); \
     break;
-    CCL_DVM(0) CCL_DVM(6) CCL_DVM(7)
+    CCL_DVM(0) CCL_DVM(5) CCL_DVM(6) CCL_DVM(7)
 #undef CCL_DVM
     default:
       __builtin_amdgcn_s_waitcnt(7 << 4 | 15 << 8);
   }
 }
 
-// BM = 128 (4 x 4 blocks per wave) or, for float64 without drains, 160 (5 x 4
-// blocks per wave, 156 KB of LDS): 160-row tiles divide o^2 = 1600 exactly and pad
-// 900 and 3600 less than 128-row ones.
+// BM = 128 (4 x 4 blocks per wave); for float64 without drains also 160 (5 x 4
+// blocks per wave, 156 KB of LDS), whose tiles divide o^2 = 1600 exactly and pad
+// 900 and 3600 less; and 64 (2 x 4 blocks per wave) for the remainder rows of a
+// product whose last 128-row tile row would be at most half full.
 template <class Tr, int EPI, int BM = kDBM>
 __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<typename Tr::T> g) {
   static_assert(EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PART, "K-contiguous epilogues");
-  static_assert(BM == kDBM || (BM == 160 && !Tr::kDrain), "tile heights");
+  static_assert(BM == kDBM || BM == 64 || (BM == 160 && !Tr::kDrain), "tile heights");
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using Chunk = typename Tr::Chunk;
   constexpr int CH = Tr::CH;                 // elements per 16 bytes
   constexpr int BK = kDRow / sizeof(T);      // K per step (16 float64 / 32 float32)
   constexpr int MI = BM / 32;                // row blocks per wave (2 wave rows)
-  constexpr int A_BYTES = BM * kDRow;        // 16 or 20 KB
+  constexpr int A_BYTES = BM * kDRow;        // 8, 16 or 20 KB
   constexpr int B_BYTES = kDBN * kDRow;      // 32 KB
   constexpr int STAGE = A_BYTES + B_BYTES;
   constexpr int A_SLABS = BM / 8, JA = (A_SLABS + 7) / 8;  // 8-row slabs of A; per wave at most JA
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
   const int wm = (wave >> 2) * (BM / 2);
   const int wn = (wave & 3) * 64;
   // slabs this wave loads per stage: A slabs wave + 8j < A_SLABS, and 4 of B
-  // (compile-time 6 when the A slabs split evenly over the 8 waves)
+  // (compile-time 5 or 6 when the A slabs split evenly over the 8 waves)
   constexpr bool A_EVEN = A_SLABS % 8 == 0;
   const int LOADS = A_EVEN ? A_SLABS / 8 + 4 : (A_SLABS - wave + 7) / 8 + 4;
   int tm, tn;

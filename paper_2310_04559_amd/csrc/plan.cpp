@@ -184,17 +184,29 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   }, plan);
 }
 
-int choose_kc_tile_rows(long long M, long long N) {
+int choose_kc_tiling(long long M, long long N, bool tall, bool split, long long* main_rows) {
   constexpr long long kCUs = 256;  // compute units of one MI355X
   constexpr long long kTN = 256;   // the K-contiguous kernel's tile width
   const long long tn = (N + kTN - 1) / kTN;
-  // one workgroup per CU at a time: the launch lasts about (rounds of the grid
+  // one workgroup per CU at a time: a launch lasts about (rounds of its grid
   // over the CUs) x (one tile's time, proportional to its height)
-  auto span = [&](long long bm) {
-    const long long tiles = (M + bm - 1) / bm * tn;
+  auto span = [&](long long rows, long long bm) {
+    const long long tiles = (rows + bm - 1) / bm * tn;
     return (tiles + kCUs - 1) / kCUs * bm;
   };
-  return span(160) < span(128) ? 160 : 128;
+  const long long rem = M % 128;
+  long long best = span(M, 128);
+  int choice = 128;
+  if (tall && span(M, 160) < best) {
+    best = span(M, 160);
+    choice = 160;
+  }
+  if (split && M > 128 && rem > 0 && rem <= 64 && span(M - rem, 128) + span(rem, 64) < best) {
+    best = span(M - rem, 128) + span(rem, 64);
+    choice = 64;
+  }
+  *main_rows = choice == 64 ? M - rem : M;
+  return choice;
 }
 
 int choose_k_splits(long long M, long long N, long long K, int bk) {

@@ -68,9 +68,13 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
 // occupied i for the hole-hole ladder), integral block [n_p][o][v][v]
 // ([n_p][o][o][o] for the hole-hole ladder).  Same search and return codes as
 // make_plan; flags are CC_LADDER_EUNSUPPORTED, SPLIT_BF16 too.
-// Tile height (128 or 160 rows) of the float64 K-contiguous product C[M][N]: the
-// one whose grid of M x N tiles finishes first on the device's compute units.
-int choose_kc_tile_rows(long long M, long long N);
+// Tiling of the K-contiguous product C[M][N] (tiles 256 columns wide) that
+// finishes first on the device's compute units: 128-row tiles; 160-row tiles
+// (when `tall` is allowed); or 128-row tiles over the first *main_rows rows and
+// one launch of 64-row tiles over the rest (when `split` is allowed and the
+// last 128-row tile row would be at most half full).  Returns 128, 160 or 64
+// (the split); *main_rows is M unless split.
+int choose_kc_tiling(long long M, long long N, bool tall, bool split, long long* main_rows);
 
 // K ranges for a K-contiguous product of M x N (tiles of 128 x 256) over K
 // elements in steps of `bk`: 1 when the tiles fill the chip, otherwise the count

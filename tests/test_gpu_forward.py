@@ -57,20 +57,22 @@ def test_forward_c1_workload(gpu_lib, precision):
     assert rel_fro(got.transpose(1, 0, 3, 2), got) < 10 * TOL[precision]
 
 
-def test_forward_tall_tiles(gpu_lib):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forward_tall_and_remainder_tiles(gpu_lib, precision):
     # o^2 = 1600 amplitude rows: for a 64-virtual block of v = 80 (20 tile
-    # columns) 160-row float64 tiles fill the 256 CUs in one round where 128-row
-    # ones need two, so the planner takes them; the last block (16 virtuals, 5
-    # columns) takes 128-row tiles.  Whole tensor against the oracle, and integer
+    # columns) 128-row tiles need two rounds of the 256 CUs, so float64 takes
+    # 160-row tiles (one round) and float32 128-row tiles over 1536 rows plus a
+    # 64-row launch over the last 64; the last block (16 virtuals, 5 columns)
+    # takes plain 128-row tiles.  Whole tensor against the oracle, and integer
     # inputs exactly.
     o, v, P = 40, 80, 30
-    announce("forward-tall", o, v, P)
+    announce("forward-tall-remainder", o, v, P, "precision", precision)
     L, t, _ = random_general(o, v, P, 4242)
     R0 = np.random.default_rng(11).standard_normal(t.shape)
-    got = run_forward(gpu_lib, L, t, R0, 0, a_block=64)
-    assert rel_fro(got - R0, oracle.ladder_forward(L, t)) < TOL[0]
+    got = run_forward(gpu_lib, L, t, R0, precision, a_block=64)
+    assert rel_fro(got - R0, oracle.ladder_forward(L, t)) < TOL[precision]
     Li, ti = integer_inputs(o, v, P, 4243)
-    got = run_forward(gpu_lib, Li, ti, np.zeros_like(ti), 0, a_block=64)
+    got = run_forward(gpu_lib, Li, ti, np.zeros_like(ti), precision, a_block=64)
     assert np.array_equal(got, oracle.ladder_forward(Li, ti))
 
 
