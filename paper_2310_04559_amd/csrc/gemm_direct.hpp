@@ -3,8 +3,9 @@
 //   C[m][n] (+)= sum_k A[m*lda + k] B[n*ldb + k]   (both operands KC; EPI_ACC, EPI_PAIR,
 //                                                   or EPI_PART: one K-range per workgroup)
 //
-// 512 threads = 8 wave64s in a 2 x 4 grid over a 128 x 256 tile; each wave owns
-// 64 x 64 = 4 x 4 MFMA blocks (v_mfma_f64_16x16x4_f64 or v_mfma_f32_16x16x4_f32).
+// 512 threads = 8 wave64s in a 2 x 4 grid over a BM x 256 tile (BM = 128; the
+// K-contiguous kernel also 64 and, for float64, 160); each wave owns (BM/2) x 64 =
+// BM/32 x 4 MFMA blocks (v_mfma_f64_16x16x4_f64 or v_mfma_f32_16x16x4_f32).
 // Every K-step is 128 bytes of each operand row.  Operand slabs of 8 rows go
 // from global memory into LDS with global_load_lds_dwordx4 (lane l of a wave
 // writes 16 bytes at the wave's LDS base + 16*l): lane l takes row l/8 and
