@@ -85,11 +85,12 @@ bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   if (!vec_ok(g0.A, g0.lda) || !vec_ok(g0.B, g0.ldb)) return false;
   GemmArgs<typename Tr::T> g = g0;
   // the tiling whose grids finish first: 160-row tiles (float64), or 128-row
-  // tiles plus a 64-row launch over the remainder rows (plain accumulation,
-  // where the rows can be offset)
+  // tiles plus a 64-row launch over the remainder rows (plain or pair-mirrored
+  // accumulation, whose rows can be offset)
   constexpr bool kTall = !Tr::kDrain;
+  constexpr bool kSplit = EPI == EPI_ACC || EPI == EPI_PAIR;
   long long main_rows = g.M;
-  const int bm = choose_kc_tiling(g.M, g.N, kTall, EPI == EPI_ACC, &main_rows);
+  const int bm = choose_kc_tiling(g.M, g.N, kTall, kSplit, &main_rows);
   auto launch = [&](auto kernel, const GemmArgs<typename Tr::T>& a, int rows_per_tile) {
     GemmArgs<typename Tr::T> b = a;
     b.tiles_m = (b.M + rows_per_tile - 1) / rows_per_tile;
@@ -102,12 +103,15 @@ bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   if (bm == 160) {
     if constexpr (kTall) launch(gemm_kc_direct_kernel<Tr, EPI, 160>, g, 160);
   } else if (bm == 64) {
-    if constexpr (EPI == EPI_ACC) {
+    if constexpr (kSplit) {
       GemmArgs<typename Tr::T> rest = g;
       g.M = static_cast<int>(main_rows);
       rest.M -= g.M;
       rest.A += main_rows * g.lda;
-      rest.C = static_cast<double*>(g.C) + main_rows * g.ldc;
+      if constexpr (EPI == EPI_PAIR)
+        rest.m_off = g.m_off + g.M;  // the mirrored store needs the global (i,j) row
+      else
+        rest.C = static_cast<double*>(g.C) + main_rows * g.ldc;
       launch(gemm_kc_direct_kernel<Tr, EPI>, g, kDBM);
       launch(gemm_kc_direct_kernel<Tr, EPI, 64>, rest, 64);
     }

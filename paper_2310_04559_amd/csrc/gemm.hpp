@@ -114,6 +114,7 @@ struct GemmArgs {
   int split_steps;       // EPI_PART: K-steps per split
   long long part_stride; // EPI_PART: elements between consecutive splits' partials
   double alpha;          // EPI_ACC: C += alpha * acc (1, or 2 for a term counted twice)
+  int m_off = 0;         // EPI_PAIR: global row of this launch's row 0 (a remainder launch)
 };
 
 // First needed tile column of tile row tm in the packed build: columns whose
@@ -188,9 +189,10 @@ __device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, co
     static_cast<T*>(g.C)[row * v * v + (long long)cc * v + c.off] = static_cast<T>(val);
   } else {  // EPI_PAIR
     double* C = static_cast<double*>(g.C);
-    C[(long long)m * g.ldc + c.off] += val;
+    const int mg = m + g.m_off;
+    C[(long long)mg * g.ldc + c.off] += val;
     if (c.x != c.y) {
-      const int i = m / g.o, j = m - i * g.o;
+      const int i = mg / g.o, j = mg - i * g.o;
       C[(long long)(j * g.o + i) * g.ldc + (long long)c.y * v + c.x] += val;
     }
   }
