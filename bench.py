@@ -223,9 +223,21 @@ def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inp, target_s=15.0):
-    """The oracle (NumPy, float64 BLAS) over the first k virtuals of the loop
-    over a, k sized to roughly target_s seconds of host work."""
+    """The oracle (NumPy/SciPy, float64 BLAS) over the first k values of its
+    explicit sum over the contracted index c, k sized to roughly target_s
+    seconds of host work, scaled to the whole forward."""
     import oracle
 
     try:
@@ -237,15 +249,16 @@ def cpu_baseline(inp, target_s=15.0):
         cores = os.cpu_count()
     o, v, P = inp.o, inp.v, inp.P
     t0 = time.perf_counter()
-    R = oracle.ladder_forward(inp.L_vv, inp.t, a_begin=0, a_end=1)
+    R = oracle.ladder_forward(inp.L_vv, inp.t, c_begin=0, c_end=1)
     one = time.perf_counter() - t0
     k = int(max(1, min(v - 1, target_s / max(one, 1e-3))))
     t0 = time.perf_counter()
-    oracle.ladder_forward(inp.L_vv, inp.t, R=R, a_begin=1, a_end=1 + k)
+    oracle.ladder_forward(inp.L_vv, inp.t, R=R, c_begin=1, c_end=1 + k)
     dt = time.perf_counter() - t0
     flops = 2.0 * (P + o * o) * float(v) ** 3 * k
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle forward over a in [1,{1 + k}) of the o={o},v={v},P={P} workload "
+            "cpu_model": cpu_model(),
+            "sample": f"oracle forward over c in [1,{1 + k}) of the o={o},v={v},P={P} workload "
                       f"({k}/{v} of its flops, {dt:.1f} s)"}
 
 

@@ -29,11 +29,17 @@ What it computes (arXiv 2310.04559):
   einsum subscript; reading its first operand the way the paper translates a
   Cholesky operand ``abcd`` into ``xac,xbd`` gives this sum.
 
-Algorithm: the paper's loop over one virtual index (Sec. "Pythonic
-implementations of the CC vector function", the tensordot variant that keeps
-intermediates at v^3): for each ``a`` the slice ``V[a,:,:,:]`` is built from
-the Cholesky vectors and contracted with the amplitudes.  Each step is one
-library matrix product in float64; there is no further blocking or fusion.
+Algorithm: the definitions written out as sums, one library matrix product
+per step, in float64.  The forward terms sum over the first contracted
+virtual index ``c`` in an explicit loop: for each ``c`` the integrals
+``(ac|bd)`` (or ``(ad|bc)``) for every ``a, b, d`` come from the Cholesky
+vectors (eq. cholesky), and their product with ``t[:, :, c, :]`` over ``d`` is
+added to the whole of ``R``.  The accumulation runs in place through BLAS
+``dgemm`` with ``beta = 1`` (``_acc_product_nt``), so no temporary of R's size
+is made.  The adjoint and the occupied-index terms loop over their first
+output index instead, building that index's slice of the integral, which is
+the same definition summed in another order.  There is no further blocking
+or fusion.
 
 Layouts: ``L[x][p][q]`` (the virtual-virtual block), ``L_ov[x][k][c]``,
 ``L_oo[x][i][k]``, ``t, R, lam[i][j][a][b]``, ``X[i][j][k][l]``,
@@ -42,6 +48,7 @@ Layouts: ``L[x][p][q]`` (the virtual-virtual block), ``L_ov[x][k][c]``,
 from __future__ import annotations
 
 import numpy as np
+from scipy.linalg.blas import dgemm
 
 __all__ = ["ladder_forward", "ladder_backward", "ladder_pairs", "ladder_row", "ladder_loss",
            "exchange_forward", "exchange_backward", "intermediate_ijkl", "intermediate_ijbk",
@@ -71,41 +78,61 @@ def eri_slice(L: np.ndarray, a: int) -> np.ndarray:
     return Vc_bd.reshape(v, v, v).transpose(1, 0, 2)
 
 
-def ladder_forward(L, t, R=None, a_begin: int = 0, a_end=None) -> np.ndarray:
-    """``R[i,j,a,b] += sum_{c,d} (ac|bd) t[i,j,c,d]`` (eq. vfunction).
+def _acc_product_nt(C, A, Bt):
+    """``C += A @ Bt.T`` in place for C-contiguous float64 ``C[m][n]``,
+    ``A[m][k]``, ``Bt[n][k]``: BLAS ``dgemm`` with ``beta = 1`` on the
+    column-major views (``C^T += Bt @ A^T``)."""
+    out = dgemm(1.0, Bt.T, A.T, beta=1.0, c=C.T, trans_a=1, overwrite_c=1)
+    if not np.shares_memory(out, C):
+        raise RuntimeError("dgemm did not accumulate in place")
 
+
+def ladder_forward(L, t, R=None, c_begin: int = 0, c_end=None) -> np.ndarray:
+    """``R[i,j,a,b] += sum_{c,d} (ac|bd) t[i,j,c,d]`` (eq. vfunction) with
+    ``(ac|bd) = sum_x L[x,a,c] L[x,b,d]`` (eq. cholesky).
+
+    The sum over ``c`` is the explicit loop: per ``c``,
+    ``Vc[(a,b), d] = (ac|bd)`` and ``R[(i,j),(a,b)] += sum_d t[i,j,c,d] Vc[(a,b),d]``.
     ``R`` is accumulated in place when given, else a zero array is made.
-    ``[a_begin, a_end)`` restricts the loop over ``a`` (a bounded sample)."""
+    ``[c_begin, c_end)`` restricts the sum over ``c`` (a bounded sample of the work)."""
     L, t = _check(L, t)
     P, v, _ = L.shape
     o = t.shape[0]
     if R is None:
         R = np.zeros((o, o, v, v))
-    a_end = v if a_end is None else a_end
-    T = t.reshape(o * o, v * v)                       # [(i,j)][(c,d)]
-    for a in range(a_begin, a_end):
-        Va = eri_slice(L, a)                          # [b][c][d]
-        # R[(i,j), a, b] += sum_{(c,d)} T[(i,j),(c,d)] * Va[b,(c,d)]
-        R[:, :, a, :] += (T @ Va.reshape(v, v * v).T).reshape(o, o, v)
+    c_end = v if c_end is None else c_end
+    R2 = R.reshape(o * o, v * v)
+    if not np.shares_memory(R2, R):
+        raise ValueError("R must be C-contiguous")
+    Lf = L.reshape(P, v * v)                              # [x][(b,d)]
+    for c in range(c_begin, c_end):
+        Lc = np.ascontiguousarray(L[:, :, c])            # [x][a] = L[x,a,c]
+        Vc = (Lc.T @ Lf).reshape(v * v, v)               # [(a,b)][d] = (ac|bd)
+        Tc = np.ascontiguousarray(t[:, :, c, :]).reshape(o * o, v)   # [(i,j)][d]
+        _acc_product_nt(R2, Tc, Vc)
     return R
 
 
 def exchange_forward(L, t, R=None) -> np.ndarray:
     """Exchange partner of the ladder (eq. vfunction2):
     ``R[i,j,a,b] += sum_{c,d} (ad|bc) t[i,j,c,d]`` with
-    ``(ad|bc) = sum_x L[x,a,d] L[x,b,c]``; same loop over ``a``."""
+    ``(ad|bc) = sum_x L[x,a,d] L[x,b,c]``; the same explicit sum over ``c``:
+    per ``c``, ``Xc[(a,b), d] = (ad|bc)``."""
     L, t = _check(L, t)
     P, v, _ = L.shape
     o = t.shape[0]
     if R is None:
         R = np.zeros((o, o, v, v))
-    T = t.reshape(o * o, v * v)                       # [(i,j)][(c,d)]
-    Lf = L.reshape(P, v * v)
-    for a in range(v):
-        # X[d][(b,c)] = sum_x L[x,a,d] L[x,b,c]
-        X = (L[:, a, :].T @ Lf).reshape(v, v, v)      # [d][b][c]
-        Xa = X.transpose(1, 2, 0).reshape(v, v * v)   # [b][(c,d)]
-        R[:, :, a, :] += (T @ Xa.T).reshape(o, o, v)
+    R2 = R.reshape(o * o, v * v)
+    if not np.shares_memory(R2, R):
+        raise ValueError("R must be C-contiguous")
+    Lf = L.reshape(P, v * v)                              # [x][(a,d)]
+    for c in range(v):
+        Lc = np.ascontiguousarray(L[:, :, c])            # [x][b] = L[x,b,c]
+        X = (Lc.T @ Lf).reshape(v, v, v)                 # [b][a][d] = (ad|bc)
+        Xc = np.ascontiguousarray(X.transpose(1, 0, 2)).reshape(v * v, v)   # [(a,b)][d]
+        Tc = np.ascontiguousarray(t[:, :, c, :]).reshape(o * o, v)
+        _acc_product_nt(R2, Tc, Xc)
     return R
 
 

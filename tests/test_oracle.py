@@ -193,11 +193,134 @@ def test_accumulates_and_range_split():
     full = oracle.ladder_forward(L, t)
     acc = oracle.ladder_forward(L, t, R=R0.copy())
     assert rel_fro(acc, R0 + full) < 1e-14
-    part = oracle.ladder_forward(L, t, a_begin=0, a_end=3)
-    part = oracle.ladder_forward(L, t, R=part, a_begin=3)
+    # the sum over the contracted index c split into two ranges: the same
+    # products added in the same order
+    part = oracle.ladder_forward(L, t, c_begin=0, c_end=3)
+    part = oracle.ladder_forward(L, t, R=part, c_begin=3)
     assert np.array_equal(part, full)
-    head = oracle.ladder_forward(L, t, a_end=3)
-    assert np.all(head[:, :, 3:, :] == 0)
+    # a range of c is the ladder of the amplitudes restricted to that range
+    head = oracle.ladder_forward(L, t, c_end=3)
+    t_head = t.copy()
+    t_head[:, :, 3:, :] = 0.0
+    assert rel_fro(head, oracle.ladder_forward(L, t_head)) < 1e-15
+
+
+def test_in_place_accumulation_helper():
+    # the forward's BLAS step: C += A @ Bt^T, in place, for rectangular shapes
+    rng = np.random.default_rng(48)
+    for m, n, k in ((5, 7, 3), (1, 9, 4), (6, 1, 2)):
+        A, Bt = rng.standard_normal((m, k)), rng.standard_normal((n, k))
+        C = rng.standard_normal((m, n))
+        want = C + A @ Bt.T
+        ref = C
+        oracle._acc_product_nt(C, A, Bt)
+        assert C is ref and np.allclose(C, want, rtol=1e-14, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# flop counts: each nominal count equals twice the multiply-adds of an explicit
+# factorised evaluation (every integral built once, then contracted), checked
+# to compute the term itself, at several shapes so that every exponent and
+# coefficient of the formula is pinned
+# ---------------------------------------------------------------------------
+
+_COUNT_SHAPES = [(2, 3, 5), (3, 2, 4), (1, 4, 2)]
+
+
+def _count_build(rows, cols, K, left, right):
+    """Integrals G[r][s] = sum_x left(x, r) right(x, s), counting multiply-adds."""
+    G, macs = {}, 0
+    for r in rows:
+        for s_ in cols:
+            acc = 0.0
+            for x in range(K):
+                acc += left(x, r) * right(x, s_)
+                macs += 1
+            G[r, s_] = acc
+    return G, macs
+
+
+@pytest.mark.parametrize("o,v,P", _COUNT_SHAPES)
+def test_forward_flop_count(o, v, P):
+    L, t, _ = random_general(o, v, P, 49)
+    pairs = list(itertools.product(range(v), range(v)))
+    G, m1 = _count_build(pairs, pairs, P, lambda x, r: L[x, r[0], r[1]], lambda x, s_: L[x, s_[0], s_[1]])
+    R, m2 = np.zeros_like(t), 0
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        for c, d in pairs:
+            R[i, j, a, b] += G[(a, c), (b, d)] * t[i, j, c, d]
+            m2 += 1
+    assert rel_fro(R, oracle.ladder_forward(L, t)) < 1e-14
+    assert oracle.nominal_flops_forward(o, v, P) == 2 * (m1 + m2)
+
+
+@pytest.mark.parametrize("o,v,P", _COUNT_SHAPES)
+def test_backward_flop_count(o, v, P):
+    L, t, lam = random_general(o, v, P, 50)
+    pairs = list(itertools.product(range(v), range(v)))
+    G, m = _count_build(pairs, pairs, P, lambda x, r: L[x, r[0], r[1]], lambda x, s_: L[x, s_[0], s_[1]])
+    dt = np.zeros_like(t)
+    for i, j, c, d in itertools.product(range(o), range(o), range(v), range(v)):
+        for a, b in pairs:
+            dt[i, j, c, d] += lam[i, j, a, b] * G[(a, c), (b, d)]
+            m += 1
+    W = np.zeros((v, v, v, v))
+    for a, b, c, d in itertools.product(range(v), repeat=4):
+        for i, j in itertools.product(range(o), range(o)):
+            W[a, b, c, d] += lam[i, j, a, b] * t[i, j, c, d]
+            m += 1
+    dL = np.zeros_like(L)
+    for x, p, q in itertools.product(range(P), range(v), range(v)):
+        for b, d in pairs:          # first term: W[p,b,q,d] L[x,b,d]
+            dL[x, p, q] += W[p, b, q, d] * L[x, b, d]
+            m += 1
+        for a, c in pairs:          # second term: W[a,p,c,q] L[x,a,c]
+            dL[x, p, q] += W[a, p, c, q] * L[x, a, c]
+            m += 1
+    dL_ref, dt_ref = oracle.ladder_backward(L, t, lam)
+    assert rel_fro(dt, dt_ref) < 1e-14 and rel_fro(dL, dL_ref) < 1e-14
+    assert oracle.nominal_flops_backward(o, v, P) == 2 * m
+
+
+@pytest.mark.parametrize("o,v,P", _COUNT_SHAPES)
+def test_intermediate_flop_counts(o, v, P):
+    L, t, _ = random_general(o, v, P, 51)
+    Lov = random_ov(o, v, P, 52)
+    ov = list(itertools.product(range(o), range(v)))
+    vv = list(itertools.product(range(v), range(v)))
+    # X[i,j,k,l] = sum_cd (kc|ld) t[i,j,c,d]
+    G, m1 = _count_build(ov, ov, P, lambda x, r: Lov[x, r[0], r[1]], lambda x, s_: Lov[x, s_[0], s_[1]])
+    X, m2 = np.zeros((o, o, o, o)), 0
+    for i, j, k, l in itertools.product(range(o), repeat=4):
+        for c, d in vv:
+            X[i, j, k, l] += G[(k, c), (l, d)] * t[i, j, c, d]
+            m2 += 1
+    assert rel_fro(X, oracle.intermediate_ijkl(Lov, t)) < 1e-14
+    assert oracle.nominal_flops_ijkl(o, v, P) == 2 * (m1 + m2)
+    # Y[i,j,b,k] = sum_cd (bd|kc) t[i,j,c,d]
+    G, m1 = _count_build(vv, ov, P, lambda x, r: L[x, r[0], r[1]], lambda x, s_: Lov[x, s_[0], s_[1]])
+    Y, m2 = np.zeros((o, o, v, o)), 0
+    for i, j, b, k in itertools.product(range(o), range(o), range(v), range(o)):
+        for c, d in vv:
+            Y[i, j, b, k] += G[(b, d), (k, c)] * t[i, j, c, d]
+            m2 += 1
+    assert rel_fro(Y, oracle.intermediate_ijbk(L, Lov, t)) < 1e-14
+    assert oracle.nominal_flops_ijbk(o, v, P) == 2 * (m1 + m2)
+
+
+@pytest.mark.parametrize("o,v,P", _COUNT_SHAPES)
+def test_hole_ladder_flop_count(o, v, P):
+    _, t, _ = random_general(o, v, P, 53)
+    Loo = np.random.default_rng(54).standard_normal((P, o, o))
+    oo = list(itertools.product(range(o), range(o)))
+    G, m1 = _count_build(oo, oo, P, lambda x, r: Loo[x, r[0], r[1]], lambda x, s_: Loo[x, s_[0], s_[1]])
+    R, m2 = np.zeros_like(t), 0
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        for k, l in oo:
+            R[i, j, a, b] += G[(i, k), (j, l)] * t[k, l, a, b]
+            m2 += 1
+    assert rel_fro(R, oracle.hole_ladder(Loo, t)) < 1e-14
+    assert oracle.nominal_flops_hole(o, v, P) == 2 * (m1 + m2)
 
 
 def test_pairs_match_forward():
