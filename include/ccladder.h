@@ -63,12 +63,15 @@ extern "C" {
 typedef enum {
   CC_LADDER_FP64 = 0,        /* float64 MFMA throughout */
   CC_LADDER_FP32 = 1,        /* float32 operands and MFMA, float32 partial sums drained to float64 */
-  CC_LADDER_SPLIT_BF16 = 2   /* operands cut into bf16 digit slices on shared exponents (per row
-                                for the integral build, per row and 128-index chunk for the
-                                contraction); slice products on bf16 MFMA, summed in float32
-                                over 128-index chunks (exactly, except that with 4 slices the
-                                products scaled by 2^-16 or less share one rounded sum) and
-                                drained to float64 */
+  CC_LADDER_SPLIT_BF16 = 2   /* operands cut into bf16 slices, slice products on bf16 MFMA, summed
+                                in float32 over 128-index chunks and drained to float64.
+                                3 or 4 slices (default 4): digits on shared exponents (per row for
+                                the integral build, per row and 128-index chunk for the
+                                contraction), summed exactly, except that with 4 slices the
+                                products scaled by 2^-16 or less share one rounded sum.
+                                2 slices: the per-element split hi = bf16(x), lo = bf16(x - hi)
+                                (round to nearest even) with the products hi*hi, hi*lo, lo*hi,
+                                about 16 significant bits per operand */
 } cc_ladder_precision;
 
 /* opts.flags bits */
@@ -90,6 +93,13 @@ typedef enum {
                                         swapping it back; the adjoint returns the exchange term's
                                         gradients.  Combines with PAIR_SYMMETRIC and every form. */
 
+#define CC_LADDER_CHECK_SYMMETRY 4u  /* with PAIR_SYMMETRIC: verify the assertion before any other
+                                        work.  A kernel compares t (and, in the adjoint, lam) with
+                                        its pair transpose; the call then synchronises `stream` to
+                                        read the result and returns CC_LADDER_EINVAL, with the
+                                        outputs untouched, when some |x[i][j][c][d] - x[j][i][d][c]|
+                                        exceeds 2^-40 max|x|.  Ignored without PAIR_SYMMETRIC. */
+
 /* Kernel phases reported to an optional trace hook. */
 typedef enum {
   CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam; the exchange swaps
@@ -110,18 +120,21 @@ typedef void (*cc_ladder_trace_fn)(void* user, int phase, int block, int end, hi
 /* Optional controls; a zero-initialised struct (or NULL) selects everything automatically. */
 typedef struct {
   int    a_block;          /* virtuals per integral block; 0 = largest that fits hbm_budget */
-  int    split_slices;     /* SPLIT_BF16 digit slices S in [2, 4]; 0 = 4 */
+  int    split_slices;     /* SPLIT_BF16 slices S in [2, 4]; 0 = 4 (2 = the hi/lo split) */
   int    k_chunk;          /* FP32 drain interval along the contracted index (multiple of 64); 0 = 512 */
   int    split_depth;      /* SPLIT_BF16 slice products (p,q), 1-based, kept when p+q <= S+depth,
                               depth in [1, 2]; 0 = 2 for S = 4 (13 products), 1 otherwise
-                              (S = 2: 3 products, S = 3: 6) */
+                              (S = 2: hi*hi, hi*lo, lo*hi; S = 3: 6 products) */
   size_t hbm_budget;       /* bytes the library may use for scratch; 0 = half the free device
                               memory, at most 64 GiB */
-  void*  workspace;        /* caller scratch (device, 256-byte aligned) or NULL */
+  void*  workspace;        /* caller scratch (device, 256-byte aligned) or NULL; the part the
+                              plan uses, [workspace, workspace + planned bytes), must not
+                              overlap any tensor argument (CC_LADDER_EINVAL) */
   size_t workspace_bytes;  /* its size; the plan must fit in it */
   cc_ladder_trace_fn trace;  /* optional per-phase hook, NULL = none */
   void*  trace_user;       /* passed back to `trace` */
-  unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE, or 0 */
+  unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE |
+                              CC_LADDER_CHECK_SYMMETRY, or 0 */
   int    reserved;         /* must be 0 */
 } cc_ladder_opts;
 
@@ -149,10 +162,13 @@ int cc_ladder_backward(int o, int v, int P,
                        int precision, hipStream_t stream, const cc_ladder_opts* opts);
 
 /*
- * float64 reductions over n = o*o*v*v entries, as used for the energy-like
- * functional and norms of the vector function:
+ * float64 reductions over n = o*o*v*v entries: the energy-like functional and
+ * the residual norm that a CC iteration evaluates once per vector function (the
+ * per-iteration quantities of the paper's timings, Table tbl:dye):
  *   out_dev[0] = sum x*y,  out_dev[1] = sum y*y        (out_dev: device, 2 doubles)
- * Deterministic for a given device and size.
+ * x, y: device [o][o][v][v] float64.  out_dev must not overlap x or y
+ * (CC_LADDER_EINVAL).  Deterministic for a given device and size.  Scratch for
+ * the partial sums (16 KB) is allocated and freed stream-ordered.
  */
 int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out_dev,
                      hipStream_t stream);
@@ -161,8 +177,13 @@ int cc_ladder_reduce(int o, int v, const double* x, const double* y, double* out
  * Host-only planner query (needs no device): the scratch bytes and the
  * integral block (virtuals per block) that cc_ladder_residual (backward = 0)
  * or cc_ladder_backward (backward = 1) would use under `hbm_budget` bytes
- * (0 = no limit, i.e. the whole virtual range in one block).  `opts` may be
- * NULL; its a_block and split_slices are honoured, its budget fields are not.
+ * (0 = no limit, i.e. the whole virtual range in one block).  This is the
+ * paper's memory-fit rule for its batches (Sec. "CuPy and batch-wise
+ * computations": element counts times element sizes, blocks shrunk until they
+ * fit), applied to device-resident data.  `opts` may be NULL; every field that
+ * shapes the plan is honoured (a_block, split_slices, split_depth, k_chunk,
+ * flags), its budget and workspace fields are not.  *bytes and *a_block are
+ * written on success only.
  */
 int cc_ladder_workspace_query(int o, int v, int P, int precision, int backward,
                               size_t hbm_budget, const cc_ladder_opts* opts,

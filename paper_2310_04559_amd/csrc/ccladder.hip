@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -60,11 +61,6 @@ int check_device() {
     g_dev_ok[dev] = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
   }
   return g_dev_ok[dev] == 1 ? CC_LADDER_OK : CC_LADDER_ENODEV;
-}
-
-bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
-  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-  return x < y + bbytes && y < x + abytes;
 }
 
 // ---------------------------------------------------------------------------
@@ -532,19 +528,88 @@ int take_scratch(const Plan& plan, hipStream_t stream, const cc_ladder_opts* opt
   return CC_LADDER_OK;
 }
 
+// Planning, device check and scratch of a ladder call, in this order: with a
+// caller workspace the plan (sized to it) and the workspace's overlap with the
+// call's arrays are settled on the host before any device call; otherwise the
+// budget (the caller's, or half the free device memory) needs the device first.
 int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream_t stream,
-                     const cc_ladder_opts* opts, Plan* plan, Scratch* ws) {
-  size_t budget;
-  if (opts && opts->workspace)
-    budget = opts->workspace_bytes;
-  else if (opts && opts->hbm_budget)
-    budget = opts->hbm_budget;
-  else
-    budget = default_budget();
-  if (!budget) return CC_LADDER_EHIP;
-  const int rc = make_plan(o, v, P, precision, backward, budget, opts, plan);
-  if (rc) return rc;
+                     const cc_ladder_opts* opts, const Operand* ops, int nops, Plan* plan,
+                     Scratch* ws) {
+  int rc;
+  if (opts && opts->workspace) {
+    rc = make_plan(o, v, P, precision, backward, opts->workspace_bytes, opts, plan);
+    if (rc) return rc;
+    rc = check_workspace(opts, plan->bytes, ops, nops);
+    if (rc) return rc;
+    rc = check_device();
+    if (rc) return rc;
+  } else {
+    rc = check_device();
+    if (rc) return rc;
+    const size_t budget = (opts && opts->hbm_budget) ? opts->hbm_budget : default_budget();
+    if (!budget) return CC_LADDER_EHIP;
+    rc = make_plan(o, v, P, precision, backward, budget, opts, plan);
+    if (rc) return rc;
+  }
   return take_scratch(*plan, stream, opts, ws);
+}
+
+// Pair-symmetry check: out[0] = max |x[i][j][c][d] - x[j][i][d][c]|, out[1] =
+// max |x| over the o^2 v^2 entries, as the bit patterns of non-negative doubles
+// (ordered like the values, so an integer maximum combines them).  out must be
+// zero on entry.
+__global__ __launch_bounds__(256) void pair_asym_kernel(const double* __restrict__ x, int o, int v,
+                                                        unsigned long long* out) {
+  const long long v2 = (long long)v * v;
+  const long long n = (long long)o * o * v2;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  double dmax = 0.0, xmax = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const long long m = e / v2, cd = e - m * v2;
+    const long long i = m / o, j = m - i * o;
+    const long long c = cd / v, d = cd - c * v;
+    const double a = x[e];
+    const double b = x[(j * o + i) * v2 + d * v + c];
+    dmax = fmax(dmax, fabs(a - b));
+    xmax = fmax(xmax, fabs(a));
+  }
+  __shared__ double s1[256], s2[256];
+  s1[threadIdx.x] = dmax;
+  s2[threadIdx.x] = xmax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + w]);
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(s1[0])));
+    atomicMax(out + 1, static_cast<unsigned long long>(__double_as_longlong(s2[0])));
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  if (static_cast<int>(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
+// CC_LADDER_CHECK_SYMMETRY: returns CC_LADDER_EINVAL when some pair of x differs
+// by more than 2^-40 max|x| (synchronises the stream to read the result).
+int check_pair_symmetric(const double* x, int o, int v, unsigned long long* buf, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, buf, 2);
+  const long long n = (long long)o * o * v * v;
+  const long long blocks = std::min<long long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(pair_asym_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x, o,
+                     v, buf);
+  if (hipGetLastError() != hipSuccess) return CC_LADDER_EHIP;
+  unsigned long long h[2] = {0, 0};
+  CCL_HIP(hipMemcpyAsync(h, buf, sizeof(h), hipMemcpyDeviceToHost, s));
+  CCL_HIP(hipStreamSynchronize(s));
+  double d, m;
+  std::memcpy(&d, &h[0], sizeof(double));
+  std::memcpy(&m, &h[1], sizeof(double));
+  return d <= std::ldexp(m, -40) ? CC_LADDER_OK : CC_LADDER_EINVAL;
 }
 
 // ---------------------------------------------------------------------------
@@ -755,20 +820,24 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
   if (overlaps(Z, nz, t, nt) || overlaps(Z, nz, Lov, nov) || overlaps(Z, nz, Lrow, nrow))
     return CC_LADDER_EINVAL;
   if (precision == CC_LADDER_SPLIT_BF16 || (opts && opts->flags)) return CC_LADDER_EUNSUPPORTED;
-  rc = check_device();
-  if (rc) return rc;
   Plan pl;
   Scratch ws;
-  size_t budget;
-  if (opts && opts->workspace)
-    budget = opts->workspace_bytes;
-  else if (opts && opts->hbm_budget)
-    budget = opts->hbm_budget;
-  else
-    budget = default_budget();
-  if (!budget) return CC_LADDER_EHIP;
-  rc = make_plan_intermediate(which, o, v, P, precision, budget, opts, &pl);
-  if (rc) return rc;
+  if (opts && opts->workspace) {
+    rc = make_plan_intermediate(which, o, v, P, precision, opts->workspace_bytes, opts, &pl);
+    if (rc) return rc;
+    const Operand ops[4] = {{Lrow, nrow}, {Lov, nov}, {t, nt}, {Z, nz}};
+    rc = check_workspace(opts, pl.bytes, ops, 4);
+    if (rc) return rc;
+    rc = check_device();
+    if (rc) return rc;
+  } else {
+    rc = check_device();
+    if (rc) return rc;
+    const size_t budget = (opts && opts->hbm_budget) ? opts->hbm_budget : default_budget();
+    if (!budget) return CC_LADDER_EHIP;
+    rc = make_plan_intermediate(which, o, v, P, precision, budget, opts, &pl);
+    if (rc) return rc;
+  }
   rc = take_scratch(pl, stream, opts, &ws);
   if (rc) return rc;
   char* base = ws.base;
@@ -822,21 +891,19 @@ using namespace ccl;
 extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const double* t,
                                   double* R, int precision, hipStream_t stream,
                                   const cc_ladder_opts* opts) {
-  int rc = check_dims(o, v, P);
-  if (rc) return rc;
-  rc = check_precision_opts(precision, opts);
-  if (rc) return rc;
-  if (!L || !t || !R) return CC_LADDER_EINVAL;
-  const size_t nt = (size_t)o * o * v * v * sizeof(double);
-  const size_t nL = (size_t)P * v * v * sizeof(double);
-  if (overlaps(R, nt, t, nt) || overlaps(R, nt, L, nL)) return CC_LADDER_EINVAL;
-  rc = check_device();
+  Operand ops[3];
+  int rc = check_residual_args(o, v, P, L, t, R, precision, opts, ops);
   if (rc) return rc;
   Plan pl;
   Scratch ws;
-  rc = plan_and_scratch(o, v, P, precision, 0, stream, opts, &pl, &ws);
+  rc = plan_and_scratch(o, v, P, precision, 0, stream, opts, ops, 3, &pl, &ws);
   if (rc) return rc;
   char* base = ws.base;
+  if (pl.check_sym) {
+    rc = check_pair_symmetric(t, o, v, reinterpret_cast<unsigned long long*>(base + pl.off_check),
+                              stream);
+    if (rc) return rc;
+  }
   const Tracer tr(opts, stream);
   if (pl.exchange && precision != CC_LADDER_FP32) {
     // the exchange partner is the ladder of the swapped amplitudes
@@ -873,25 +940,21 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
 extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const double* t,
                                   const double* lam, double* dL, double* dt, int precision,
                                   hipStream_t stream, const cc_ladder_opts* opts) {
-  int rc = check_dims(o, v, P);
+  Operand ops[5];
+  int rc = check_backward_args(o, v, P, L, t, lam, dL, dt, precision, opts, ops);
   if (rc) return rc;
-  rc = check_precision_opts(precision, opts);
-  if (rc) return rc;
-  if (!L || !t || !lam || !dL || !dt) return CC_LADDER_EINVAL;
-  const size_t nt = (size_t)o * o * v * v * sizeof(double);
-  const size_t nL = (size_t)P * v * v * sizeof(double);
-  if (overlaps(dt, nt, t, nt) || overlaps(dt, nt, lam, nt) || overlaps(dt, nt, L, nL) ||
-      overlaps(dL, nL, L, nL) || overlaps(dL, nL, t, nt) || overlaps(dL, nL, lam, nt) ||
-      overlaps(dL, nL, dt, nt))
-    return CC_LADDER_EINVAL;
   if (precision == CC_LADDER_SPLIT_BF16) return CC_LADDER_EUNSUPPORTED;
-  rc = check_device();
-  if (rc) return rc;
   Plan pl;
   Scratch ws;
-  rc = plan_and_scratch(o, v, P, precision, 1, stream, opts, &pl, &ws);
+  rc = plan_and_scratch(o, v, P, precision, 1, stream, opts, ops, 5, &pl, &ws);
   if (rc) return rc;
   char* base = ws.base;
+  if (pl.check_sym) {
+    unsigned long long* buf = reinterpret_cast<unsigned long long*>(base + pl.off_check);
+    rc = check_pair_symmetric(t, o, v, buf, stream);
+    if (!rc) rc = check_pair_symmetric(lam, o, v, buf, stream);
+    if (rc) return rc;
+  }
   const Tracer tr(opts, stream);
   // exchange: gradients of the ladder at the swapped amplitudes; dt is
   // accumulated in swapped order in scratch and swapped back at the end

@@ -35,13 +35,65 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
     return CC_LADDER_EINVAL;
   if (!opts) return CC_LADDER_OK;
   if (opts->a_block < 0 || opts->split_depth < 0 || opts->split_depth > 2) return CC_LADDER_EINVAL;
-  if ((opts->flags & ~(CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE)) != 0 || opts->reserved != 0)
+  if ((opts->flags & ~(CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE | CC_LADDER_CHECK_SYMMETRY)) != 0 ||
+      opts->reserved != 0)
     return CC_LADDER_EINVAL;
   if (opts->split_slices != 0 && (opts->split_slices < 2 || opts->split_slices > 4))
     return CC_LADDER_EINVAL;
   if (opts->k_chunk < 0 || opts->k_chunk % 64 != 0) return CC_LADDER_EINVAL;
   if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
     return CC_LADDER_EINVAL;
+  return CC_LADDER_OK;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!abytes || !bbytes) return false;
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bbytes && y < x + abytes;
+}
+
+int check_residual_args(int o, int v, int P, const double* L, const double* t, const double* R,
+                        int precision, const cc_ladder_opts* opts, Operand ops[3]) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  if (!L || !t || !R) return CC_LADDER_EINVAL;
+  const size_t nt = static_cast<size_t>(o) * o * v * v * sizeof(double);
+  const size_t nL = static_cast<size_t>(P) * v * v * sizeof(double);
+  ops[0] = {L, nL};
+  ops[1] = {t, nt};
+  ops[2] = {R, nt};
+  if (overlaps(R, nt, t, nt) || overlaps(R, nt, L, nL)) return CC_LADDER_EINVAL;
+  return CC_LADDER_OK;
+}
+
+int check_backward_args(int o, int v, int P, const double* L, const double* t, const double* lam,
+                        const double* dL, const double* dt, int precision,
+                        const cc_ladder_opts* opts, Operand ops[5]) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  if (!L || !t || !lam || !dL || !dt) return CC_LADDER_EINVAL;
+  const size_t nt = static_cast<size_t>(o) * o * v * v * sizeof(double);
+  const size_t nL = static_cast<size_t>(P) * v * v * sizeof(double);
+  ops[0] = {L, nL};
+  ops[1] = {t, nt};
+  ops[2] = {lam, nt};
+  ops[3] = {dL, nL};
+  ops[4] = {dt, nt};
+  if (overlaps(dt, nt, t, nt) || overlaps(dt, nt, lam, nt) || overlaps(dt, nt, L, nL) ||
+      overlaps(dL, nL, L, nL) || overlaps(dL, nL, t, nt) || overlaps(dL, nL, lam, nt) ||
+      overlaps(dL, nL, dt, nt))
+    return CC_LADDER_EINVAL;
+  return CC_LADDER_OK;
+}
+
+int check_workspace(const cc_ladder_opts* opts, size_t plan_bytes, const Operand* ops, int n) {
+  if (!opts || !opts->workspace) return CC_LADDER_OK;
+  for (int i = 0; i < n; ++i)
+    if (overlaps(opts->workspace, plan_bytes, ops[i].p, ops[i].bytes)) return CC_LADDER_EINVAL;
   return CC_LADDER_OK;
 }
 
@@ -113,6 +165,11 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   if (p.pairsym_adj) {
     // the adjoint's dt accumulates B[(ij)][(cd)] over packed rows; dt += B + mirror(B)
     p.off_B = take(&cur, o2 * v2 * sizeof(double));
+  }
+  if ((p.pairsym || p.pairsym_adj) && (flags & CC_LADDER_CHECK_SYMMETRY)) {
+    // two maxima of the pair-symmetry check (bit patterns of non-negative doubles)
+    p.check_sym = 1;
+    p.off_check = take(&cur, 2 * sizeof(unsigned long long));
   }
   if (p.pairsym || p.pairsym_adj) {
     // tile-row offsets of the packed build's compact grid (128-row tiles; 64 rows

@@ -30,6 +30,8 @@ struct Plan {
                         // one dL term added twice
   size_t off_lamP = 0;  // pair-symmetric adjoint: lam at the block's packed pairs, weighted
   size_t off_B = 0;     // pair-symmetric adjoint: float64 B[(ij)][(cd)], dt += B + mirror(B)
+  int check_sym = 0;    // verify the pair-symmetry assertion before any other work
+  size_t off_check = 0; // its result: max |x - pair transpose of x|, max |x| (as uint64 bits)
   int exchange = 0;     // exchange partner: amplitudes (and dt) with c,d swapped
   size_t off_tx = 0;    // exchange: t with its last two indices swapped (float64; not in FP32)
   size_t off_dtx = 0;   // exchange adjoint: dt of the swapped amplitudes (float64)
@@ -101,5 +103,30 @@ struct Tracer {
 // Argument checks shared by every entry point (dimensions, precision, options).
 int check_dims(int o, int v, int P);
 int check_precision_opts(int precision, const cc_ladder_opts* opts);
+
+// One array argument of a call: its first byte and its size in bytes.
+struct Operand {
+  const void* p;
+  size_t bytes;
+};
+
+// True when [a, a + abytes) and [b, b + bbytes) share a byte.
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
+
+// Host-only argument validation of the ladder entry points, in the order the
+// entry points apply it: dimensions, precision and options, null pointers, then
+// outputs overlapping inputs (or each other).  Returns 0 or CC_LADDER_EINVAL.
+// The array sizes these checks use are filled into ops[] (inputs then outputs:
+// forward L, t, R; adjoint L, t, lam, dL, dt) for the workspace check below.
+int check_residual_args(int o, int v, int P, const double* L, const double* t, const double* R,
+                        int precision, const cc_ladder_opts* opts, Operand ops[3]);
+int check_backward_args(int o, int v, int P, const double* L, const double* t, const double* lam,
+                        const double* dL, const double* dt, int precision,
+                        const cc_ladder_opts* opts, Operand ops[5]);
+
+// A caller workspace must not overlap any array of the call over the bytes the
+// plan uses: CC_LADDER_EINVAL when [workspace, workspace + plan_bytes) meets
+// ops[i] for some i < n, else 0 (also when there is no caller workspace).
+int check_workspace(const cc_ladder_opts* opts, size_t plan_bytes, const Operand* ops, int n);
 
 }  // namespace ccl

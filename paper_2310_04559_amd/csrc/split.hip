@@ -1,9 +1,9 @@
 // Split-bf16 form of the ladder forward.
 //
-// Every operand row (a row of the matrix along its contracted index) gets an
-// exponent e with max|x| < 2^e -- one per row for the integral build, one per
-// (row, chunk of 128 contracted indices) for the amplitude contraction -- and
-// each value is cut into S balanced base-256 digits:
+// Three or four slices: every operand row (a row of the matrix along its
+// contracted index) gets an exponent e with max|x| < 2^e -- one per row for the
+// integral build, one per (row, chunk of 128 contracted indices) for the
+// amplitude contraction -- and each value is cut into S balanced base-256 digits:
 //   x = 2^e * sum_{p=1..S} d_p 2^(-8p) + r,   d_1 in [-256, 256], d_p in [-128, 128] (p > 1),
 // |r| <= 2^(e - 8S - 1).  Digits are integers, exact in bf16.  A product of two
 // such matrices is, per K-chunk c,
@@ -17,6 +17,14 @@
 // error at the same digit count (1.0e-9 -> 5.0e-10 over whole rows at
 // o=20 v=180 P=600 in the exact NumPy model of the scheme); for the build,
 // whose rows (Cholesky vectors along x) are evenly scaled, they change nothing.
+//
+// Two slices are the per-element hi/lo split instead: hi = bf16(x) and
+// lo = bf16(x - hi), both rounded to nearest even, so each operand carries about
+// 16 significant bits of its own magnitude (no shared exponent).  The products
+// hi*hi, hi*lo and lo*hi (D = 1; D = 2 adds lo*lo) are summed in float32 over
+// each 128-index chunk (rounded, not exact) and drained to float64.  The same
+// kernels serve it with every exponent fixed at 8, which makes every scale 1.
+//
 // The two contractions then run as:
 //   build    V_A = L-slices x L-slices (K = x), float64 block, permuted store
 //   re-slice V_A rows (a,b) along (c,d)
@@ -57,6 +65,26 @@ __device__ __forceinline__ void digits(double y, __bf16 (&d)[S]) {
     d[p] = static_cast<__bf16>(static_cast<float>(static_cast<int>(q)) * scale);
   }
 }
+
+// Per-element split for two slices: x = hi + lo + r with hi = bf16(x),
+// lo = bf16(x - hi) (x - hi is exact in float64), |r| <= 2^-16 |x|.
+__device__ __forceinline__ void hi_lo(double x, __bf16 (&d)[2]) {
+  const __bf16 h = static_cast<__bf16>(x);  // round to nearest even
+  d[0] = h;
+  d[1] = static_cast<__bf16>(x - static_cast<double>(h));
+}
+
+// Cuts x (scaled by 2^-e in the digit forms) into the S slices of the form.
+template <int S>
+__device__ __forceinline__ void cut(double x, int e, __bf16 (&d)[S]) {
+  if constexpr (S == 2)
+    hi_lo(x, d);
+  else
+    digits<S>(ldexp(x, -e), d);
+}
+
+// The exponent every row gets in the hi/lo form: 2^(eA + eB - 16) = 1.
+constexpr int kHiLoExp = 8;
 
 // Digit buffers are [rows][k_pad / 32][S][32]: for each 32-deep K-step the S
 // slices of one row are adjacent, so the loads of a K-step read whole 128-byte
@@ -116,17 +144,20 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
         x[j] = (r < R && k < K) ? row[k] : 0.0;
       }
     }
-    double m = 0.0;
+    int e = kHiLoExp;
+    if constexpr (S != 2) {
+      double m = 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) m = fmax(m, fabs(x[j]));
+      for (int j = 0; j < 8; ++j) m = fmax(m, fabs(x[j]));
 #pragma unroll
-    for (int w = 8; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, 16));
-    int e = 0;
-    if (m > 0.0) (void)frexp(m, &e);  // max|x| < 2^e over the chunk
+      for (int w = 8; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, 16));
+      e = 0;
+      if (m > 0.0) (void)frexp(m, &e);  // max|x| < 2^e over the chunk
+    }
     if ((tid & 15) == 0 && cstart < Kp) ex[(cstart / kExpChunk) * (long long)ex_stride + r] = e;
     __bf16 d[8][S];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) digits<S>(ldexp(x[j], -e), d[j]);
+    for (int j = 0; j < 8; ++j) cut<S>(x[j], e, d[j]);
     // memory image of the wave's 16 K-steps: step lane/4, slice p, piece lane%4
 #pragma unroll
     for (int p = 0; p < S; ++p) {
@@ -166,20 +197,25 @@ __global__ __launch_bounds__(256) void rc_rowmax_kernel(const double* __restrict
 template <int S>
 __global__ __launch_bounds__(256) void slice_rc_kernel(const double* __restrict__ X, long long ld,
                                                        int R, int Rp, int K, int Kp,
-                                                       const int* __restrict__ ex,
+                                                       int* __restrict__ ex,
                                                        __bf16* __restrict__ out) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long total = (long long)Rp * (Kp / 8);
   if (idx >= total) return;
   const int r = static_cast<int>(idx % Rp);
   const int k0 = static_cast<int>(idx / Rp) * 8;
-  const int e = ex[r];
+  int e = kHiLoExp;
+  if constexpr (S == 2) {
+    if (k0 == 0) ex[r] = e;  // the hi/lo form needs no row maximum
+  } else {
+    e = ex[r];
+  }
   __bf16 d[8][S];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = k0 + j;
     const double x = (r < R && k < K) ? X[(long long)k * ld + r] : 0.0;
-    digits<S>(ldexp(x, -e), d[j]);
+    cut<S>(x, e, d[j]);
   }
 #pragma unroll
   for (int p = 0; p < S; ++p) {
@@ -412,10 +448,13 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          sa[i][r] = ldexp(1.0, g.ea[(long long)c * g.ea_stride + m0 + wm + 16 * i + 4 * (lane >> 4) + r]);
+          sa[i][r] = S == 2 ? 256.0  // hi/lo: every exponent is kHiLoExp
+                            : ldexp(1.0, g.ea[(long long)c * g.ea_stride + m0 + wm + 16 * i +
+                                               4 * (lane >> 4) + r]);
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        sb[j] = ldexp(1.0, g.eb[(long long)c * g.eb_stride + n0 + wn + 16 * j + (lane & 15)]);
+        sb[j] = S == 2 ? 256.0
+                       : ldexp(1.0, g.eb[(long long)c * g.eb_stride + n0 + wn + 16 * j + (lane & 15)]);
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -446,7 +485,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   for (int j = 0; j < NJ; ++j) {
     const int n = n0 + wn + 16 * j + (lane & 15);
     if (n >= g.N) continue;
-    const int en = CE ? 0 : g.eb[n];
+    const int en = CE ? 0 : (S == 2 ? kHiLoExp : g.eb[n]);
     long long ncol = n;
     int pa = 0, pb = 0;  // EPI_PACK: b - a0 and d; EPI_PAIR: a and b
     if (EPI == EPI_PERM) {
@@ -466,7 +505,8 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         if (m >= g.M) continue;
-        const double val = CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], g.ea[m] + en);
+        const double val =
+            CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], (S == 2 ? kHiLoExp : g.ea[m]) + en);
         double* C = static_cast<double*>(g.C);
         if (EPI == EPI_ACC) {
           C[(long long)m * g.ldc + n] += val;
@@ -506,9 +546,9 @@ __global__ void split_pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n,
 // Kernel shape per slice count.  S = 4: 128 x 128 tiles in two 64 KB stages,
 // 8 waves of 64 x 32 sub-tiles, anti-diagonals g >= 2 (scales <= 2^-16 of the
 // leading one) in one rounded float32 accumulator so that the sub-tile fits 256
-// registers; S = 2: 128 x 128 tiles in four 32 KB stages, every anti-diagonal
-// exact; S = 3: 64 x 128 tiles in three stages and 4 waves (its stage does not
-// split 8 ways) of 64 x 32 sub-tiles, exact.
+// registers; S = 2 (hi/lo): 128 x 128 tiles in four 32 KB stages, one float32
+// sum per anti-diagonal; S = 3: 64 x 128 tiles in three stages and 4 waves (its
+// stage does not split 8 ways) of 64 x 32 sub-tiles, exact.
 template <int S, int D>
 struct SplitShape {
   static constexpr int NG = S + D - 1;
@@ -557,8 +597,9 @@ int slice_kc(const double* X, long long ld, int R, int K, const SliceDims& d, __
 template <int S>
 int slice_rc(const double* X, long long ld, int R, int K, const SliceDims& d, __bf16* out, int* ex,
              hipStream_t s) {
-  hipLaunchKernelGGL(rc_rowmax_kernel, dim3((d.rows_pad + 255) / 256), dim3(256), 0, s, X, ld, R,
-                     d.rows_pad, K, ex);
+  if (S != 2)
+    hipLaunchKernelGGL(rc_rowmax_kernel, dim3((d.rows_pad + 255) / 256), dim3(256), 0, s, X, ld, R,
+                       d.rows_pad, K, ex);
   const long long total = (long long)d.rows_pad * (d.k_pad / 8);
   hipLaunchKernelGGL((slice_rc_kernel<S>), dim3(static_cast<unsigned>((total + 255) / 256)),
                      dim3(256), 0, s, X, ld, R, d.rows_pad, K, d.k_pad, ex, out);

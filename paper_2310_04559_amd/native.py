@@ -51,6 +51,7 @@ class CcLadderOpts(ctypes.Structure):
 
 CC_LADDER_PAIR_SYMMETRIC = 1
 CC_LADDER_EXCHANGE = 2
+CC_LADDER_CHECK_SYMMETRY = 4
 CC_INTERMEDIATE_IJKL = 0
 CC_INTERMEDIATE_IJBK = 1
 CC_HOLE_LADDER = 2
@@ -112,23 +113,49 @@ def strerror(code: int) -> str:
 def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
               workspace: Optional[torch.Tensor] = None, trace=None,
               split_depth: int = 0, pair_symmetric: bool = False,
-              exchange: bool = False) -> CcLadderOpts:
-    """``trace`` is a TRACE_FN (keep a reference to it while the options are in use)."""
+              exchange: bool = False, check_symmetry: bool = False) -> CcLadderOpts:
+    """``trace`` is a TRACE_FN.  The options keep references to the workspace
+    tensor and the trace callback, so neither is freed while they are in use."""
     o = CcLadderOpts()
     o.a_block = int(a_block)
     o.split_slices = int(split_slices)
     o.k_chunk = int(k_chunk)
     o.split_depth = int(split_depth)
-    o.flags = (CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0) | (
-        CC_LADDER_EXCHANGE if exchange else 0)
+    o.flags = ((CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0)
+               | (CC_LADDER_EXCHANGE if exchange else 0)
+               | (CC_LADDER_CHECK_SYMMETRY if check_symmetry else 0))
     o.reserved = 0
     o.hbm_budget = int(hbm_budget)
+    o._workspace_ref = None
+    o._trace_ref = None
     if workspace is not None:
+        if workspace.device.type != "cuda" or not workspace.is_contiguous():
+            raise TypeError("workspace must be a contiguous device tensor")
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
+        o._workspace_ref = workspace
     if trace is not None:
         o.trace = ctypes.cast(trace, ctypes.c_void_p)
         o._trace_ref = trace
+    return o
+
+
+def copy_opts(opts: CcLadderOpts, **changes) -> CcLadderOpts:
+    """A copy of ``opts`` (with its references) with fields replaced; passing
+    ``workspace=None`` drops the workspace and its reference."""
+    o = CcLadderOpts.from_buffer_copy(opts)
+    o._workspace_ref = getattr(opts, "_workspace_ref", None)
+    o._trace_ref = getattr(opts, "_trace_ref", None)
+    for k, val in changes.items():
+        if k == "workspace":
+            if val is None:
+                o.workspace, o.workspace_bytes, o._workspace_ref = None, 0, None
+            else:
+                o.workspace = val.data_ptr()
+                o.workspace_bytes = val.numel() * val.element_size()
+                o._workspace_ref = val
+        else:
+            setattr(o, k, val)
     return o
 
 

@@ -27,10 +27,14 @@ def rel_fro(x, ref):
 
 # Relative Frobenius tolerances of each arithmetic form against the float64 oracle.
 TOL = {0: 1e-12, 1: 1e-6, 2: 1e-9}
-# split-bf16 at S digit slices (default product sets: S = 2, 3 the triangle, S = 4
-# one more anti-diagonal).  Each operand keeps 8S bits below its row maximum;
-# 16 * 2^(-8S) bounds the relative error on unstructured inputs (four rounded
-# operands, rows whose maximum exceeds their rms several times).  The MP2-like
-# workloads are held to the precision form's 1e-9 target at S = 4.
+# split-bf16 at S slices, default product sets.  S = 3, 4: exponent-aligned
+# digits, each operand keeping 8S bits below its row (or chunk) maximum; on
+# unstructured N(0,1) inputs a row's maximum is about four times its rms, and
+# the representation errors of the four operands of the two products add, so
+# S = 4 is held to 2e-9 there and to the precision form's 1e-9 on the MP2-like
+# workloads; S = 3 to 16 * 2^-24.  S = 2: the per-element hi/lo split, each
+# operand within 2^-16 of itself plus the dropped lo*lo product and float32
+# sums: 16 * 2^-16 on unstructured inputs, 2e-5 on the workloads (about 6e-6
+# measured).  S = 2 cannot meet the 1e-9 target and is reported with its error.
 TOL_SPLIT = {2: 16 * 2.0 ** -16, 3: 16 * 2.0 ** -24, 4: 2e-9}
-TOL_SPLIT_WORKLOAD = {2: 16 * 2.0 ** -16, 3: 16 * 2.0 ** -24, 4: 1e-9}
+TOL_SPLIT_WORKLOAD = {2: 2e-5, 3: 16 * 2.0 ** -24, 4: 1e-9}

@@ -1,10 +1,17 @@
-"""NumPy model of the split-bf16 digit arithmetic (test-side reference for the
-scheme, not for the ladder): exponents per row (the integral build) or per
-(row, chunk of 128 contracted indices) (the amplitude contraction), balanced
+"""NumPy model of the split-bf16 arithmetic (test-side reference for the
+scheme, not for the ladder).
+
+Three or four slices: exponents per row (the integral build) or per (row,
+chunk of 128 contracted indices) (the amplitude contraction), balanced
 base-256 digits, slice products (p, q) kept when p + q <= S + D (1-based),
-exact integer sums per chunk.  Used to check that the GPU kernels implement
-exactly this scheme; the scheme's own error is measured against the float64
-oracle."""
+exact integer sums per chunk.
+
+Two slices: the per-element split hi = bf16(x), lo = bf16(x - hi), both
+rounded to nearest even, and the products hi*hi, hi*lo, lo*hi (D = 2 adds
+lo*lo), summed here in float64.
+
+Used to check that the GPU kernels implement exactly this scheme; the
+scheme's own error is measured against the float64 oracle."""
 import numpy as np
 
 
@@ -41,8 +48,26 @@ def digits(X, S, chunk=0):
     return D, e
 
 
+def bf16_rne(x):
+    """x rounded to the nearest bf16 value (8 significant bits, ties to even),
+    for finite values inside bf16's normal range."""
+    m, e = np.frexp(np.asarray(x, dtype=np.float64))   # x = m 2^e, 1/2 <= |m| < 1
+    return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+
+
+def hi_lo(X):
+    hi = bf16_rne(X)
+    return hi, bf16_rne(X - hi)
+
+
 def product(A, B, S, depth, chunk=0):
-    """C = A @ B.T through the digit scheme (integer digit sums are exact in float64)."""
+    """C = A @ B.T through the split scheme (integer digit sums are exact in
+    float64; the hi/lo products are exact in float64 and summed there)."""
+    if S == 2:
+        Ah, Al = hi_lo(A)
+        Bh, Bl = hi_lo(B)
+        C = Ah @ Bh.T + Ah @ Bl.T + Al @ Bh.T
+        return C + Al @ Bl.T if depth >= 2 else C
     Da, ea = digits(A, S, chunk)
     Db, eb = digits(B, S, chunk)
     C = np.zeros((A.shape[0], B.shape[0]))

@@ -229,7 +229,7 @@ def test_bad_options_rejected(native):
         with pytest.raises(native.LadderError) as e:
             native.cc_ladder_workspace_query(3, 8, 10, "fp32", opts=native.make_opts(**kw))
         assert e.value.code == native.CC_LADDER_EINVAL
-    for flags, reserved in ((4, 0), (1 << 31, 0), (0, 1)):
+    for flags, reserved in ((8, 0), (1 << 31, 0), (0, 1)):
         o = native.make_opts()
         o.flags, o.reserved = flags, reserved
         with pytest.raises(native.LadderError) as e:
@@ -276,3 +276,83 @@ def test_no_device_is_reported(native):
     assert lib.cc_intermediate_ijbk(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 1 << 30, 1, None,
                                     None) == native.CC_LADDER_ENODEV
     assert lib.cc_hole_ladder(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None, None) == native.CC_LADDER_ENODEV
+
+
+def test_symmetry_check_flag_plan(native):
+    # the check needs one 256-byte slot, and only with the pair-symmetric flag
+    for backward in (False, True):
+        base, _ = native.cc_ladder_workspace_query(
+            3, 20, 30, "fp64", backward=backward, opts=native.make_opts(pair_symmetric=True))
+        chk, _ = native.cc_ladder_workspace_query(
+            3, 20, 30, "fp64", backward=backward,
+            opts=native.make_opts(pair_symmetric=True, check_symmetry=True))
+        assert chk == base + 256
+        plain, _ = native.cc_ladder_workspace_query(3, 20, 30, "fp64", backward=backward)
+        alone, _ = native.cc_ladder_workspace_query(3, 20, 30, "fp64", backward=backward,
+                                                    opts=native.make_opts(check_symmetry=True))
+        assert alone == plain
+
+
+def _opts_at(native, addr, nbytes):
+    o = native.make_opts()
+    o.workspace, o.workspace_bytes = addr, nbytes
+    return o
+
+
+def test_workspace_overlapping_an_array_is_rejected_on_the_host(native):
+    # host-side: the plan (sized to the workspace) and the overlap of the bytes
+    # it uses with every array argument are checked before any device call
+    lib = native.load()
+    o, v, P = 2, 8, 4
+    planned, _ = native.cc_ladder_workspace_query(o, v, P, "fp64", hbm_budget=1 << 30)
+    nt, nL = o * o * v * v * 8, P * v * v * 8
+    L, t, R = 1 << 24, 1 << 26, 1 << 28
+    big = 1 << 30
+    ref = ctypes.byref
+    for ws in (L, t + 256, R + nt - 256, t - 256 * ((planned + 255) // 256) + 256):
+        opts = _opts_at(native, ws, big)
+        assert lib.cc_ladder_residual(o, v, P, L, t, R, 0, None, ref(opts)) == native.CC_LADDER_EINVAL, ws
+    # the adjoint: every one of its five arrays counts
+    lam, dL, dt = 1 << 29, 1 << 31, 1 << 32
+    planned_b, _ = native.cc_ladder_workspace_query(o, v, P, "fp64", backward=True,
+                                                    hbm_budget=1 << 30)
+    for ws in (L, t, lam + 512, dL, dt + nt - 256):
+        opts = _opts_at(native, ws, big)
+        assert lib.cc_ladder_backward(o, v, P, L, t, lam, dL, dt, 0, None,
+                                      ref(opts)) == native.CC_LADDER_EINVAL, ws
+    # an occupied-index term
+    Lov, X = 1 << 24, 1 << 28
+    opts = _opts_at(native, X, big)
+    assert lib.cc_intermediate_ijkl(o, v, P, Lov, t, X, 0, None, ref(opts)) == native.CC_LADDER_EINVAL
+
+
+def test_workspace_overlap_counts_only_the_planned_bytes(native):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = native.load()
+    o, v, P = 2, 8, 4
+    planned, _ = native.cc_ladder_workspace_query(o, v, P, "fp64", hbm_budget=1 << 30)
+    L, t, R = 1 << 24, 1 << 26, 1 << 28
+    # a workspace ending inside t, but whose planned part ends before t: accepted
+    # by the host checks, so the call proceeds to the device check
+    ws = t - ((planned + 255) // 256) * 256
+    opts = _opts_at(native, ws, (t - ws) + 4096)
+    rc = lib.cc_ladder_residual(o, v, P, L, t, R, 0, None, ctypes.byref(opts))
+    assert rc == native.CC_LADDER_ENODEV
+    # clear of every array: the device check is reached as well
+    opts = _opts_at(native, 1 << 34, 1 << 30)
+    assert lib.cc_ladder_residual(o, v, P, L, t, R, 0, None, ctypes.byref(opts)) == native.CC_LADDER_ENODEV
+
+
+def test_make_opts_keeps_its_tensors(native):
+    import torch
+
+    ws = torch.empty(512, dtype=torch.uint8)
+    with pytest.raises(TypeError):
+        native.make_opts(workspace=ws)  # host memory is not a device workspace
+    o = native.make_opts(pair_symmetric=True, check_symmetry=True)
+    assert o.flags == native.CC_LADDER_PAIR_SYMMETRIC | native.CC_LADDER_CHECK_SYMMETRY
+    c = native.copy_opts(o, a_block=3)
+    assert c.a_block == 3 and c.flags == o.flags and o.a_block == 0

@@ -208,3 +208,68 @@ def test_autograd_clears_pair_symmetry_for_the_backward(gpu_lib):
     dL_ref, dt_ref = oracle.ladder_backward(L, t, lam)
     assert rel_fro(host(gL), dL_ref) < 1e-12
     assert rel_fro(host(gt), dt_ref) < 1e-12
+
+
+def test_autograd_inline_workspace_is_kept_and_not_reused_by_the_backward(gpu_lib):
+    # a workspace made inline in the options call: the options keep it alive for
+    # the forward, and the backward plans and allocates its own scratch
+    announce("autograd-inline-workspace")
+    from paper_2310_04559_amd.ladder import ladder
+
+    o, v, P = 4, 18, 25
+    L, t, lam = random_general(o, v, P, 34)
+    nbytes, _ = gpu_lib.cc_ladder_workspace_query(o, v, P, 0)
+    Ld = dev(L).requires_grad_(True)
+    td = dev(t).requires_grad_(True)
+    opts = gpu_lib.make_opts(workspace=torch.empty(nbytes, dtype=torch.uint8, device="cuda"))
+    R = ladder(Ld, td, opts=opts)
+    # allocations after the forward may not land in the workspace
+    junk = [torch.full((nbytes // 8 + 1,), 7.0, dtype=torch.float64, device="cuda") for _ in range(3)]
+    gL, gt = torch.autograd.grad((R * dev(lam)).sum(), (Ld, td))
+    del junk
+    dL_ref, dt_ref = oracle.ladder_backward(L, t, lam)
+    assert rel_fro(host(R), oracle.ladder_forward(L, t)) < 1e-12
+    assert rel_fro(host(gL), dL_ref) < 1e-12
+    assert rel_fro(host(gt), dt_ref) < 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_symmetry_check_flag(gpu_lib, precision):
+    # with the check flag a false pair-symmetry assertion is an EINVAL that
+    # leaves the outputs untouched; a true one runs as without the check
+    announce("symmetry-check", precision)
+    o, v, P = 5, 23, 37
+    L, t, lam = random_general(o, v, P, 35)
+    ts, lams = _pair_symmetric(t), _pair_symmetric(lam)
+    R0 = np.random.default_rng(36).standard_normal(t.shape)
+    kw = dict(pair_symmetric=True, check_symmetry=True)
+    nudged = ts.copy()
+    nudged[0, 1, 2, 3] += 1e-9 * np.abs(ts).max()  # one entry off its mirror
+    for bad_t in (t, nudged):
+        R = dev(R0)
+        with pytest.raises(gpu_lib.LadderError) as e:
+            gpu_lib.cc_ladder_residual(dev(L), dev(bad_t), R, precision, opts=gpu_lib.make_opts(**kw))
+        assert e.value.code == gpu_lib.CC_LADDER_EINVAL
+        torch.cuda.synchronize()
+        assert np.array_equal(host(R), R0)
+    R = dev(R0)
+    gpu_lib.cc_ladder_residual(dev(L), dev(ts), R, precision, opts=gpu_lib.make_opts(**kw))
+    R1 = dev(R0)
+    gpu_lib.cc_ladder_residual(dev(L), dev(ts), R1, precision,
+                               opts=gpu_lib.make_opts(pair_symmetric=True))
+    torch.cuda.synchronize()
+    assert torch.equal(R, R1)
+    # the adjoint checks lam as well
+    dL, dt = dev(np.zeros_like(L)), dev(np.zeros_like(t))
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_backward(dev(L), dev(ts), dev(lam), dL, dt, precision,
+                                   opts=gpu_lib.make_opts(**kw))
+    assert e.value.code == gpu_lib.CC_LADDER_EINVAL
+    torch.cuda.synchronize()
+    assert float(torch.count_nonzero(dL)) == 0 and float(torch.count_nonzero(dt)) == 0
+    dL_ref, dt_ref = oracle.ladder_backward(L, ts, lams)
+    gpu_lib.cc_ladder_backward(dev(L), dev(ts), dev(lams), dL, dt, precision,
+                               opts=gpu_lib.make_opts(**kw))
+    torch.cuda.synchronize()
+    assert rel_fro(host(dL), dL_ref) < TOL_BWD[precision]
+    assert rel_fro(host(dt), dt_ref) < TOL_BWD[precision]
