@@ -888,17 +888,14 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
 
 using namespace ccl;
 
-extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const double* t,
-                                  double* R, int precision, hipStream_t stream,
-                                  const cc_ladder_opts* opts) {
-  Operand ops[3];
-  int rc = check_residual_args(o, v, P, L, t, R, precision, opts, ops);
-  if (rc) return rc;
-  Plan pl;
-  Scratch ws;
-  rc = plan_and_scratch(o, v, P, precision, 0, stream, opts, ops, 3, &pl, &ws);
-  if (rc) return rc;
-  char* base = ws.base;
+namespace ccl {
+namespace {
+
+// The forward once its plan and scratch (`base`) are settled.
+int residual_body(const Plan& pl, const double* L, const double* t, double* R, int precision,
+                  char* base, const cc_ladder_opts* opts, hipStream_t stream) {
+  const int o = pl.o, v = pl.v, P = pl.P;
+  int rc;
   if (pl.check_sym) {
     rc = check_pair_symmetric(t, o, v, reinterpret_cast<unsigned long long*>(base + pl.off_check),
                               stream);
@@ -935,6 +932,31 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
     default:
       return CC_LADDER_EINVAL;
   }
+}
+
+}  // namespace
+
+int ladder_forward_planned(const Plan& pl, const double* L, const double* t, double* R,
+                           int precision, char* base, const cc_ladder_opts* opts,
+                           hipStream_t stream) {
+  return residual_body(pl, L, t, R, precision, base, opts, stream);
+}
+
+int device_ok() { return check_device(); }
+
+}  // namespace ccl
+
+extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const double* t,
+                                  double* R, int precision, hipStream_t stream,
+                                  const cc_ladder_opts* opts) {
+  Operand ops[3];
+  int rc = check_residual_args(o, v, P, L, t, R, precision, opts, ops);
+  if (rc) return rc;
+  Plan pl;
+  Scratch ws;
+  rc = plan_and_scratch(o, v, P, precision, 0, stream, opts, ops, 3, &pl, &ws);
+  if (rc) return rc;
+  return residual_body(pl, L, t, R, precision, ws.base, opts, stream);
 }
 
 extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const double* t,

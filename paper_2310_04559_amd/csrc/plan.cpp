@@ -26,6 +26,14 @@ int check_dims(int o, int v, int P) {
   if (o <= 0 || v <= 0 || P <= 0) return CC_LADDER_EINVAL;
   // o^2 and v^2 are GEMM extents held in 32-bit ints.
   if (o > 46340 || v > 46340 || P > (1 << 24)) return CC_LADDER_EINVAL;
+  // element counts of the arrays (o^2 v^2, P v^2, P o v) stay far inside size_t
+  // byte counts: at most 2^52 elements each
+  const unsigned long long o2 = static_cast<unsigned long long>(o) * o;
+  const unsigned long long v2 = static_cast<unsigned long long>(v) * v;
+  constexpr unsigned long long kMaxElems = 1ull << 52;
+  if (o2 * v2 > kMaxElems || static_cast<unsigned long long>(P) * v2 > kMaxElems ||
+      static_cast<unsigned long long>(P) * o * v > kMaxElems)
+    return CC_LADDER_EINVAL;
   return CC_LADDER_OK;
 }
 

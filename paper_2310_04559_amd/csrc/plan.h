@@ -129,4 +129,14 @@ int check_backward_args(int o, int v, int P, const double* L, const double* t, c
 // ops[i] for some i < n, else 0 (also when there is no caller workspace).
 int check_workspace(const cc_ladder_opts* opts, size_t plan_bytes, const Operand* ops, int n);
 
+// The ladder forward once its plan is made and its scratch (`base`, at least
+// pl.bytes, 256-byte aligned) is settled: the optional pair-symmetry check,
+// operand preparation and the block loop, enqueued on `stream`.
+int ladder_forward_planned(const Plan& pl, const double* L, const double* t, double* R,
+                           int precision, char* base, const cc_ladder_opts* opts,
+                           hipStream_t stream);
+
+// CC_LADDER_OK when the current device is a gfx950, else CC_LADDER_ENODEV.
+int device_ok();
+
 }  // namespace ccl
