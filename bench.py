@@ -40,22 +40,28 @@ METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 
 # workload's amplitudes are pair-symmetric (t[i,j,c,d] = t[j,i,d,c]); the
 # *_exchange forms evaluate the exchange partner sum_cd (ad|bc) t[i,j,c,d]
 # (eq. vfunction2) with the same nominal flops.
+# The *_pm forms contract the symmetric and antisymmetric combinations t+- with
+# V+- = (ac|bd) +- (ad|bc) over i <= j, a <= b, c <= d (pair-symmetric amplitudes).
 FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16": ("split_bf16", 4, False, False),
          "split_bf16_s2": ("split_bf16", 2, False, False),
          "split_bf16_s3": ("split_bf16", 3, False, False),
          "fp64_pairsym": ("fp64", 0, True, False), "fp32_pairsym": ("fp32", 0, True, False),
          "split_bf16_pairsym": ("split_bf16", 4, True, False),
+         "fp64_pm": ("fp64", 0, "pm", False), "fp32_pm": ("fp32", 0, "pm", False),
          "fp64_exchange": ("fp64", 0, False, True), "fp32_exchange": ("fp32", 0, False, True),
-         "split_bf16_exchange": ("split_bf16", 4, False, True)}
-_PEAK = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}  # dense MFMA, TFLOP/s
-_DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16"}
+         "split_bf16_exchange": ("split_bf16", 4, False, True),
+         "split_int8": ("split_int8", 5, False, False),
+         "split_int8_pairsym": ("split_int8", 5, True, False)}
+_PEAK = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0,
+         "split_int8": 5000.0}  # dense MFMA, TFLOP/s (int8: TOP/s)
+_DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split_int8": "i8"}
 # Target relative Frobenius errors against the float64 oracle per arithmetic
 # (every split form is held to the precision form's 1e-9), and the bound each
 # slice count can reach by construction (S = 2: the per-element hi/lo split,
 # about 16 significant bits per operand; S = 3: 24 bits; S = 4: 33 bits).
-_TARGET = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9}
-_SPLIT_BOUND = {2: 2e-5, 3: 16 * 2.0 ** -24, 4: 1e-9}
+_TARGET = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-9, "split_int8": 1e-9}
+_SPLIT_BOUND = {2: 2e-5, 3: 16 * 2.0 ** -24, 4: 1e-9, 5: 1e-9}
 PEAK_TFLOPS = {f: _PEAK[p[0]] for f, p in FORMS.items()}
 DTYPE = {f: _DTYPE[p[0]] for f, p in FORMS.items()}
 TOL = {f: _TARGET[p[0]] for f, p in FORMS.items()}
@@ -64,17 +70,37 @@ DESIGN_BOUND = {f: (_SPLIT_BOUND[p[1]] if p[1] else _TARGET[p[0]]) for f, p in F
 
 def mfma_products(form):
     """Slice products per nominal product (executed MFMA work multiplier): the
-    S(S+1)/2 triangle (hi*hi, hi*lo, lo*hi for S = 2), plus S-1 for the
-    4-slice form's extra anti-diagonal."""
+    S(S+1)/2 triangle (hi*hi, hi*lo, lo*hi for S = 2), plus S-1 for the bf16
+    4-slice form's extra anti-diagonal; the int8 form keeps the triangle."""
     s = FORMS[form][1]
     if not s:
         return 1
+    if FORMS[form][0] == "split_int8":
+        return s * (s + 1) // 2
     return s * (s + 1) // 2 + (s - 1 if s == 4 else 0)
 
 
-def executed_fraction(form, v):
-    """Share of the nominal flops a form executes: (v+1)/(2v) with packed rows."""
-    return (v + 1) / (2.0 * v) if FORMS[form][2] else 1.0
+def executed_flops(form, o, v, P):
+    """(build, contraction) flops a form executes per forward: 2 P v^4 and
+    2 o^2 v^4 in general; packed rows a <= b halve both (the build's (v+1)/(2v));
+    the +- combinations contract o(o+1)/2 rows with the v(v+1)/2 pairs c <= d
+    and o(o-1)/2 rows with the v(v-1)/2 pairs c < d."""
+    v4 = float(v) ** 4
+    sym = FORMS[form][2]
+    if not sym:
+        return 2.0 * P * v4, 2.0 * o * o * v4
+    npk = v * (v + 1) / 2.0
+    build = 2.0 * P * v * v * npk
+    if sym == "pm":
+        nm = v * (v - 1) / 2.0
+        return build, 2.0 * (o * (o + 1) / 2.0 * npk * npk + o * (o - 1) / 2.0 * nm * nm)
+    return build, 2.0 * o * o * v * v * npk
+
+
+def executed_fraction(form, v, o=1, P=1):
+    """Share of the nominal flops a form executes per forward."""
+    b, c = executed_flops(form, o, v, P)
+    return (b + c) / (2.0 * (P + o * o) * float(v) ** 4)
 KERNEL_SRC = [os.path.join(ROOT, "paper_2310_04559_amd", "csrc", f)
               for f in ("gemm.hpp", "gemm_direct.hpp", "ccladder.hip", "split.hip", "split.hpp",
                         "plan.cpp", "plan.h")]
@@ -179,14 +205,16 @@ def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
 
     prec = native.PRECISIONS[FORMS[form][0]]
     slices, pairsym, exchange = FORMS[form][1:]
+    pm = pairsym == "pm"
     stream = torch.cuda.current_stream()
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     nbytes, n_a = native.cc_ladder_workspace_query(
         o, v, P, prec, hbm_budget=ws_bytes,
-        opts=native.make_opts(split_slices=slices, pair_symmetric=pairsym, exchange=exchange))
+        opts=native.make_opts(split_slices=slices, pair_symmetric=bool(pairsym), exchange=exchange,
+                              plus_minus=pm))
     timer = PhaseTimer(native, stream)
     opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices,
-                            pair_symmetric=pairsym, exchange=exchange)
+                            pair_symmetric=bool(pairsym), exchange=exchange, plus_minus=pm)
 
     def step():
         native.cc_ladder_residual(L, t, R, prec, opts=opts)
@@ -221,8 +249,9 @@ def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     native.cc_ladder_residual(L, t, R, native.PRECISIONS[FORMS[form][0]],
                               opts=native.make_opts(workspace=ws, split_slices=FORMS[form][1],
-                                                    pair_symmetric=FORMS[form][2],
-                                                    exchange=FORMS[form][3]))
+                                                    pair_symmetric=bool(FORMS[form][2]),
+                                                    exchange=FORMS[form][3],
+                                                    plus_minus=FORMS[form][2] == "pm"))
     torch.cuda.synchronize()
     got = R[:, :, idx_a, idx_b].permute(2, 0, 1).cpu().numpy()
     del R, ws
@@ -326,9 +355,14 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
     return res
 
 
-def bench_large(native):
-    """The large single-GPU workload (o=60, v=600, P=1800): float64 and split-bf16
-    forwards and the float32 adjoint, one call each, planner-chosen blocks."""
+def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
+    """The large single-GPU workload (o=60, v=600, P=1800) under two scratch
+    budgets, each a caller workspace allocated once: the default (half the free
+    memory, at most 64 GiB) and one sized to the device (the free memory left
+    with every array of the call resident, less 8 GiB).  Per budget and form: a
+    warm-up call, then one timed call (HIP events on the call's stream) with
+    per-phase times; the float32 adjoint is timed the same way.  Errors: the
+    forwards against the oracle on sampled (a,b) columns."""
     import numpy as np
     import torch
 
@@ -346,35 +380,74 @@ def bench_large(native):
     ia = torch.tensor([a for a, _ in pairs], device="cuda")
     ib = torch.tensor([b for _, b in pairs], device="cuda")
     fwd = 2.0 * (P + o * o) * float(v) ** 4
-    res = {"workload": f"o={o},v={v},P={P}", "nominal_tflop_forward": fwd / 1e12}
+    bwd = (6.0 * P + 4.0 * o * o) * float(v) ** 4
+    res = {"workload": f"o={o},v={v},P={P}", "nominal_tflop_forward": fwd / 1e12,
+           "nominal_tflop_adjoint": bwd / 1e12}
+    stream = torch.cuda.current_stream()
     R = torch.zeros_like(t)
-    for form in ("fp64", "split_bf16"):
-        prec, slices = native.PRECISIONS[FORMS[form][0]], FORMS[form][1]
-        R.zero_()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    # the adjoint's dL and dt are allocated later: keep their room out of the large budget
+    extra = 2 * t.numel() * 8 + L.numel() * 8
+    budgets = {"default": int(min(free // 2, 64 << 30)),
+               "device": int(free - extra - (8 << 30))}
+    res["device_total_bytes"] = int(total)
+
+    def timed(call, timer, after_warmup=None):
+        call()  # warm-up (also plans nothing new: the workspace is the caller's)
         torch.cuda.synchronize()
+        if after_warmup is not None:
+            after_warmup()
+        timer.reset()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        native.cc_ladder_residual(L, t, R, prec, opts=native.make_opts(split_slices=slices))
-        e1.record()
+        e0.record(stream)
+        call()
+        e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        got = R[:, :, ia, ib].permute(2, 0, 1).cpu().numpy()
-        res[form] = {"ms": ms, "tflops": fwd / (ms * 1e-3) / 1e12,
-                     "rel_err_vs_oracle_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
-        log(f"large {form}: {ms:.0f} ms {res[form]['tflops']:.1f} TFLOP/s")
+        return e0.elapsed_time(e1)
+
+    for bname, budget in budgets.items():
+        for form in forms:
+            prec, slices = native.PRECISIONS[FORMS[form][0]], FORMS[form][1]
+            nbytes, n_a = native.cc_ladder_workspace_query(
+                o, v, P, prec, hbm_budget=budget, opts=native.make_opts(split_slices=slices))
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            timer = PhaseTimer(native, stream)
+            opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices)
+            R.zero_()
+            got = []
+
+            def check():
+                # the warm-up call's R (one forward onto zeros), then zeros again
+                got.append(R[:, :, ia, ib].permute(2, 0, 1).cpu().numpy())
+                R.zero_()
+                torch.cuda.synchronize()
+
+            ms = timed(lambda: native.cc_ladder_residual(L, t, R, prec, opts=opts), timer, check)
+            got = got[0]
+            del ws
+            r = {"ms": ms, "tflops": fwd / (ms * 1e-3) / 1e12, "a_block": n_a,
+                 "workspace_bytes": nbytes,
+                 "rel_err_vs_oracle_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                 "phases_ms": {k: d["ms_total"] for k, d in timer.summary().items()}}
+            res[f"{form}_{bname}"] = r
+            log(f"large {form} budget {bname} ({budget / 2**30:.0f} GiB, a_block {n_a}): "
+                f"{ms:.0f} ms {r['tflops']:.1f} TFLOP/s phases {json.dumps(r['phases_ms'])}")
     del R
+    torch.cuda.empty_cache()
     dL = torch.zeros_like(L)
     dt = torch.zeros_like(t)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    native.cc_ladder_backward(L, t, lam, dL, dt, native.CC_LADDER_FP32)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    bwd = (6.0 * P + 4.0 * o * o) * float(v) ** 4
-    res["adjoint_fp32"] = {"ms": ms, "tflops": bwd / (ms * 1e-3) / 1e12}
-    log(f"large adjoint fp32: {ms:.0f} ms {res['adjoint_fp32']['tflops']:.1f} TFLOP/s")
+    nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, native.CC_LADDER_FP32, backward=True,
+                                                   hbm_budget=budgets["device"])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    timer = PhaseTimer(native, stream)
+    opts = native.make_opts(workspace=ws, trace=timer.fn)
+    ms = timed(lambda: native.cc_ladder_backward(L, t, lam, dL, dt, native.CC_LADDER_FP32,
+                                                 opts=opts), timer)
+    res["adjoint_fp32_device"] = {"ms": ms, "tflops": bwd / (ms * 1e-3) / 1e12, "a_block": n_a,
+                                  "phases_ms": {k: d["ms_total"] for k, d in timer.summary().items()}}
+    log(f"large adjoint fp32 (a_block {n_a}): {ms:.0f} ms "
+        f"{res['adjoint_fp32_device']['tflops']:.1f} TFLOP/s")
     return res
 
 
@@ -461,13 +534,18 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
-    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_bf16_s2,fp64_pairsym,"
-                                       "split_bf16_pairsym,fp64_exchange")
+    ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_int8,split_bf16_s2,fp64_pairsym,"
+                                       "fp64_pm,fp32_pm,split_bf16_pairsym,split_int8_pairsym,"
+                                       "fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-intermediates", action="store_true")
     ap.add_argument("--large", action="store_true",
-                    help="also run the o=60, v=600, P=1800 workload (about two minutes)")
+                    help="also run the o=60, v=600, P=1800 workload (about five minutes)")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the o=60, v=600, P=1800 workload and print its JSON")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="run only the adjoint on the o=30, v=300, P=900 workload and print its JSON")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "reference for HBM byte counters)")
@@ -501,6 +579,12 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
         del src, dst
+    if args.only_large:
+        print(json.dumps({"large": bench_large(native)}), flush=True)
+        return
+    if args.only_adjoint:
+        print(json.dumps({"adjoint": bench_adjoint(native, max(1, min(args.steps, 2)))}), flush=True)
+        return
     o, v, P = CONFIGS["o40_v360_P1200"]
     t0 = time.perf_counter()
     inp = make_inputs(o, v, P, seed_for("o40_v360_P1200"), device="cuda")
@@ -531,7 +615,7 @@ def main():
             continue
         r = bench_form(native, form, L, t, R, out, ws_bytes, args.steps, args.warmup, o, v, P)
         r["tflops"] = flops / (r["ms_per_step"] * 1e-3) / 1e12
-        r["executed_tflops"] = r["tflops"] * executed_fraction(form, v)
+        r["executed_tflops"] = r["tflops"] * executed_fraction(form, v, o, P)
         r["rel_err_vs_oracle"] = err
         r["tolerance"] = TOL[form]
         r["within_tolerance"] = err < TOL[form]
@@ -541,11 +625,12 @@ def main():
         c = r["phases"].get("contract")
         if c:
             per_step = c["launches"] / args.steps  # launches of the kernel in one step
-            launch_flops = 2.0 * o * o * float(v) ** 4 * executed_fraction(form, v) / per_step
+            launch_flops = executed_flops(form, o, v, P)[1] / per_step
             # executed MFMA flops: the split forms run S(S+1)/2 slice products per product
             achieved = mfma_products(form) * launch_flops / (c["ms_avg"] * 1e-3) / 1e12
             r["roofline"] = {"kernel": "contract", "bound": "mfma", "achieved": achieved,
-                             "peak": PEAK_TFLOPS[form], "unit": "TFLOP/s",
+                             "peak": PEAK_TFLOPS[form],
+                             "unit": "TOP/s" if FORMS[form][0] == "split_int8" else "TFLOP/s",
                              "frac": achieved / PEAK_TFLOPS[form],
                              "traffic": read_traffic("contract", form),
                              "mfma_busy_counter": read_mfma_busy("contract", form),
@@ -553,7 +638,7 @@ def main():
                              "nominal_tflops": launch_flops / (c["ms_avg"] * 1e-3) / 1e12}
         b = r["phases"].get("build")
         if b:
-            bflops = 2.0 * P * float(v) ** 4 * executed_fraction(form, v) / (b["launches"] / args.steps)
+            bflops = executed_flops(form, o, v, P)[0] / (b["launches"] / args.steps)
             r["build_tflops"] = bflops / (b["ms_avg"] * 1e-3) / 1e12
         forms[form] = r
         log(f"{form}: {r['ms_per_step']:.1f} +- {r['ms_std']:.1f} (min {r['ms_min']:.1f}) ms/step "

@@ -63,15 +63,24 @@ extern "C" {
 typedef enum {
   CC_LADDER_FP64 = 0,        /* float64 MFMA throughout */
   CC_LADDER_FP32 = 1,        /* float32 operands and MFMA, float32 partial sums drained to float64 */
-  CC_LADDER_SPLIT_BF16 = 2   /* operands cut into bf16 slices, slice products on bf16 MFMA, summed
-                                in float32 over 128-index chunks and drained to float64.
+  CC_LADDER_SPLIT_BF16 = 2,  /* operands cut into bf16 slices, slice products on bf16 MFMA, summed
+                                in float32 over chunks of 256 indices (128 with 3 slices) and
+                                drained to float64.
                                 3 or 4 slices (default 4): digits on shared exponents (per row for
-                                the integral build, per row and 128-index chunk for the
-                                contraction), summed exactly, except that with 4 slices the
-                                products scaled by 2^-16 or less share one rounded sum.
+                                the integral build, per row and chunk for the contraction),
+                                summed exactly, except that with 4 slices the products scaled
+                                by 2^-16 or less share one rounded sum.
                                 2 slices: the per-element split hi = bf16(x), lo = bf16(x - hi)
                                 (round to nearest even) with the products hi*hi, hi*lo, lo*hi,
                                 about 16 significant bits per operand */
+  CC_LADDER_SPLIT_INT8 = 3   /* the digit scheme on the integer matrix cores: each operand row
+                                gets an exponent per chunk of 16384 contracted indices and
+                                every value S balanced int8 digits (default and most 5: 39 bits
+                                below the chunk's maximum; 4 also accepted), digit products on
+                                the int8 MFMA summed exactly in int32 over each chunk (products
+                                (p,q) with p+q <= S+depth, 1-based; depth 1, the triangle of
+                                S(S+1)/2 products, or 2 with 4 digits), drained to float64.
+                                Forward only. */
 } cc_ladder_precision;
 
 /* opts.flags bits */
@@ -100,6 +109,27 @@ typedef enum {
                                         outputs untouched, when some |x[i][j][c][d] - x[j][i][d][c]|
                                         exceeds 2^-40 max|x|.  Ignored without PAIR_SYMMETRIC. */
 
+#define CC_LADDER_PLUS_MINUS 8u      /* with PAIR_SYMMETRIC, FP64 and FP32 forward: contract the
+                                        symmetric and antisymmetric combinations of the integral
+                                        with its exchange partner (eqs. vfunction and vfunction2;
+                                        the permutational symmetry of the integrals, Sec. "The CC
+                                        ansatz") instead of packed rows.  With t+[ij][cd] = t[i][j][c][d] + t[i][j][d][c]
+                                        (c < d; t[i][j][c][c] for c = d), t-[ij][cd] = t[i][j][c][d]
+                                        - t[i][j][d][c] (c < d) and the integrals
+                                        V+-[ab][cd] = (ac|bd) +- (ad|bc), the sums
+                                        R+[ij][ab] = R[i][j][a][b] + R[i][j][b][a] =
+                                        sum_{c<=d} V+[ab][cd] t+[ij][cd] and R- (the same with -,
+                                        over c < d) are symmetric (antisymmetric) in a,b and in
+                                        i,j, so rows i <= j, columns a <= b and the contracted pairs
+                                        c <= d suffice: a quarter of the general contraction (half of
+                                        the packed-row form), the build as with PAIR_SYMMETRIC, plus
+                                        one pass forming V+- from each built block.  R[i][j][a][b]
+                                        = (R+ + R-)/2 and R[i][j][b][a] = (R+ - R-)/2, added with
+                                        their (j,i) mirrors.  Holds for any Cholesky vectors (it
+                                        uses (pq|rs) = (rs|pq) only).  EINVAL without
+                                        PAIR_SYMMETRIC; EUNSUPPORTED in the split forms; the
+                                        adjoint ignores it. */
+
 /* Kernel phases reported to an optional trace hook. */
 typedef enum {
   CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam; the exchange swaps
@@ -120,7 +150,8 @@ typedef void (*cc_ladder_trace_fn)(void* user, int phase, int block, int end, hi
 /* Optional controls; a zero-initialised struct (or NULL) selects everything automatically. */
 typedef struct {
   int    a_block;          /* virtuals per integral block; 0 = largest that fits hbm_budget */
-  int    split_slices;     /* SPLIT_BF16 slices S in [2, 4]; 0 = 4 (2 = the hi/lo split) */
+  int    split_slices;     /* SPLIT_BF16 slices S in [2, 4]; 0 = 4 (2 = the hi/lo split);
+                              SPLIT_INT8 digits in [4, 5]; 0 = 5 */
   int    k_chunk;          /* FP32 drain interval along the contracted index (multiple of 64); 0 = 512 */
   int    split_depth;      /* SPLIT_BF16 slice products (p,q), 1-based, kept when p+q <= S+depth,
                               depth in [1, 2]; 0 = 2 for S = 4 (13 products), 1 otherwise
@@ -134,7 +165,7 @@ typedef struct {
   cc_ladder_trace_fn trace;  /* optional per-phase hook, NULL = none */
   void*  trace_user;       /* passed back to `trace` */
   unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE |
-                              CC_LADDER_CHECK_SYMMETRY, or 0 */
+                              CC_LADDER_CHECK_SYMMETRY | CC_LADDER_PLUS_MINUS, or 0 */
   int    reserved;         /* must be 0 */
 } cc_ladder_opts;
 

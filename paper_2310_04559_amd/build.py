@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libccladder.so")
-SOURCES = ["ccladder.hip", "split.hip", "plan.cpp"]
+SOURCES = ["ccladder.hip", "split.hip", "split_i8.hip", "plan.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -84,7 +84,7 @@ bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   // tiles plus a 64-row launch over the remainder rows (plain or pair-mirrored
   // accumulation, whose rows can be offset)
   constexpr bool kTall = !Tr::kDrain;
-  constexpr bool kSplit = EPI == EPI_ACC || EPI == EPI_PAIR;
+  constexpr bool kSplit = EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PM;
   long long main_rows = g.M;
   const int bm = choose_kc_tiling(g.M, g.N, kTall, kSplit, &main_rows);
   auto launch = [&](auto kernel, const GemmArgs<typename Tr::T>& a, int rows_per_tile) {
@@ -104,7 +104,7 @@ bool launch_kc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
       g.M = static_cast<int>(main_rows);
       rest.M -= g.M;
       rest.A += main_rows * g.lda;
-      if constexpr (EPI == EPI_PAIR)
+      if constexpr (EPI == EPI_PAIR || EPI == EPI_PM)
         rest.m_off = g.m_off + g.M;  // the mirrored store needs the global (i,j) row
       else
         rest.C = static_cast<double*>(g.C) + main_rows * g.ldc;
@@ -187,10 +187,11 @@ template <class Tr, int LA, int LB, int EPI>
 int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
                 void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
                 hipStream_t stream, int o = 0, int a0 = 0, int* row_tiles = nullptr,
-                double alpha = 1.0) {
+                double alpha = 1.0, int pm = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
   GemmArgs<typename Tr::T> g;
   g.alpha = alpha;
+  g.pm = pm;
   g.A = A; g.lda = lda;
   g.B = B; g.ldb = ldb;
   g.C = C; g.ldc = ldc;
@@ -225,7 +226,8 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
                        g.tiles_n, v, kBM, kBN);
     grid = dim3(static_cast<unsigned>(needed));
   }
-  if constexpr (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR) && Tr::kDirectKC) {
+  if constexpr (LA == KC && LB == KC && (EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PM) &&
+                Tr::kDirectKC) {
     int rc = CC_LADDER_OK;
     if (launch_kc_direct<Tr, EPI>(g, stream, &rc)) return rc;
   }
@@ -431,6 +433,87 @@ int mirror_add(const double* B, double* dt, int o, int v, hipStream_t s) {
   const long long blocks = std::min<long long>(work, 16384);
   hipLaunchKernelGGL(mirror_add_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, B, dt,
                      o, v, tiles);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+// Symmetric and antisymmetric combinations of the v x v matrices X[r] of a set
+// of rows, over the pairs of their two indices:
+//   plus [rp][k(c,d)] = X[c][d] + X[d][c] for c < d,  wdiag * X[c][c] for c = d
+//   minus[rm][k'(c,d)] = sm * (X[c][d] - X[d][c])      for c < d
+// with k(c,d) = prefix_v(c) + d - c numbering the pairs c <= d and k'(c,d) =
+// prefix_{v-1}(c) + d - c - 1 the pairs c < d.  Rows:
+//   AMPS: the pairs (i, j), i <= j, of o; X = t[i][j]; rp = the pair index, rm
+//         its index among the pairs i < j (none for i = j)
+//   INTS: the packed integral rows (a, b), a <= b, a from a0; X = row r of the
+//         block; rp = r, rm = the local index among the pairs a < b (none for a = b)
+// One workgroup per (row, tile pair C <= D of 32 x 32 tiles): both tiles X[C][D]
+// and X[D][C] go through LDS, so reads and writes run along contiguous d.
+enum { PM_AMPS = 0, PM_INTS = 1 };
+
+template <int MODE, typename In, typename Out>
+__global__ __launch_bounds__(256) void pm_rows_kernel(const In* __restrict__ X, long long nrows,
+                                                      int n, int a0, int v, int tiles,
+                                                      Out* __restrict__ plus, long long ldp,
+                                                      Out* __restrict__ minus, long long ldm,
+                                                      double wdiag, double sm) {
+  __shared__ double xs[kSwapTile][kSwapTile + 1], ys[kSwapTile][kSwapTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const long long ntp = (long long)tiles * (tiles + 1) / 2;
+  const long long v2 = (long long)v * v;
+  for (long long w = blockIdx.x; w < nrows * ntp; w += gridDim.x) {
+    const long long r = w / ntp;
+    const int tp = static_cast<int>(w - r * ntp);
+    const int C = pair_row(tp, tiles);
+    const int D = C + static_cast<int>(tp - pair_prefix_d(C, tiles));
+    const int c0 = C * kSwapTile, d0 = D * kSwapTile;
+    long long src, rm;
+    if (MODE == PM_AMPS) {
+      const int i = pair_row(r, n);
+      const int j = i + static_cast<int>(r - pair_prefix_d(i, n));
+      src = (long long)i * n + j;
+      rm = i < j ? pair_prefix_d(i, n - 1) + (j - i - 1) : -1;
+    } else {
+      const long long q = pair_prefix_d(a0, v) + r;
+      const int a = pair_row(q, v);
+      const int b = a + static_cast<int>(q - pair_prefix_d(a, v));
+      src = r;
+      rm = a < b ? pair_prefix_d(a, v - 1) - pair_prefix_d(a0, v - 1) + (b - a - 1) : -1;
+    }
+    const In* x = X + src * v2;
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      const int c = c0 + k, d = d0 + tx;  // xs[k][tx] = X[c0+k][d0+tx]
+      xs[k][tx] = (c < v && d < v) ? static_cast<double>(x[(long long)c * v + d]) : 0.0;
+      const int dd = d0 + k, cc = c0 + tx;  // ys[k][tx] = X[d0+k][c0+tx]
+      ys[k][tx] = (dd < v && cc < v) ? static_cast<double>(x[(long long)dd * v + cc]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      const int c = c0 + k, d = d0 + tx;
+      if (c < v && d < v && c <= d) {
+        const double xcd = xs[k][tx], xdc = ys[tx][k];
+        const long long kp = pair_prefix_d(c, v) + (d - c);
+        plus[r * ldp + kp] = static_cast<Out>(c == d ? wdiag * xcd : xcd + xdc);
+        if (rm >= 0 && c < d) {
+          const long long km = pair_prefix_d(c, v - 1) + (d - c - 1);
+          minus[rm * ldm + km] = static_cast<Out>(sm * (xcd - xdc));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int MODE, typename In, typename Out>
+int pm_rows(const In* X, long long nrows, int n, int a0, int v, Out* plus, long long ldp,
+            Out* minus, long long ldm, double wdiag, double sm, hipStream_t s) {
+  if (nrows <= 0) return CC_LADDER_OK;
+  const int tiles = (v + kSwapTile - 1) / kSwapTile;
+  const long long work = nrows * ((long long)tiles * (tiles + 1) / 2);
+  const long long blocks = std::min<long long>(work, 65536);
+  hipLaunchKernelGGL((pm_rows_kernel<MODE, In, Out>), dim3(static_cast<unsigned>(blocks)), dim3(256),
+                     0, s, X, nrows, n, a0, v, tiles, plus, ldp, minus, ldm, wdiag, sm);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -658,6 +741,47 @@ int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T
   return CC_LADDER_OK;
 }
 
+// Forward over the symmetric and antisymmetric combinations (pair-symmetric t):
+// per block, the packed integral rows a <= b are built as in the pair-symmetric
+// forward, combined into V+ (a <= b, c <= d) and V- (a < b, c < d), and
+// contracted with t+ (rows i <= j) and t- (rows i < j); each product adds half
+// its result to R at the four (i,j)/(a,b) mirrors.
+template <class Tr>
+int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr::T* Tp,
+                      const typename Tr::T* Tm, double* R, typename Tr::T* V,
+                      typename Tr::T* Vp, typename Tr::T* Vm, int* row_tiles, const Tracer& tr,
+                      hipStream_t s) {
+  const int o = pl.o, v = pl.v, P = pl.P;
+  const long long v2 = (long long)v * v;
+  const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  const int mp = o * (o + 1) / 2, mm = o * (o - 1) / 2;
+  const int kp = static_cast<int>((long long)v * (v + 1) / 2);
+  const int km = static_cast<int>((long long)v * (v - 1) / 2);
+  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
+    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+    const long long off = (long long)a0 * v;
+    const long long np = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
+    const long long nm = np - na;
+    tr(CC_LADDER_PHASE_BUILD, blk, 0);
+    int rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
+                                               static_cast<int>((long long)(v - a0) * v), P, v,
+                                               drain, s, o, a0, row_tiles);
+    if (!rc)
+      rc = pm_rows<PM_INTS>(V, np, v, a0, v, Vp, pl.ldp, Vm, pl.ldm, 2.0, 1.0, s);
+    tr(CC_LADDER_PHASE_BUILD, blk, 1);
+    if (rc) return rc;
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
+    rc = launch_gemm<Tr, KC, KC, EPI_PM>(Tp, pl.ldp, Vp, pl.ldp, R, v2, mp, static_cast<int>(np), kp,
+                                         v, drain, s, o, a0, nullptr, 0.5, 1);
+    if (!rc)
+      rc = launch_gemm<Tr, KC, KC, EPI_PM>(Tm, pl.ldm, Vm, pl.ldm, R, v2, mm, static_cast<int>(nm),
+                                           km, v, drain, s, o, a0, nullptr, 0.5, 2);
+    tr(CC_LADDER_PHASE_CONTRACT, blk, 1);
+    if (rc) return rc;
+  }
+  return CC_LADDER_OK;
+}
+
 template <class Tr>
 int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t,
                     const typename Tr::T* lam, double* dL, double* dt, char* base,
@@ -819,7 +943,9 @@ int intermediate_call(int which, int o, int v, int P, const double* Lrow, const 
   const size_t nz = hole ? nt : (size_t)o * o * n_first * o * sizeof(double);
   if (overlaps(Z, nz, t, nt) || overlaps(Z, nz, Lov, nov) || overlaps(Z, nz, Lrow, nrow))
     return CC_LADDER_EINVAL;
-  if (precision == CC_LADDER_SPLIT_BF16 || (opts && opts->flags)) return CC_LADDER_EUNSUPPORTED;
+  if (precision == CC_LADDER_SPLIT_BF16 || precision == CC_LADDER_SPLIT_INT8 ||
+      (opts && opts->flags))
+    return CC_LADDER_EUNSUPPORTED;
   Plan pl;
   Scratch ws;
   if (opts && opts->workspace) {
@@ -902,6 +1028,35 @@ int residual_body(const Plan& pl, const double* L, const double* t, double* R, i
     if (rc) return rc;
   }
   const Tracer tr(opts, stream);
+  if (pl.pm) {
+    // t+ and t- (the exchange partner's amplitudes give t+ and -t-), then the blocks
+    const double sm = pl.exchange ? -1.0 : 1.0;
+    const long long mp = (long long)o * (o + 1) / 2;
+    tr(CC_LADDER_PHASE_PREP, 0, 0);
+    if (precision == CC_LADDER_FP64) {
+      double* Tp = reinterpret_cast<double*>(base + pl.off_Tp);
+      double* Tm = reinterpret_cast<double*>(base + pl.off_Tm);
+      rc = pm_rows<PM_AMPS>(t, mp, o, 0, v, Tp, pl.ldp, Tm, pl.ldm, 1.0, sm, stream);
+      tr(CC_LADDER_PHASE_PREP, 0, 1);
+      if (rc) return rc;
+      return forward_blocks_pm<TrF64>(pl, L, Tp, Tm, R, reinterpret_cast<double*>(base + pl.off_V),
+                                      reinterpret_cast<double*>(base + pl.off_Vp),
+                                      reinterpret_cast<double*>(base + pl.off_Vm),
+                                      reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
+    }
+    if (precision != CC_LADDER_FP32) return CC_LADDER_EUNSUPPORTED;
+    float* Tp = reinterpret_cast<float*>(base + pl.off_Tp);
+    float* Tm = reinterpret_cast<float*>(base + pl.off_Tm);
+    float* L32 = reinterpret_cast<float*>(base + pl.off_L);
+    rc = to_f32(L, L32, (size_t)P * v * v, stream);
+    if (!rc) rc = pm_rows<PM_AMPS>(t, mp, o, 0, v, Tp, pl.ldp, Tm, pl.ldm, 1.0, sm, stream);
+    tr(CC_LADDER_PHASE_PREP, 0, 1);
+    if (rc) return rc;
+    return forward_blocks_pm<TrF32>(pl, L32, Tp, Tm, R, reinterpret_cast<float*>(base + pl.off_V),
+                                    reinterpret_cast<float*>(base + pl.off_Vp),
+                                    reinterpret_cast<float*>(base + pl.off_Vm),
+                                    reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
+  }
   if (pl.exchange && precision != CC_LADDER_FP32) {
     // the exchange partner is the ladder of the swapped amplitudes
     double* tx = reinterpret_cast<double*>(base + pl.off_tx);
@@ -929,6 +1084,8 @@ int residual_body(const Plan& pl, const double* L, const double* t, double* R, i
     }
     case CC_LADDER_SPLIT_BF16:
       return split_forward(pl, L, t, R, base, tr, stream);
+    case CC_LADDER_SPLIT_INT8:
+      return split_i8_forward(pl, L, t, R, base, tr, stream);
     default:
       return CC_LADDER_EINVAL;
   }
@@ -965,7 +1122,8 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
   Operand ops[5];
   int rc = check_backward_args(o, v, P, L, t, lam, dL, dt, precision, opts, ops);
   if (rc) return rc;
-  if (precision == CC_LADDER_SPLIT_BF16) return CC_LADDER_EUNSUPPORTED;
+  if (precision == CC_LADDER_SPLIT_BF16 || precision == CC_LADDER_SPLIT_INT8)
+    return CC_LADDER_EUNSUPPORTED;
   Plan pl;
   Scratch ws;
   rc = plan_and_scratch(o, v, P, precision, 1, stream, opts, ops, 5, &pl, &ws);

@@ -26,6 +26,11 @@
 //             below the diagonal exit at once)
 //   EPI_PAIR: the contraction over packed rows: m = (i,j), n = pair(a,b) - pair(a0,a0);
 //             C[m*ldc + a*v + b] += acc and, for a != b, C[(j,i)*ldc + b*v + a] += acc
+//   EPI_PM:   the symmetric (pm = 1) or antisymmetric (pm = 2) combination over rows
+//             m = pair (i,j), i <= j (i < j for pm = 2), and columns n = pair (a,b) from
+//             a0, a <= b (a < b for pm = 2): val = alpha * acc is added to the set
+//             {R[i,j,a,b], R[j,i,b,a]} and, as +val (pm = 1) or -val (pm = 2), to
+//             {R[i,j,b,a], R[j,i,a,b]}, each distinct element once
 //   EPI_PART: split K: workgroup s of a tile sums K-steps [s*split_steps, (s+1)*split_steps)
 //             and stores C[s*part_stride + m*ldc + n] = acc (float64 partials, summed
 //             in order of s by a separate pass)
@@ -54,7 +59,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 enum { KC = 0, RC = 1 };
-enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3, EPI_PART = 4 };
+enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3, EPI_PART = 4, EPI_PM = 5 };
 
 // float64 operands on v_mfma_f64_16x16x4_f64.
 struct TrF64 {
@@ -114,7 +119,8 @@ struct GemmArgs {
   int split_steps;       // EPI_PART: K-steps per split
   long long part_stride; // EPI_PART: elements between consecutive splits' partials
   double alpha;          // EPI_ACC: C += alpha * acc (1, or 2 for a term counted twice)
-  int m_off = 0;         // EPI_PAIR: global row of this launch's row 0 (a remainder launch)
+  int m_off = 0;         // EPI_PAIR/PM: global row of this launch's row 0 (a remainder launch)
+  int pm = 0;            // EPI_PM: 1 = symmetric pairs (i <= j, a <= b), 2 = antisymmetric (<)
 };
 
 // First needed tile column of tile row tm in the packed build: columns whose
@@ -166,6 +172,15 @@ __device__ __forceinline__ EpiCol epi_col(const GemmArgs<T>& g, int n) {
     c.x = a;
     c.y = b;
     c.off = (long long)a * v + b;
+  } else if (EPI == EPI_PM) {
+    // pairs a < b of v are the pairs a <= b' = b - 1 of v - 1
+    const int s = g.pm == 2 ? 1 : 0;
+    const long long q = pair_prefix_d(g.a0, v - s) + n;
+    const int a = pair_row(q, g.v - s);
+    const int b = a + s + static_cast<int>(q - pair_prefix_d(a, v - s));
+    c.x = a;
+    c.y = b;
+    c.off = (long long)a * v + b;
   }
   return c;
 }
@@ -187,6 +202,22 @@ __device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, co
     if (c.x < al) return;
     const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (c.x - al);
     static_cast<T*>(g.C)[row * v * v + (long long)cc * v + c.off] = static_cast<T>(val);
+  } else if (EPI == EPI_PM) {
+    double* C = static_cast<double*>(g.C);
+    const int s = g.pm == 2 ? 1 : 0;
+    const int mg = m + g.m_off;
+    const int i = pair_row(mg, g.o - s);
+    const int j = i + s + static_cast<int>(mg - pair_prefix_d(i, g.o - s));
+    const double w = g.alpha * val;
+    const double x = s ? -w : w;  // weight of the a <-> b exchanged elements
+    const long long rij = (long long)(i * g.o + j) * g.ldc, rji = (long long)(j * g.o + i) * g.ldc;
+    const long long ab = c.off, ba = (long long)c.y * v + c.x;
+    C[rij + ab] += w;
+    if (c.x != c.y) C[rij + ba] += x;
+    if (i != j) {
+      C[rji + ba] += w;
+      if (c.x != c.y) C[rji + ab] += x;
+    }
   } else {  // EPI_PAIR
     double* C = static_cast<double*>(g.C);
     const int mg = m + g.m_off;

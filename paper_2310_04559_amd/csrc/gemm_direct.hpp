@@ -47,7 +47,8 @@ __device__ __forceinline__ void d_wait_vm(int n) {
 // product whose last 128-row tile row would be at most half full.
 template <class Tr, int EPI, int BM = kDBM>
 __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<typename Tr::T> g) {
-  static_assert(EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PART, "K-contiguous epilogues");
+  static_assert(EPI == EPI_ACC || EPI == EPI_PAIR || EPI == EPI_PART || EPI == EPI_PM,
+                "K-contiguous epilogues");
   static_assert(BM == kDBM || BM == 64 || (BM == 160 && !Tr::kDrain), "tile heights");
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;

@@ -39,15 +39,22 @@ int check_dims(int o, int v, int P) {
 
 int check_precision_opts(int precision, const cc_ladder_opts* opts) {
   if (precision != CC_LADDER_FP64 && precision != CC_LADDER_FP32 &&
-      precision != CC_LADDER_SPLIT_BF16)
+      precision != CC_LADDER_SPLIT_BF16 && precision != CC_LADDER_SPLIT_INT8)
     return CC_LADDER_EINVAL;
   if (!opts) return CC_LADDER_OK;
   if (opts->a_block < 0 || opts->split_depth < 0 || opts->split_depth > 2) return CC_LADDER_EINVAL;
-  if ((opts->flags & ~(CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE | CC_LADDER_CHECK_SYMMETRY)) != 0 ||
+  if ((opts->flags & ~(CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE | CC_LADDER_CHECK_SYMMETRY |
+                       CC_LADDER_PLUS_MINUS)) != 0 ||
       opts->reserved != 0)
     return CC_LADDER_EINVAL;
-  if (opts->split_slices != 0 && (opts->split_slices < 2 || opts->split_slices > 4))
+  // the symmetric/antisymmetric combinations rest on the pair-symmetry assertion
+  if ((opts->flags & CC_LADDER_PLUS_MINUS) && !(opts->flags & CC_LADDER_PAIR_SYMMETRIC))
     return CC_LADDER_EINVAL;
+  if (opts->split_slices != 0) {
+    const int lo = precision == CC_LADDER_SPLIT_INT8 ? 4 : 2;
+    const int hi = precision == CC_LADDER_SPLIT_INT8 ? 5 : 4;
+    if (opts->split_slices < lo || opts->split_slices > hi) return CC_LADDER_EINVAL;
+  }
   if (opts->k_chunk < 0 || opts->k_chunk % 64 != 0) return CC_LADDER_EINVAL;
   if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
     return CC_LADDER_EINVAL;
@@ -129,11 +136,35 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   const size_t blk_w = static_cast<size_t>(n_a) * v * v2;
   size_t cur = 0;
   p.exchange = (flags & CC_LADDER_EXCHANGE) ? 1 : 0;
+  p.pm = (p.pairsym && (flags & CC_LADDER_PLUS_MINUS)) ? 1 : 0;
   if (p.exchange) {
-    // the float32 form swaps while converting into its own operand copy
-    if (precision != CC_LADDER_FP32) p.off_tx = take(&cur, o2 * v2 * sizeof(double));
+    // the float32 form swaps while converting into its own operand copy; the
+    // combinations t+- of swapped amplitudes are t+ and -t-, made without a copy
+    if (precision != CC_LADDER_FP32 && !p.pm) p.off_tx = take(&cur, o2 * v2 * sizeof(double));
     if (p.backward) p.off_dtx = take(&cur, o2 * v2 * sizeof(double));
   }
+  if (p.pm) {
+    if (precision == CC_LADDER_SPLIT_BF16 || precision == CC_LADDER_SPLIT_INT8)
+      return CC_LADDER_EUNSUPPORTED;
+    // operand rows over the pairs c <= d (t+, V+) and c < d (t-, V-), strides
+    // rounded to 16-byte multiples of either element size
+    const size_t es = precision == CC_LADDER_FP64 ? sizeof(double) : sizeof(float);
+    const size_t kp = static_cast<size_t>(v) * (v + 1) / 2, km = static_cast<size_t>(v) * (v - 1) / 2;
+    p.ldp = static_cast<long long>((kp + 3) / 4 * 4);
+    p.ldm = static_cast<long long>((km + 3) / 4 * 4);
+    const size_t mp = static_cast<size_t>(o) * (o + 1) / 2, mm = static_cast<size_t>(o) * (o - 1) / 2;
+    // packed rows of the largest (first) block: a <= b, and a < b
+    const size_t np = npk, nm = npk - static_cast<size_t>(n_a);
+    p.off_Tp = take(&cur, mp * p.ldp * es);
+    p.off_Tm = take(&cur, mm * p.ldm * es);
+    p.off_Vp = take(&cur, np * p.ldp * es);
+    p.off_Vm = take(&cur, nm * p.ldm * es);
+    if (precision == CC_LADDER_FP32) {
+      p.k_chunk = k_chunk ? k_chunk : 512;
+      p.off_L = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
+    }
+    p.off_V = take(&cur, blk * es);
+  } else {
   switch (precision) {
     case CC_LADDER_FP64:
       p.off_V = take(&cur, blk * sizeof(double));
@@ -161,14 +192,34 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad * 2);
       p.off_Lexp = take(&cur, static_cast<size_t>(dL.rows_pad) * sizeof(int));
       p.off_t = take(&cur, s * dt.rows_pad * dt.k_pad * 2);
-      p.off_texp = take(&cur, static_cast<size_t>(dt.rows_pad) * exp_chunks(dt.k_pad) * sizeof(int));
+      p.off_texp = take(&cur, static_cast<size_t>(dt.rows_pad) * exp_chunks(dt.k_pad, p.slices) * sizeof(int));
       p.off_V = take(&cur, blk * sizeof(double));
       p.off_Vs = take(&cur, s * dV.rows_pad * dV.k_pad * 2);
-      p.off_Vexp = take(&cur, static_cast<size_t>(dV.rows_pad) * exp_chunks(dV.k_pad) * sizeof(int));
+      p.off_Vexp = take(&cur, static_cast<size_t>(dV.rows_pad) * exp_chunks(dV.k_pad, p.slices) * sizeof(int));
+      break;
+    }
+    case CC_LADDER_SPLIT_INT8: {
+      if (p.backward) return CC_LADDER_EUNSUPPORTED;
+      p.slices = slices ? slices : 5;
+      p.split_depth = depth ? depth : 1;
+      // the kernels hold S + depth - 1 int32 sums per output: 5 at most
+      if (p.slices + p.split_depth - 1 > 5) return CC_LADDER_EUNSUPPORTED;
+      const size_t s = static_cast<size_t>(p.slices);  // one byte per digit
+      const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
+      const SliceDims dt = slice_dims(static_cast<long long>(o2), static_cast<int>(v2));
+      const SliceDims dV = slice_dims(static_cast<long long>(rows), static_cast<int>(v2));
+      p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad);
+      p.off_Lexp = take(&cur, static_cast<size_t>(dL.rows_pad) * i8_chunks(dL.k_pad) * sizeof(int));
+      p.off_t = take(&cur, s * dt.rows_pad * dt.k_pad);
+      p.off_texp = take(&cur, static_cast<size_t>(dt.rows_pad) * i8_chunks(dt.k_pad) * sizeof(int));
+      p.off_V = take(&cur, blk * sizeof(double));
+      p.off_Vs = take(&cur, s * dV.rows_pad * dV.k_pad);
+      p.off_Vexp = take(&cur, static_cast<size_t>(dV.rows_pad) * i8_chunks(dV.k_pad) * sizeof(int));
       break;
     }
     default:
       return CC_LADDER_EINVAL;
+  }
   }
   if (p.pairsym_adj) {
     // the adjoint's dt accumulates B[(ij)][(cd)] over packed rows; dt += B + mirror(B)
@@ -327,6 +378,7 @@ int layout_intermediate(int which, int o, int v, int P, int precision, int n_p, 
       p.off_V = take(&cur, blk * sizeof(float));
       break;
     case CC_LADDER_SPLIT_BF16:
+    case CC_LADDER_SPLIT_INT8:
       return CC_LADDER_EUNSUPPORTED;
     default:
       return CC_LADDER_EINVAL;

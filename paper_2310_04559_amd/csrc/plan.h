@@ -35,6 +35,10 @@ struct Plan {
   int exchange = 0;     // exchange partner: amplitudes (and dt) with c,d swapped
   size_t off_tx = 0;    // exchange: t with its last two indices swapped (float64; not in FP32)
   size_t off_dtx = 0;   // exchange adjoint: dt of the swapped amplitudes (float64)
+  int pm = 0;           // forward over the symmetric/antisymmetric combinations (PLUS_MINUS)
+  long long ldp = 0, ldm = 0;  // PLUS_MINUS: row strides of the c <= d and c < d operands
+  size_t off_Tp = 0, off_Tm = 0;  // PLUS_MINUS: t+ [o(o+1)/2][ldp], t- [o(o-1)/2][ldm]
+  size_t off_Vp = 0, off_Vm = 0;  // PLUS_MINUS: V+ [pairs a <= b][ldp], V- [pairs a < b][ldm]
   int k_chunk = 0;      // float32 drain interval along the contracted index
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;

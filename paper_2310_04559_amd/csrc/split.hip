@@ -2,27 +2,31 @@
 //
 // Three or four slices: every operand row (a row of the matrix along its
 // contracted index) gets an exponent e with max|x| < 2^e -- one per row for the
-// integral build, one per (row, chunk of 128 contracted indices) for the
-// amplitude contraction -- and each value is cut into S balanced base-256 digits:
+// integral build, one per (row, chunk of contracted indices) for the amplitude
+// contraction -- and each value is cut into S balanced base-256 digits:
 //   x = 2^e * sum_{p=1..S} d_p 2^(-8p) + r,   d_1 in [-256, 256], d_p in [-128, 128] (p > 1),
 // |r| <= 2^(e - 8S - 1).  Digits are integers, exact in bf16.  A product of two
 // such matrices is, per K-chunk c,
 //   C[m][n] += 2^(eA[m,c] + eB[n,c]) sum_{g} 2^(-8g) sum_{p+q=g} sum_{k in c} dA_p[m][k] dB_q[n][k],
 // keeping the anti-diagonals g = p + q <= S + D (D = 1: the S(S+1)/2-product
 // triangle; D = 2 adds the next anti-diagonal).  Each inner sum is a sum of
-// integer products; over a chunk of 128 every partial sum of one group stays
-// below 2^24, so the bf16 MFMA's float32 accumulation is exact and each chunk is
-// drained into float64 with its own scale.  Exponents per chunk follow the
-// operands' magnitude along the contracted index and halve the contraction's
-// error at the same digit count (1.0e-9 -> 5.0e-10 over whole rows at
-// o=20 v=180 P=600 in the exact NumPy model of the scheme); for the build,
-// whose rows (Cholesky vectors along x) are evenly scaled, they change nothing.
+// integer products.  A chunk is 256 indices with four slices: the products of
+// the two leading anti-diagonals are at most 2^16 each and 2^24 over the
+// chunk, so those float32 sums are exact (the anti-diagonals g >= 2 share one
+// rounded sum); with three slices, whose third anti-diagonal has three
+// products, it is 128 indices and every group is exact.  Each chunk is drained
+// into float64 with its own scale.  Exponents per chunk follow the operands'
+// magnitude along the contracted index and cut the contraction's error at the
+// same digit count (1.0e-9 with one exponent per row, 4.0e-10 per 128 and
+// 4.4e-10 per 256 indices at o=20 v=180 P=600 in the exact NumPy model of the
+// scheme); for the build, whose rows (Cholesky vectors along x) are evenly
+// scaled, they change nothing.  Chunks of 256 halve the drains against 128.
 //
 // Two slices are the per-element hi/lo split instead: hi = bf16(x) and
 // lo = bf16(x - hi), both rounded to nearest even, so each operand carries about
 // 16 significant bits of its own magnitude (no shared exponent).  The products
 // hi*hi, hi*lo and lo*hi (D = 1; D = 2 adds lo*lo) are summed in float32 over
-// each 128-index chunk (rounded, not exact) and drained to float64.  The same
+// each 256-index chunk (rounded, not exact) and drained to float64.  The same
 // kernels serve it with every exponent fixed at 8, which makes every scale 1.
 //
 // The two contractions then run as:
@@ -45,8 +49,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kSBN = 128;   // workgroup tile columns (N)
 constexpr int kSBK = 32;    // K per stage = one bf16 MFMA depth
-constexpr int kChunkSteps = 4;  // K-steps per float32 chunk (128 contracted indices)
-static_assert(kChunkSteps * kSBK == kExpChunk, "one exponent per chunk");
+// K-steps per float32 chunk (one exponent per chunk of the contraction's rows)
+template <int S>
+constexpr int chunk_steps() { return exp_chunk_len(S) / kSBK; }
 
 // Balanced base-256 digits of y in (-1, 1): y = 2^-8 sum_p q_p 2^(-8p) with
 // integers |q_0| <= 256, |q_p| <= 128.  Slice p holds q_p 2^(-8p) (exact in
@@ -101,9 +106,9 @@ __device__ __forceinline__ long long digit_offset(long long r, int k, int Kp) {
 
 // Rows with the contracted index contiguous: X[r][k] = X[r*ld + k], r < R, k < K.
 // One workgroup per output row (R_pad rows, the padding rows get zero digits).
-// Exponents per (row, chunk of kExpChunk): ex[c * ex_stride + r].  The 16
-// threads that cut one chunk (8 values each) are adjacent lanes of one wave and
-// agree on its maximum through shuffles.  A wave's 512 indices are 16 K-steps,
+// Exponents per (row, chunk of exp_chunk_len(S)): ex[c * ex_stride + r].  The
+// 32 (16 for three slices) threads that cut one chunk (8 values each) are
+// adjacent lanes of one wave and agree on its maximum through shuffles.  A wave's 512 indices are 16 K-steps,
 // whose digits are S KB of contiguous memory: the wave lays them out in a
 // private LDS block and stores them as whole 1 KB rows (a lane's own digits
 // would cover only 64 bytes of a line per store).
@@ -112,7 +117,8 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
                                                        int R, int K, int Kp,
                                                        __bf16* __restrict__ out, int* __restrict__ ex,
                                                        int ex_stride) {
-  static_assert(kExpChunk == 16 * 8, "a chunk is cut by 16 threads of 8 values");
+  constexpr int TPC = exp_chunk_len(S) / 8;  // threads per chunk
+  static_assert(TPC == 16 || TPC == 32, "a chunk is cut by 16 or 32 threads of 8 values");
   constexpr int STEP_BYTES = S * kSBK * 2;  // one K-step of one row, all slices
   __shared__ __attribute__((aligned(16))) unsigned char stage[4][16 * STEP_BYTES];
   const int r = blockIdx.x;
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
   // stored), so the wave-level exchange below always has the whole wave
   for (int base = 0; base < Kp; base += 256 * 8) {
     const int k0 = base + tid * 8;
-    const int cstart = base + (tid & ~15) * 8;  // first index of this lane's chunk
+    const int cstart = base + (tid & ~(TPC - 1)) * 8;  // first index of this lane's chunk
     double x[8];
     if (vec && k0 + 8 <= K) {
 #pragma unroll
@@ -150,11 +156,12 @@ __global__ __launch_bounds__(256) void slice_kc_kernel(const double* __restrict_
 #pragma unroll
       for (int j = 0; j < 8; ++j) m = fmax(m, fabs(x[j]));
 #pragma unroll
-      for (int w = 8; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, 16));
+      for (int w = TPC / 2; w >= 1; w >>= 1) m = fmax(m, __shfl_xor(m, w, TPC));
       e = 0;
       if (m > 0.0) (void)frexp(m, &e);  // max|x| < 2^e over the chunk
     }
-    if ((tid & 15) == 0 && cstart < Kp) ex[(cstart / kExpChunk) * (long long)ex_stride + r] = e;
+    if ((tid & (TPC - 1)) == 0 && cstart < Kp)
+      ex[(cstart / exp_chunk_len(S)) * (long long)ex_stride + r] = e;
     __bf16 d[8][S];
 #pragma unroll
     for (int j = 0; j < 8; ++j) cut<S>(x[j], e, d[j]);
@@ -246,6 +253,7 @@ struct SplitArgs {
   int a0;            // EPI_PACK/PAIR: first virtual of the integral block
   const int* row_tiles;  // EPI_PACK compact grid: first linear tile of each tile row
   int tiles_m, tiles_n, group_m;
+  int m_off;             // EPI_ACC/PAIR: output row of this product's row 0 (a remainder launch)
 };
 
 // Workgroup tile BM x 128 (M x N), K-steps of 32 (one bf16 MFMA depth).  Slice
@@ -382,6 +390,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     if (k < nk) issue_a(k);
     if (k < nk) issue_b(k);
   }
+  constexpr int kChunkSteps = chunk_steps<S>();
   for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
     // one chunk: float32 sums per anti-diagonal g = p + q (the last accumulator
     // takes every g >= NACC - 1)
@@ -508,8 +517,9 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
         const double val =
             CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], (S == 2 ? kHiLoExp : g.ea[m]) + en);
         double* C = static_cast<double*>(g.C);
+        const int mo = m + g.m_off;  // output row
         if (EPI == EPI_ACC) {
-          C[(long long)m * g.ldc + n] += val;
+          C[(long long)mo * g.ldc + n] += val;
         } else if (EPI == EPI_PERM) {
           const int a = m / g.v, x = m - a * g.v;
           C[(long long)a * v * v * v + ncol + (long long)x * v] = val;
@@ -520,9 +530,9 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
           const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (pa - al);
           C[row * v * v + (long long)c * v + pb] = val;
         } else {  // EPI_PAIR: R[i][j][a][b] and, for a != b, R[j][i][b][a]
-          C[(long long)m * g.ldc + (long long)pa * v + pb] += val;
+          C[(long long)mo * g.ldc + (long long)pa * v + pb] += val;
           if (pa != pb) {
-            const int ii = m / g.o, jj = m - ii * g.o;
+            const int ii = mo / g.o, jj = mo - ii * g.o;
             C[(long long)(jj * g.o + ii) * g.ldc + (long long)pb * v + pa] += val;
           }
         }
@@ -558,11 +568,46 @@ struct SplitShape {
   static constexpr int NACC = S == 4 && NG > 3 ? 3 : NG;
 };
 
+// Rows of a 128-row-tile product that a launch of 64-row tiles takes over (0 =
+// none): the remainder, when the last tile row would be at most half full and
+// the two launches finish first by (rounds of the grid over the 256 CUs) x
+// (tile height).
+long long split_remainder_rows(long long M, long long N) {
+  constexpr long long kCUs = 256;
+  const long long tn = (N + kSBN - 1) / kSBN;
+  auto span = [&](long long rows, long long bm) {
+    return ((rows + bm - 1) / bm * tn + kCUs - 1) / kCUs * bm;
+  };
+  const long long rem = M % 128;
+  if (M <= 128 || rem == 0 || rem > 64) return 0;
+  return span(M - rem, 128) + span(rem, 64) < span(M, 128) ? rem : 0;
+}
+
 template <int S, int D, int EPI>
 int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
   using Sh = SplitShape<S, D>;
   SplitArgs a = a0;
   if (a.M <= 0 || a.N <= 0) return CC_LADDER_OK;
+  if constexpr ((EPI == EPI_ACC || EPI == EPI_PAIR) && Sh::BM == 128) {
+    // the remainder rows of the amplitude contraction in a launch of 64-row
+    // tiles (8 waves of 32 x 32, three stages, or four with two slices)
+    const long long rem = split_remainder_rows(a.M, a.N);
+    if (rem > 0) {
+      SplitArgs r = a;
+      a.M -= static_cast<int>(rem);
+      r.M = static_cast<int>(rem);
+      r.A += (long long)a.M * a.Kp * S;
+      r.ea += a.M;
+      r.m_off = a.m_off + a.M;
+      r.tiles_m = 1;
+      r.tiles_n = (r.N + kSBN - 1) / kSBN;
+      r.group_m = 1;
+      constexpr int RST = S == 2 ? 4 : 3;
+      hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, 8, 64, RST, Sh::NACC>),
+                         dim3(static_cast<unsigned>(r.tiles_n)), dim3(512), 0, s, r);
+      if (hipGetLastError() != hipSuccess) return CC_LADDER_EHIP;
+    }
+  }
   a.tiles_m = (a.M + Sh::BM - 1) / Sh::BM;
   a.tiles_n = (a.N + kSBN - 1) / kSBN;
   const long long tiles = (long long)a.tiles_m * a.tiles_n;

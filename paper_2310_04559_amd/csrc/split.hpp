@@ -17,10 +17,21 @@ struct SliceDims {
   int k_pad;
 };
 
-// Contracted indices per exponent of the contraction's digit rows (one exact
-// float32 chunk of the slice-pair GEMM).
-constexpr int kExpChunk = 128;
-inline int exp_chunks(int k_pad) { return (k_pad + kExpChunk - 1) / kExpChunk; }
+// Contracted indices per exponent of the contraction's digit rows, which is
+// also the length of one float32 chunk of the slice-pair GEMM: 256 for four
+// slices and the hi/lo split, whose exact groups (the leading two
+// anti-diagonals, partial sums of at most 256 * 2^16 = 2^24) stay exact over
+// 256 indices; 128 for three slices, whose third anti-diagonal would not.
+constexpr int exp_chunk_len(int slices) { return slices == 3 ? 128 : 256; }
+inline int exp_chunks(int k_pad, int slices) {
+  return (k_pad + exp_chunk_len(slices) - 1) / exp_chunk_len(slices);
+}
+
+// Contracted indices per exponent and per exact int32 chunk of the split-int8
+// form (a group of at most 5 products of int8 digits stays below
+// 5 * 2^14 * 16384 < 2^31).
+constexpr int kI8Chunk = 16384;
+inline int i8_chunks(int k_pad) { return k_pad > 0 ? (k_pad + kI8Chunk - 1) / kI8Chunk : 1; }
 
 inline SliceDims slice_dims(long long rows, int K) {
   SliceDims d;
@@ -31,5 +42,7 @@ inline SliceDims slice_dims(long long rows, int K) {
 
 int split_forward(const Plan& pl, const double* L, const double* t, double* R, char* ws,
                   const Tracer& tr, hipStream_t stream);
+int split_i8_forward(const Plan& pl, const double* L, const double* t, double* R, char* ws,
+                     const Tracer& tr, hipStream_t stream);
 
 }  // namespace ccl

@@ -63,8 +63,8 @@ class LadderFn(torch.autograd.Function):
     def backward(ctx, gR):
         L, t = ctx.saved_tensors
         precision = native._prec(ctx.precision)
-        if precision == native.CC_LADDER_SPLIT_BF16:
-            # the slice form is forward-only; its adjoint runs in float32
+        if precision in (native.CC_LADDER_SPLIT_BF16, native.CC_LADDER_SPLIT_INT8):
+            # the digit forms are forward-only; their adjoint runs in float32
             precision = native.CC_LADDER_FP32
         opts = ctx.opts
         if opts is not None:
@@ -72,7 +72,8 @@ class LadderFn(torch.autograd.Function):
             # not be pair-symmetric
             opts = native.copy_opts(opts, workspace=None,
                                     flags=opts.flags & ~(native.CC_LADDER_PAIR_SYMMETRIC
-                                                         | native.CC_LADDER_CHECK_SYMMETRY))
+                                                         | native.CC_LADDER_CHECK_SYMMETRY
+                                                         | native.CC_LADDER_PLUS_MINUS))
         P, v, _ = L.shape
         o = t.shape[0]
         run = _with_workspace(opts, o, v, P, precision, True, t.device)

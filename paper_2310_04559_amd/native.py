@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libccladder.so")
 CC_LADDER_FP64 = 0
 CC_LADDER_FP32 = 1
 CC_LADDER_SPLIT_BF16 = 2
-PRECISIONS = {"fp64": CC_LADDER_FP64, "fp32": CC_LADDER_FP32, "split_bf16": CC_LADDER_SPLIT_BF16}
+CC_LADDER_SPLIT_INT8 = 3
+PRECISIONS = {"fp64": CC_LADDER_FP64, "fp32": CC_LADDER_FP32, "split_bf16": CC_LADDER_SPLIT_BF16,
+              "split_int8": CC_LADDER_SPLIT_INT8}
 
 CC_LADDER_OK = 0
 CC_LADDER_EINVAL = -1
@@ -52,6 +54,7 @@ class CcLadderOpts(ctypes.Structure):
 CC_LADDER_PAIR_SYMMETRIC = 1
 CC_LADDER_EXCHANGE = 2
 CC_LADDER_CHECK_SYMMETRY = 4
+CC_LADDER_PLUS_MINUS = 8
 CC_INTERMEDIATE_IJKL = 0
 CC_INTERMEDIATE_IJBK = 1
 CC_HOLE_LADDER = 2
@@ -113,7 +116,8 @@ def strerror(code: int) -> str:
 def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_budget: int = 0,
               workspace: Optional[torch.Tensor] = None, trace=None,
               split_depth: int = 0, pair_symmetric: bool = False,
-              exchange: bool = False, check_symmetry: bool = False) -> CcLadderOpts:
+              exchange: bool = False, check_symmetry: bool = False,
+              plus_minus: bool = False) -> CcLadderOpts:
     """``trace`` is a TRACE_FN.  The options keep references to the workspace
     tensor and the trace callback, so neither is freed while they are in use."""
     o = CcLadderOpts()
@@ -123,7 +127,8 @@ def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_bud
     o.split_depth = int(split_depth)
     o.flags = ((CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0)
                | (CC_LADDER_EXCHANGE if exchange else 0)
-               | (CC_LADDER_CHECK_SYMMETRY if check_symmetry else 0))
+               | (CC_LADDER_CHECK_SYMMETRY if check_symmetry else 0)
+               | (CC_LADDER_PLUS_MINUS if plus_minus else 0))
     o.reserved = 0
     o.hbm_budget = int(hbm_budget)
     o._workspace_ref = None

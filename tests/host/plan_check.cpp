@@ -33,7 +33,7 @@ static void argument_checks() {
   CHECK(check_residual_args(2, 8, 4, nullptr, P_(t), P_(R), 0, nullptr, ops) == CC_LADDER_EINVAL);
   CHECK(check_residual_args(2, 8, 4, P_(L), P_(t), P_(t + 8), 0, nullptr, ops) == CC_LADDER_EINVAL);
   CHECK(check_residual_args(2, 8, 4, P_(L), P_(t), P_(L + 2040), 0, nullptr, ops) == CC_LADDER_EINVAL);
-  CHECK(check_residual_args(2, 8, 4, P_(L), P_(t), P_(R), 3, nullptr, ops) == CC_LADDER_EINVAL);
+  CHECK(check_residual_args(2, 8, 4, P_(L), P_(t), P_(R), 4, nullptr, ops) == CC_LADDER_EINVAL);
   // dimensions whose byte counts would not fit comfortably in size_t
   CHECK(check_residual_args(46340, 46340, 1, P_(L), P_(t), P_(R), 0, nullptr, ops) == CC_LADDER_EINVAL);
   CHECK(check_residual_args(1, 46340, 1 << 24, P_(L), P_(t), P_(R), 0, nullptr, ops) ==
@@ -52,7 +52,7 @@ static void argument_checks() {
   cc_ladder_opts o{};
   o.flags = CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE | CC_LADDER_CHECK_SYMMETRY;
   CHECK(check_precision_opts(0, &o) == CC_LADDER_OK);
-  o.flags = 8;
+  o.flags = 16;  // no such flag
   CHECK(check_precision_opts(0, &o) == CC_LADDER_EINVAL);
   o = cc_ladder_opts{};
   o.workspace = reinterpret_cast<void*>(uintptr_t(4096 + 128));
@@ -89,12 +89,20 @@ static void plan_invariants(const Plan& p, int backward, size_t budget) {
   CHECK(budget == 0 || p.bytes <= budget);
   const size_t offs[] = {p.off_lamP, p.off_B, p.off_check, p.off_tx, p.off_dtx, p.off_L, p.off_t,
                          p.off_lam, p.off_L2, p.off_part, p.off_Lexp, p.off_texp, p.off_V, p.off_W,
-                         p.off_Vs, p.off_Vexp, p.off_tiles};
+                         p.off_Vs, p.off_Vexp, p.off_tiles, p.off_Tp, p.off_Tm, p.off_Vp,
+                         p.off_Vm};
   for (size_t off : offs) {
     CHECK(off % 256 == 0);
     CHECK(off == 0 || off < p.bytes);
   }
-  if (backward) CHECK(p.off_W > p.off_V || p.precision == CC_LADDER_SPLIT_BF16);
+  if (backward) CHECK(p.off_W > p.off_V);
+  if (p.pm) {
+    // row strides of the pair operands: whole 16-byte chunks of either element size
+    CHECK(p.ldp % 4 == 0 && p.ldm % 4 == 0);
+    CHECK(p.ldp >= static_cast<long long>(p.v) * (p.v + 1) / 2);
+    CHECK(p.ldm >= static_cast<long long>(p.v) * (p.v - 1) / 2);
+    CHECK(p.pairsym && !backward && p.off_Vp > p.off_Tp && p.off_V > 0);
+  }
 }
 
 static void planner_sweep() {
@@ -104,17 +112,29 @@ static void planner_sweep() {
     const int o = 1 + static_cast<int>(rng() % 64);
     const int v = 1 + static_cast<int>(rng() % 700);
     const int P = 1 + static_cast<int>(rng() % 2500);
-    const int precision = static_cast<int>(rng() % 3);
+    const int precision = static_cast<int>(rng() % 4);
     const int backward = static_cast<int>(rng() % 2);
+    const bool split = precision == CC_LADDER_SPLIT_BF16 || precision == CC_LADDER_SPLIT_INT8;
     cc_ladder_opts opts{};
-    opts.flags = static_cast<unsigned>(rng() % 8);
-    opts.split_slices = (rng() % 3 == 0) ? 0 : 2 + static_cast<int>(rng() % 3);
+    opts.flags = static_cast<unsigned>(rng() % 16);
+    if (precision == CC_LADDER_SPLIT_INT8)
+      opts.split_slices = (rng() % 3 == 0) ? 0 : 4 + static_cast<int>(rng() % 2);
+    else
+      opts.split_slices = (rng() % 3 == 0) ? 0 : 2 + static_cast<int>(rng() % 3);
     opts.split_depth = static_cast<int>(rng() % 3);
     opts.a_block = (rng() % 4 == 0) ? 1 + static_cast<int>(rng() % v) : 0;
     const size_t budget = (rng() % 5 == 0) ? 0 : (size_t(1) << (20 + rng() % 20));
     Plan p;
     const int rc = make_plan(o, v, P, precision, backward, budget, &opts, &p);
-    if (precision == CC_LADDER_SPLIT_BF16 && backward) {
+    const bool pm = (opts.flags & CC_LADDER_PLUS_MINUS) != 0;
+    if (pm && !(opts.flags & CC_LADDER_PAIR_SYMMETRIC)) {
+      CHECK(rc == CC_LADDER_EINVAL);
+      continue;
+    }
+    const int i8_slices = opts.split_slices ? opts.split_slices : 5;
+    const int i8_depth = opts.split_depth ? opts.split_depth : 1;
+    if ((split && backward) || (split && pm) ||
+        (precision == CC_LADDER_SPLIT_INT8 && i8_slices + i8_depth - 1 > 5)) {
       CHECK(rc == CC_LADDER_EUNSUPPORTED);
       continue;
     }

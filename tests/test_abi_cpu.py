@@ -98,7 +98,7 @@ def test_planner_pair_symmetric_footprint(native):
     assert n3 == v and shalf < sfull
     rows_pad = lambda r: (r + 127) // 128 * 128 + 128
     kp, npk = (v * v + 63) // 64 * 64, v * (v + 1) // 2
-    chunks = (kp + 127) // 128
+    chunks = (kp + 255) // 256  # one exponent per 256 contracted indices with four slices
     packed = (rnd(npk * v * v * 8) + rnd(4 * rows_pad(npk) * kp * 2) + rnd(rows_pad(npk) * chunks * 4)
               + rnd(((v * v + 63) // 64 + 1) * 4))
     dense = rnd(v ** 4 * 8) + rnd(4 * rows_pad(v * v) * kp * 2) + rnd(rows_pad(v * v) * chunks * 4)
@@ -215,7 +215,7 @@ def test_planner_explicit_block_and_enomem(native):
     assert e.value.code == native.CC_LADDER_ENOMEM
 
 
-@pytest.mark.parametrize("o,v,P,prec", [(0, 4, 4, 0), (2, 0, 4, 0), (2, 4, -1, 0), (2, 4, 4, 3),
+@pytest.mark.parametrize("o,v,P,prec", [(0, 4, 4, 0), (2, 0, 4, 0), (2, 4, -1, 0), (2, 4, 4, 4),
                                         (2, 4, 4, -1), (50000, 4, 4, 0)])
 def test_planner_rejects_bad_arguments(native, o, v, P, prec):
     with pytest.raises(native.LadderError) as e:
@@ -356,3 +356,78 @@ def test_make_opts_keeps_its_tensors(native):
     assert o.flags == native.CC_LADDER_PAIR_SYMMETRIC | native.CC_LADDER_CHECK_SYMMETRY
     c = native.copy_opts(o, a_block=3)
     assert c.a_block == 3 and c.flags == o.flags and o.a_block == 0
+
+
+def test_planner_plus_minus_footprint(native):
+    # t+ / t- over the pairs i <= j, i < j and c <= d, c < d (row strides rounded
+    # to 4 elements), V+ / V- over the block's pairs a <= b, a < b, the packed
+    # integral block, and the packed build's tile offsets
+    def r256(x):
+        return (x + 255) // 256 * 256
+
+    o, v, P, n_a = 5, 21, 30, 6
+    for prec, es in (("fp64", 8), ("fp32", 4)):
+        nbytes, blk = native.cc_ladder_workspace_query(
+            o, v, P, prec, opts=native.make_opts(a_block=n_a, pair_symmetric=True, plus_minus=True))
+        assert blk == n_a
+        kp, km = v * (v + 1) // 2, v * (v - 1) // 2
+        ldp, ldm = (kp + 3) // 4 * 4, (km + 3) // 4 * 4
+        npk = n_a * v - n_a * (n_a - 1) // 2
+        want = (r256(o * (o + 1) // 2 * ldp * es) + r256(o * (o - 1) // 2 * ldm * es)
+                + r256(npk * ldp * es) + r256((npk - n_a) * ldm * es))
+        if prec == "fp32":
+            want += r256(P * v * v * 4)
+        want += r256(npk * v * v * es)
+        tiles_m = (n_a * v + 127) // 128
+        want += r256((tiles_m + 1) * 4)
+        assert nbytes == want, (prec, nbytes, want)
+
+
+def test_plus_minus_needs_pair_symmetry(native):
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(3, 10, 5, "fp64", opts=native.make_opts(plus_minus=True))
+    assert e.value.code == native.CC_LADDER_EINVAL
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(3, 10, 5, "split_bf16",
+                                         opts=native.make_opts(pair_symmetric=True, plus_minus=True))
+    assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+    # the adjoint plans as with pair symmetry alone
+    a = native.cc_ladder_workspace_query(3, 10, 5, "fp64", backward=True,
+                                         opts=native.make_opts(pair_symmetric=True, plus_minus=True))
+    b = native.cc_ladder_workspace_query(3, 10, 5, "fp64", backward=True,
+                                         opts=native.make_opts(pair_symmetric=True))
+    assert a == b
+
+
+def test_planner_split_int8_footprint(native):
+    # int8 digit buffers (one byte per digit) of L (rows v^2, K = P padded to
+    # 64), t and one integral block, exponents per (row, chunk of 16384), and
+    # the float64 block
+    def r256(x):
+        return (x + 255) // 256 * 256
+
+    rows_pad = lambda r: (r + 127) // 128 * 128 + 128
+    o, v, P = 4, 30, 50
+    for S in (0, 4, 5):
+        nbytes, n = native.cc_ladder_workspace_query(o, v, P, "split_int8",
+                                                     opts=native.make_opts(split_slices=S))
+        s = S or 5
+        kL, kt = (P + 63) // 64 * 64, (v * v + 63) // 64 * 64
+        ch = lambda k: max(1, (k + 16383) // 16384)
+        want = (r256(s * rows_pad(v * v) * kL) + r256(rows_pad(v * v) * ch(kL) * 4)
+                + r256(s * rows_pad(o * o) * kt) + r256(rows_pad(o * o) * ch(kt) * 4)
+                + r256(v ** 4 * 8) + r256(s * rows_pad(v * v) * kt) + r256(rows_pad(v * v) * ch(kt) * 4))
+        assert n == v and nbytes == want, (S, nbytes, want)
+    for bad in (2, 3, 6):
+        with pytest.raises(native.LadderError) as e:
+            native.cc_ladder_workspace_query(o, v, P, "split_int8",
+                                             opts=native.make_opts(split_slices=bad))
+        assert e.value.code == native.CC_LADDER_EINVAL
+    # five digits keep the triangle only (five int32 sums per output)
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(o, v, P, "split_int8",
+                                         opts=native.make_opts(split_slices=5, split_depth=2))
+    assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(o, v, P, "split_int8", backward=True)
+    assert e.value.code == native.CC_LADDER_EUNSUPPORTED

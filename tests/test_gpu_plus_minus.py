@@ -1,0 +1,99 @@
+"""GPU parity of the symmetric/antisymmetric (t+, t-) forward against the
+float64 oracle, through the C ABI.
+
+With pair-symmetric amplitudes the library contracts V+ = (ac|bd) + (ad|bc)
+with t+ over the pairs c <= d, and V- with t- over c < d, for rows i <= j
+(i < j) and columns a <= b (a < b), and scatters half of each result to the
+four (i,j)/(a,b) mirrors.  Any Cholesky vectors (the scheme uses only the
+pair exchange (pq|rs) = (rs|pq)); ragged shapes across the 32-wide pair
+tiles of the combination pass, the 128/160-row and 64-row remainder tiles of
+the contraction, and blocks of several sizes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2310_04559_amd.inputs import CONFIGS, integer_inputs, make_inputs, random_general, seed_for
+from tests.gpu_common import TOL, announce, dev, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair_symmetric(t):
+    return 0.5 * (t + t.transpose(1, 0, 3, 2))
+
+
+def run(native, L, t, R0, precision, **kw):
+    R = dev(R0)
+    native.cc_ladder_residual(dev(L), dev(t), R, precision,
+                              opts=native.make_opts(pair_symmetric=True, plus_minus=True, **kw))
+    torch.cuda.synchronize()
+    return host(R)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (4, 44, 131, 13),
+                                           (3, 130, 17, 40), (2, 3, 2, 0), (16, 64, 200, 1),
+                                           (1, 33, 9, 0), (7, 1, 4, 0), (23, 65, 50, 30)])
+def test_plus_minus_general_vectors(gpu_lib, o, v, P, a_block, precision):
+    announce("forward-pm", o, v, P, "a_block", a_block, "precision", precision)
+    L, t, _ = random_general(o, v, P, 1300 + o + v)
+    t = _pair_symmetric(t)
+    R0 = np.random.default_rng(10).standard_normal(t.shape)
+    inc = oracle.ladder_forward(L, t)
+    got = run(gpu_lib, L, t, R0, precision, a_block=a_block)
+    err = rel_fro(got - R0, inc)
+    print(f"CASE forward-pm error {err:.2e}", flush=True)
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plus_minus_integer_exact(gpu_lib, precision):
+    # integer vectors and pair-symmetric integer amplitudes: every sum, the
+    # halves and the mirrored additions are exact
+    announce("forward-pm-int", precision)
+    L, t = integer_inputs(4, 11, 5, 79)
+    t = t + t.transpose(1, 0, 3, 2)
+    ref = oracle.ladder_forward(L, t)
+    got = run(gpu_lib, L, t, np.zeros_like(t), precision, a_block=4)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plus_minus_exchange(gpu_lib, precision):
+    # the exchange partner's amplitudes combine to t+ and -t-
+    announce("forward-pm-exchange", precision)
+    L, t, _ = random_general(9, 37, 101, 45)
+    t = _pair_symmetric(t)
+    inc = oracle.exchange_forward(L, t)
+    got = run(gpu_lib, L, t, np.zeros_like(t), precision, a_block=7, exchange=True)
+    assert rel_fro(got, inc) < TOL[precision]
+
+
+def test_plus_minus_c2_workload_whole_tensor(gpu_lib):
+    name = "o20_v180_P600"
+    o, v, P = CONFIGS[name]
+    announce("forward-pm", name)
+    inp = make_inputs(o, v, P, seed_for(name))
+    ref = oracle.ladder_forward(inp.L_vv, inp.t)
+    for precision in (0, 1):
+        got = run(gpu_lib, inp.L_vv, inp.t, np.zeros_like(inp.t), precision)
+        err = rel_fro(got, ref)
+        print(f"CASE forward-pm {name} precision {precision} error {err:.2e}", flush=True)
+        assert err < TOL[precision]
+
+
+def test_plus_minus_rejections(gpu_lib):
+    announce("forward-pm-rejections")
+    L, t, _ = random_general(3, 10, 4, 46)
+    R = torch.zeros(t.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_residual(dev(L), dev(t), R, 0, opts=gpu_lib.make_opts(plus_minus=True))
+    assert e.value.code == gpu_lib.CC_LADDER_EINVAL
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_residual(dev(L), dev(_pair_symmetric(t)), R, 2,
+                                   opts=gpu_lib.make_opts(pair_symmetric=True, plus_minus=True))
+    assert e.value.code == gpu_lib.CC_LADDER_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert float(R.abs().max()) == 0.0

@@ -24,7 +24,7 @@ SPLIT = 2
 TOL_MODEL_EXACT = 1e-12
 TOL_MODEL_MERGED = 2e-10
 # Two slices (hi/lo): the kernel sums the products in float32 over chunks of
-# 128 and the model in float64; that rounding stays near 1e-7, while a missing
+# 256 and the model in float64; that rounding stays near 1e-7, while a missing
 # hi*lo product moves the result by about 2^-9.
 TOL_MODEL_HILO = 2e-6
 
