@@ -178,6 +178,33 @@ int cc_ladder_residual(int o, int v, int P,
                        const double* L, const double* t, double* R,
                        int precision, hipStream_t stream, const cc_ladder_opts* opts);
 
+/* Size of the static scratch of cc_ladder_residual_noalloc (bytes per device). */
+#define CC_LADDER_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/*
+ * cc_ladder_residual for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, result and kernels as cc_ladder_residual, but
+ * the scratch is a static device array of CC_LADDER_NOALLOC_SCRATCH_BYTES
+ * (256 MiB) that every device the library runs on holds until the process
+ * ends; the call makes no hipMalloc/hipFree and no other allocating call.
+ * Its device address is looked up once per device, on the first call there.
+ * - The plan is sized to that array (or to opts->hbm_budget when smaller):
+ *   CC_LADDER_ENOMEM when not even a one-virtual block fits it (for float64,
+ *   v^3 * 8 bytes must be below 256 MiB, i.e. v <= 322; query beforehand with
+ *   cc_ladder_workspace_query(..., hbm_budget = CC_LADDER_NOALLOC_SCRATCH_BYTES)).
+ * - opts->workspace must be NULL and workspace_bytes 0, and the
+ *   CC_LADDER_CHECK_SYMMETRY flag (which reads a result back to the host) is
+ *   not accepted: CC_LADDER_EINVAL.
+ * - Every call on one device shares that device's array and leaves its
+ *   contents behind; each call rewrites what it reads, so no state carries
+ *   over.  Calls that overlap in time on one device (different streams, or
+ *   host threads enqueueing concurrently) race on the array: serialise them.
+ */
+int cc_ladder_residual_noalloc(int o, int v, int P,
+                               const double* L, const double* t, double* R,
+                               int precision, hipStream_t stream, const cc_ladder_opts* opts);
+
 /*
  * Adjoint of the ladder term for Loss = sum lam[i][j][a][b] R[i][j][a][b]
  * (lam = dLoss/dR, any values, pair symmetry not assumed):

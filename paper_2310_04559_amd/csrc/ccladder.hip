@@ -1116,6 +1116,64 @@ extern "C" int cc_ladder_residual(int o, int v, int P, const double* L, const do
   return residual_body(pl, L, t, R, precision, ws.base, opts, stream);
 }
 
+namespace ccl {
+namespace {
+
+// Scratch of cc_ladder_residual_noalloc.  Each device holds its own copy of
+// this array from the library's load until the process ends.  In host code the
+// name is a host-side stand-in, never a device address: the device address
+// comes from hipGetSymbolAddress, once per device, and only that pointer is
+// handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CC_LADDER_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[64];  // device address of `scratch` per device, null until looked up
+
+// The current device's copy of `scratch` (looked up on its first use there).
+int noalloc_scratch(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CC_LADDER_ENODEV;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return CC_LADDER_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CC_LADDER_OK;
+}
+
+}  // namespace
+}  // namespace ccl
+
+extern "C" int cc_ladder_residual_noalloc(int o, int v, int P, const double* L, const double* t,
+                                          double* R, int precision, hipStream_t stream,
+                                          const cc_ladder_opts* opts) {
+  Operand ops[3];
+  int rc = check_residual_args(o, v, P, L, t, R, precision, opts, ops);
+  if (rc) return rc;
+  // the scratch is the static array: no caller workspace, and no flag whose
+  // work reads a result back to the host
+  if (opts && (opts->workspace || opts->workspace_bytes ||
+               (opts->flags & CC_LADDER_CHECK_SYMMETRY)))
+    return CC_LADDER_EINVAL;
+  const size_t cap = CC_LADDER_NOALLOC_SCRATCH_BYTES;
+  const size_t budget = (opts && opts->hbm_budget && opts->hbm_budget < cap) ? opts->hbm_budget : cap;
+  Plan pl;
+  rc = make_plan(o, v, P, precision, 0, budget, opts, &pl);
+  if (rc) return rc;
+  if (pl.bytes > cap) return CC_LADDER_ENOMEM;
+  rc = check_device();
+  if (rc) return rc;
+  char* base = nullptr;
+  rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  return residual_body(pl, L, t, R, precision, base, opts, stream);
+}
+
 extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const double* t,
                                   const double* lam, double* dL, double* dt, int precision,
                                   hipStream_t stream, const cc_ladder_opts* opts) {

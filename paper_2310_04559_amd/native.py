@@ -24,13 +24,15 @@ PRECISIONS = {"fp64": CC_LADDER_FP64, "fp32": CC_LADDER_FP32, "split_bf16": CC_L
               "split_int8": CC_LADDER_SPLIT_INT8}
 
 CC_LADDER_OK = 0
+# static scratch of cc_ladder_residual_noalloc, bytes per device
+CC_LADDER_NOALLOC_SCRATCH_BYTES = 256 << 20
 CC_LADDER_EINVAL = -1
 CC_LADDER_ENOMEM = -2
 CC_LADDER_ENODEV = -3
 CC_LADDER_EHIP = -4
 CC_LADDER_EUNSUPPORTED = -5
 
-EXPORTS = ("cc_ladder_residual", "cc_ladder_backward", "cc_ladder_reduce",
+EXPORTS = ("cc_ladder_residual", "cc_ladder_residual_noalloc", "cc_ladder_backward", "cc_ladder_reduce",
            "cc_ladder_workspace_query", "cc_ladder_strerror", "cc_intermediate_ijkl",
            "cc_intermediate_ijbk", "cc_intermediate_workspace_query", "cc_hole_ladder")
 
@@ -87,6 +89,8 @@ def load():
     opts_p = ctypes.POINTER(CcLadderOpts)
     lib.cc_ladder_residual.argtypes = [i, i, i, p, p, p, i, p, opts_p]
     lib.cc_ladder_residual.restype = i
+    lib.cc_ladder_residual_noalloc.argtypes = [i, i, i, p, p, p, i, p, opts_p]
+    lib.cc_ladder_residual_noalloc.restype = i
     lib.cc_ladder_backward.argtypes = [i, i, i, p, p, p, p, p, i, p, opts_p]
     lib.cc_ladder_backward.restype = i
     lib.cc_ladder_reduce.argtypes = [i, i, p, p, p, p]
@@ -207,6 +211,22 @@ def cc_ladder_residual(L: torch.Tensor, t: torch.Tensor, R: torch.Tensor, precis
         rc = lib.cc_ladder_residual(o, v, P, pL, pt, pR, _prec(precision),
                                     _stream(R.device, stream), _opts_ref(opts))
     _check(rc, "cc_ladder_residual")
+    return R
+
+
+def cc_ladder_residual_noalloc(L: torch.Tensor, t: torch.Tensor, R: torch.Tensor, precision=0,
+                               stream=None, opts: Optional[CcLadderOpts] = None) -> torch.Tensor:
+    """cc_ladder_residual with the library's static scratch (no device allocation); returns R."""
+    lib = load()
+    P, v, _ = L.shape
+    o = t.shape[0]
+    pL = _dev_f64(L, "L", (P, v, v))
+    pt = _dev_f64(t, "t", (o, o, v, v))
+    pR = _dev_f64(R, "R", (o, o, v, v))
+    with torch.cuda.device(R.device):
+        rc = lib.cc_ladder_residual_noalloc(o, v, P, pL, pt, pR, _prec(precision),
+                                            _stream(R.device, stream), _opts_ref(opts))
+    _check(rc, "cc_ladder_residual_noalloc")
     return R
 
 

@@ -431,3 +431,32 @@ def test_planner_split_int8_footprint(native):
     with pytest.raises(native.LadderError) as e:
         native.cc_ladder_workspace_query(o, v, P, "split_int8", backward=True)
     assert e.value.code == native.CC_LADDER_EUNSUPPORTED
+
+
+def test_noalloc_host_checks(native):
+    import torch
+
+    lib = native.load()
+    # one float64 virtual at v = 330 needs 330^3 * 8 bytes, beyond the static
+    # scratch: rejected before any device call
+    assert lib.cc_ladder_residual_noalloc(1, 330, 2, 1 << 24, 1 << 34, 1 << 36, 0, None,
+                                          None) == native.CC_LADDER_ENOMEM
+    nbytes, _ = native.cc_ladder_workspace_query(
+        1, 322, 2, "fp64", hbm_budget=native.CC_LADDER_NOALLOC_SCRATCH_BYTES)
+    assert nbytes <= native.CC_LADDER_NOALLOC_SCRATCH_BYTES
+    # a caller workspace, or the symmetry check's read-back, is not accepted
+    o = _opts_at(native, 1 << 40, 1 << 20)
+    assert lib.cc_ladder_residual_noalloc(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None,
+                                          ctypes.byref(o)) == native.CC_LADDER_EINVAL
+    o = native.make_opts(pair_symmetric=True, check_symmetry=True)
+    assert lib.cc_ladder_residual_noalloc(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None,
+                                          ctypes.byref(o)) == native.CC_LADDER_EINVAL
+    # argument checks as the allocating entry point
+    assert lib.cc_ladder_residual_noalloc(2, 4, 2, None, 1 << 26, 1 << 28, 0, None,
+                                          None) == native.CC_LADDER_EINVAL
+    R = 1 << 20
+    assert lib.cc_ladder_residual_noalloc(2, 4, 2, 1 << 24, R + 8, R, 0, None,
+                                          None) == native.CC_LADDER_EINVAL
+    if not torch.cuda.is_available():
+        assert lib.cc_ladder_residual_noalloc(2, 4, 2, 1 << 24, 1 << 26, 1 << 28, 0, None,
+                                              None) == native.CC_LADDER_ENODEV
