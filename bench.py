@@ -103,7 +103,7 @@ def executed_fraction(form, v, o=1, P=1):
     return (b + c) / (2.0 * (P + o * o) * float(v) ** 4)
 KERNEL_SRC = [os.path.join(ROOT, "paper_2310_04559_amd", "csrc", f)
               for f in ("gemm.hpp", "gemm_direct.hpp", "ccladder.hip", "split.hip", "split.hpp",
-                        "plan.cpp", "plan.h")]
+                        "split_i8.hip", "plan.cpp", "plan.h")]
 
 
 def log(*a):
@@ -538,6 +538,9 @@ def main():
                                        "fp64_pm,fp32_pm,split_bf16_pairsym,split_int8_pairsym,"
                                        "fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--budget-gib", type=float, default=64.0,
+                    help="scratch budget of the timed forms: at most this many GiB, and at most "
+                         "half the free device memory")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-intermediates", action="store_true")
     ap.add_argument("--large", action="store_true",
@@ -594,7 +597,7 @@ def main():
     R = torch.zeros_like(t)
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
     free, _ = torch.cuda.mem_get_info()
-    ws_bytes = int(min(free // 2, 64 << 30))
+    ws_bytes = int(min(free // 2, args.budget_gib * (1 << 30)))
     flops = 2.0 * (P + o * o) * float(v) ** 4
 
     pairs = sampled_pairs(v, 24, 3)

@@ -705,8 +705,10 @@ int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
-  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
-    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+  for (int blk = 0; blk < pl.nblocks; ++blk) {
+    int a0, na;
+    block_range(pl, blk, &a0, &na);
+    if (na <= 0) continue;
     if (pl.pairsym) {
       // packed rows (a,b), a in the block, b >= a: columns (b,d) from b = a0 on
       const long long off = (long long)a0 * v;
@@ -757,8 +759,10 @@ int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr
   const int mp = o * (o + 1) / 2, mm = o * (o - 1) / 2;
   const int kp = static_cast<int>((long long)v * (v + 1) / 2);
   const int km = static_cast<int>((long long)v * (v - 1) / 2);
-  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
-    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+  for (int blk = 0; blk < pl.nblocks; ++blk) {
+    int a0, na;
+    block_range(pl, blk, &a0, &na);
+    if (na <= 0) continue;
     const long long off = (long long)a0 * v;
     const long long np = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
     const long long nm = np - na;
@@ -801,8 +805,10 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     const int rc = fill_zero(Bacc, (long long)o * o * v2, s);
     if (rc) return rc;
   }
-  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
-    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+  for (int blk = 0; blk < pl.nblocks; ++blk) {
+    int a0, na;
+    block_range(pl, blk, &a0, &na);
+    if (na <= 0) continue;
     const long long off = (long long)a0 * v;
     int rc;
     if (sym) {

@@ -112,24 +112,63 @@ int check_workspace(const cc_ladder_opts* opts, size_t plan_bytes, const Operand
   return CC_LADDER_OK;
 }
 
+int pair_block_start(int v, int nb, int k) {
+  if (k <= 0) return 0;
+  if (k >= nb) return v;
+  const long long target = (long long)k * ((long long)v * (v + 1) / 2);
+  int lo = 0, hi = v;  // smallest a with pair_prefix(a) * nb >= target
+  while (lo < hi) {
+    const int mid = lo + (hi - lo) / 2;
+    if (pair_prefix(mid, v) * nb >= target) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+void block_range(const Plan& pl, int blk, int* a0, int* na) {
+  if (pl.balanced) {
+    *a0 = pair_block_start(pl.v, pl.nblocks, blk);
+    *na = pair_block_start(pl.v, pl.nblocks, blk + 1) - *a0;
+    return;
+  }
+  *a0 = blk * pl.n_a;
+  *na = (pl.v - *a0) < pl.n_a ? (pl.v - *a0) : pl.n_a;
+}
+
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int depth, int k_chunk, unsigned flags, Plan* plan) {
+                int slices, int depth, int k_chunk, unsigned flags, Plan* plan, int nb) {
   const int pairsym = (flags & CC_LADDER_PAIR_SYMMETRIC) ? 1 : 0;
-  if (n_a < 1 || n_a > v) return CC_LADDER_EINVAL;
   Plan p;
+  // packed forward in pair-balanced blocks: the widest block sizes the tile
+  // table, the block with the most pairs (a <= b, and a < b) the buffers
+  size_t npk_max = 0, nstrict_max = 0;
+  if (nb > 0 && pairsym && !backward) {
+    if (nb > v) return CC_LADDER_EINVAL;
+    p.balanced = 1;
+    n_a = 0;
+    for (int k = 0; k < nb; ++k) {
+      const int a0 = pair_block_start(v, nb, k), a1 = pair_block_start(v, nb, k + 1);
+      const size_t np = static_cast<size_t>(pair_prefix(a1, v) - pair_prefix(a0, v));
+      n_a = (a1 - a0) > n_a ? (a1 - a0) : n_a;
+      npk_max = np > npk_max ? np : npk_max;
+      const size_t ns = np - static_cast<size_t>(a1 - a0);
+      nstrict_max = ns > nstrict_max ? ns : nstrict_max;
+    }
+  }
+  if (n_a < 1 || n_a > v) return CC_LADDER_EINVAL;
   p.o = o; p.v = v; p.P = P;
   p.precision = precision;
   p.backward = backward ? 1 : 0;
   p.n_a = n_a;
-  p.nblocks = (v + n_a - 1) / n_a;
+  p.nblocks = p.balanced ? nb : (v + n_a - 1) / n_a;
   const size_t v2 = static_cast<size_t>(v) * v;
   const size_t o2 = static_cast<size_t>(o) * o;
   p.pairsym = (pairsym && !backward) ? 1 : 0;
   p.pairsym_adj = (pairsym && backward) ? 1 : 0;
   // entries of one integral block: n_a*v rows (a,b); packed rows a <= b when the
-  // amplitudes are pair-symmetric (the first block holds the most).  The adjoint's
-  // W block always has n_a*v rows.
-  const size_t npk = static_cast<size_t>(pair_prefix(n_a, v));
+  // amplitudes are pair-symmetric (with equal virtual counts the first block
+  // holds the most).  The adjoint's W block always has n_a*v rows.
+  const size_t npk = p.balanced ? npk_max : static_cast<size_t>(pair_prefix(n_a, v));
+  p.npk = p.pairsym ? static_cast<long long>(npk) : 0;
   const size_t npk_ld = (npk + 3) / 4 * 4;  // row stride of the adjoint's gathered lam
   const size_t rows = (p.pairsym || p.pairsym_adj) ? npk : static_cast<size_t>(n_a) * v;
   const size_t blk = rows * v2;
@@ -153,8 +192,8 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
     p.ldp = static_cast<long long>((kp + 3) / 4 * 4);
     p.ldm = static_cast<long long>((km + 3) / 4 * 4);
     const size_t mp = static_cast<size_t>(o) * (o + 1) / 2, mm = static_cast<size_t>(o) * (o - 1) / 2;
-    // packed rows of the largest (first) block: a <= b, and a < b
-    const size_t np = npk, nm = npk - static_cast<size_t>(n_a);
+    // packed rows of the largest block: a <= b, and a < b
+    const size_t np = npk, nm = p.balanced ? nstrict_max : npk - static_cast<size_t>(n_a);
     p.off_Tp = take(&cur, mp * p.ldp * es);
     p.off_Tm = take(&cur, mm * p.ldm * es);
     p.off_Vp = take(&cur, np * p.ldp * es);
@@ -295,7 +334,42 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   const int depth = opts ? opts->split_depth : 0;
   const unsigned flags = opts ? opts->flags : 0u;
   const int k_chunk = opts ? opts->k_chunk : 0;
-  return search_block(v, budget, opts ? opts->a_block : 0, [&](int n_a, Plan* p) {
+  const int fixed = opts ? opts->a_block : 0;
+  if ((flags & CC_LADDER_PAIR_SYMMETRIC) && !backward && fixed == 0) {
+    // packed forward: blocks of about equal pair counts (equal virtual counts
+    // would leave the last blocks, whose virtuals pair with few others, a
+    // small fraction of the first one's work); the fewest blocks that fit
+    auto fits = [&](int nb, Plan* p) {
+      const int rc = layout_plan(o, v, P, precision, backward, 0, slices, depth, k_chunk, flags, p,
+                                 nb);
+      if (rc) return rc;
+      return (budget && p->bytes > budget) ? CC_LADDER_ENOMEM : CC_LADDER_OK;
+    };
+    Plan best;
+    int rc = fits(v, &best);
+    if (rc) return rc;
+    int lo = 1, hi = v;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      Plan trial;
+      rc = fits(mid, &trial);
+      if (rc == CC_LADDER_OK) {
+        hi = mid;
+        best = trial;
+      } else if (rc == CC_LADDER_ENOMEM) {
+        lo = mid + 1;
+      } else {
+        return rc;
+      }
+    }
+    if (best.nblocks != lo) {
+      rc = fits(lo, &best);
+      if (rc) return rc;
+    }
+    *plan = best;
+    return CC_LADDER_OK;
+  }
+  return search_block(v, budget, fixed, [&](int n_a, Plan* p) {
     return layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, flags, p);
   }, plan);
 }

@@ -53,16 +53,30 @@ struct Plan {
   size_t off_Vs = 0;    // bf16 slices of the integral block
   size_t off_Vexp = 0;  // exponents of the integral block's digit rows, per (row, chunk)
   size_t off_tiles = 0; // packed build: first tile of every tile row (int32, tiles_m + 1)
+  int balanced = 0;     // packed forward: nblocks blocks of about equal pair counts (n_a is
+                        // then the widest block's virtual count)
+  long long npk = 0;    // packed forward: packed rows (a,b) of the block that has the most
   size_t bytes = 0;     // total scratch
 };
 
-// Fills `plan` for a block size of n_a (1 <= n_a <= v).  Returns 0 or CC_LADDER_EINVAL.
+// Fills `plan` for a block size of n_a (1 <= n_a <= v), or, when nb > 0 and the
+// plan is a packed (pair-symmetric) forward, for nb pair-balanced blocks (n_a
+// ignored).  Returns 0, CC_LADDER_EINVAL or CC_LADDER_EUNSUPPORTED.
 int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
-                int slices, int depth, int k_chunk, unsigned flags, Plan* plan);
+                int slices, int depth, int k_chunk, unsigned flags, Plan* plan, int nb = 0);
 
 // Packed integral rows (a,b), a <= b, ordered by a then b: rows of virtuals
 // [0, a) come first.  pair_prefix(a, v) = sum_{a' < a} (v - a').
 inline long long pair_prefix(long long a, long long v) { return a * v - a * (a - 1) / 2; }
+
+// First virtual of block k of nb blocks with about equal pair counts: the
+// smallest a with pair_prefix(a, v) * nb >= k * v(v+1)/2 (0 for k = 0, v for k = nb).
+int pair_block_start(int v, int nb, int k);
+
+// Virtual range [*a0, *a0 + *na) of block `blk` of a plan: equal virtual
+// counts (n_a, the last block the remainder), or equal pair counts for a
+// balanced plan.  *na may be 0 for a balanced plan (an empty block).
+void block_range(const Plan& pl, int blk, int* a0, int* na);
 
 // Picks n_a (honouring opts->a_block when set) so that plan.bytes <= budget
 // (budget 0 = unlimited).  Returns 0, CC_LADDER_EINVAL or CC_LADDER_ENOMEM.

@@ -300,13 +300,12 @@ __device__ __forceinline__ void wait_vm(int n) {
 // products of a sub-tile over two waves, or one wave per SIMD, the same or
 // slower.  Raising the wave priority over the product loop gains 2-3%; the same
 // in the float64 and float32 contraction loses 2%.
-template <int S, int D, int EPI, int WAVES, int BM, int STAGES, int NACC>
+template <int S, int D, int EPI, int WAVES, int BM, int STAGES, int NACC, int NJ = 2>
 __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) {
   // the contraction's operands carry chunk exponents
   constexpr bool CE = EPI == EPI_ACC || EPI == EPI_PAIR;
   constexpr int NG = S + D - 1;            // anti-diagonals kept
-  constexpr int NJ = 2;                    // column blocks per wave
-  constexpr int WCOLS = kSBN / (16 * NJ);  // waves along N (4)
+  constexpr int WCOLS = kSBN / (16 * NJ);  // waves along N (NJ column blocks per wave)
   constexpr int MI = BM / (16 * (WAVES / WCOLS));  // row blocks per wave
   constexpr int A_BYTES = S * BM * kRowBytes;
   constexpr int B_BYTES = S * kSBN * kRowBytes;
@@ -327,21 +326,33 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = (wave / WCOLS) * (16 * MI);
   const int wn = (wave % WCOLS) * (16 * NJ);
-  int tm, tn;
-  if (EPI == EPI_PACK) {
-    // compact grid over the tiles on or above the a = b diagonal
-    const int id = blockIdx.x;
-    int lo = 0, hi = g.tiles_m - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (g.row_tiles[mid] <= id) lo = mid; else hi = mid - 1;
+  // Tiles of linear ids it * G + xcd_linear(b) for workgroup b of G, so each
+  // XCD walks contiguous runs of the tile order.  With two stages the kernel is
+  // launched persistent (one workgroup per compute unit) and loads the first
+  // K-step of its next tile while the current tile drains; otherwise G covers
+  // every tile once.
+  const int G = gridDim.x;
+  const int ntiles = (EPI == EPI_PACK) ? g.row_tiles[g.tiles_m] : g.tiles_m * g.tiles_n;
+  const int lin0 = xcd_linear(blockIdx.x, G);
+  auto coords = [&](int lin, int& m0, int& n0) {
+    int tm, tn;
+    if (EPI == EPI_PACK) {
+      // compact grid over the tiles on or above the a = b diagonal
+      int lo = 0, hi = g.tiles_m - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.row_tiles[mid] <= lin) lo = mid; else hi = mid - 1;
+      }
+      tm = lo;
+      tn = pack_first_tile(tm, BM, kSBN, g.v) + (lin - g.row_tiles[tm]);
+    } else {
+      tile_from_linear(lin, ntiles, g.tiles_m, g.group_m, tm, tn);
     }
-    tm = lo;
-    tn = pack_first_tile(tm, BM, kSBN, g.v) + (id - g.row_tiles[tm]);
-  } else {
-    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
-  }
-  const int m0 = tm * BM, n0 = tn * kSBN;
+    // uniform over the workgroup: kept in scalar registers
+    m0 = __builtin_amdgcn_readfirstlane(tm * BM);
+    n0 = __builtin_amdgcn_readfirstlane(tn * kSBN);
+  };
+  if (lin0 >= ntiles) return;
 
   const int lrow = lane >> 2;
   const int lchunk = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
@@ -350,10 +361,11 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   // a wave loads slab after slab of the same 16 rows (consecutive slices), so
   // its instructions of a K-step cover whole lines
   // stage rings: A's STAGES stages, then B's
-  auto a_stage = [&](int kt) { return lds + (kt % STAGES) * A_BYTES; };
-  auto b_stage = [&](int kt) { return lds + STAGES * A_BYTES + (kt % STAGES) * B_BYTES; };
-  auto issue_a = [&](int kt) {
-    unsigned char* st = a_stage(kt);
+  // stages by global step gs (steps counted over all tiles of this workgroup)
+  auto a_stage = [&](int gs) { return lds + (gs % STAGES) * A_BYTES; };
+  auto b_stage = [&](int gs) { return lds + STAGES * A_BYTES + (gs % STAGES) * B_BYTES; };
+  auto issue_a = [&](int m0, int kt, int gs) {
+    unsigned char* st = a_stage(gs);
     const long long ko = (long long)kt * (S * kSBK);
 #pragma unroll
     for (int j = 0; j < NLA; ++j) {
@@ -363,8 +375,8 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
           (lds_void_t*)(st + (s * BM + 16 * r) * kRowBytes), 16, 0, 0);
     }
   };
-  auto issue_b = [&](int kt) {
-    unsigned char* st = b_stage(kt);
+  auto issue_b = [&](int n0, int kt, int gs) {
+    unsigned char* st = b_stage(gs);
     const long long ko = (long long)kt * (S * kSBK);
 #pragma unroll
     for (int j = 0; j < NLB; ++j) {
@@ -375,21 +387,30 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     }
   };
 
+  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
+  const int nk = g.Kp / kSBK;
+  if (nk <= 0) return;
+  const long long v = g.v;
+
+  int lin = lin0, m0, n0;
+  coords(lin, m0, n0);
+  int gbase = 0;  // global step of this tile's first K-step
+  // issue order: per K-step A then B; the wait counts below follow from it
+#pragma unroll
+  for (int k = 0; k < AHEAD; ++k) {
+    if (k < nk) issue_a(m0, k, k);
+    if (k < nk) issue_b(n0, k, k);
+  }
+  for (;;) {
+  const int lin_next = lin + G;
+  const bool more = lin_next < ntiles;  // only in a persistent (two-stage) launch
+  int m0n = 0, n0n = 0;
+  if (more) coords(lin_next, m0n, n0n);
   f64x4 acc64[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc64[i][j] = f64x4{0, 0, 0, 0};
-
-  const int frag_off = (lane & 15) * kRowBytes + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
-  const int nk = g.Kp / kSBK;
-
-  // issue order: per K-step A then B; the wait counts below follow from it
-#pragma unroll
-  for (int k = 0; k < AHEAD; ++k) {
-    if (k < nk) issue_a(k);
-    if (k < nk) issue_b(k);
-  }
   constexpr int kChunkSteps = chunk_steps<S>();
   for (int k0 = 0; k0 < nk; k0 += kChunkSteps) {
     // one chunk: float32 sums per anti-diagonal g = p + q (the last accumulator
@@ -409,12 +430,17 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
         const int later = (nk - 1 - kt) < (AHEAD - 1) ? (nk - 1 - kt) : (AHEAD - 1);
         wait_vm(later * LOADS);
         __builtin_amdgcn_s_barrier();
-        if (kt + AHEAD < nk) {
-          issue_a(kt + AHEAD);
-          issue_b(kt + AHEAD);
+        {
+          // this tile's step kt + AHEAD, or with two stages the next tile's
+          // first step, into the stage this tile is done with
+          const bool same = kt + AHEAD < nk;
+          if (same || (STAGES == 2 && more)) {
+            issue_a(same ? m0 : m0n, same ? kt + AHEAD : 0, gbase + kt + AHEAD);
+            issue_b(same ? n0 : n0n, same ? kt + AHEAD : 0, gbase + kt + AHEAD);
+          }
         }
-        const unsigned char* sta = a_stage(kt);
-        const unsigned char* stb = b_stage(kt);
+        const unsigned char* sta = a_stage(gbase + kt);
+        const unsigned char* stb = b_stage(gbase + kt);
         bf16x8 fb[S][NJ];
 #pragma unroll
         for (int q = 0; q < S; ++q)
@@ -489,7 +515,6 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     }
   }
 
-  const long long v = g.v;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int n = n0 + wn + 16 * j + (lane & 15);
@@ -538,6 +563,12 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
         }
       }
   }
+  if (!more) break;
+  lin = lin_next;
+  m0 = m0n;
+  n0 = n0n;
+  gbase += nk;
+  }
 }
 
 // Tile-row offsets of the packed build's compact grid (one thread; a few
@@ -562,11 +593,26 @@ __global__ void split_pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n,
 template <int S, int D>
 struct SplitShape {
   static constexpr int NG = S + D - 1;
+  static constexpr int NJ = 2;  // column blocks per wave
   static constexpr int W = S == 3 ? 4 : 8;
   static constexpr int BM = S == 3 ? 64 : 128;
   static constexpr int STAGES = S == 4 ? 2 : (S == 2 ? 4 : 3);
   static constexpr int NACC = S == 4 && NG > 3 ? 3 : NG;
 };
+
+// Compute units of the current device (queried once per device).
+int split_compute_units() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
 
 // Rows of a 128-row-tile product that a launch of 64-row tiles takes over (0 =
 // none): the remainder, when the last tile row would be at most half full and
@@ -626,7 +672,9 @@ int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
                        const_cast<int*>(a.row_tiles), a.tiles_m, a.tiles_n, a.v, Sh::BM);
     grid = needed;
   }
-  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, Sh::W, Sh::BM, Sh::STAGES, Sh::NACC>),
+  // two-stage shapes run persistent: one workgroup per compute unit
+  if (Sh::STAGES == 2 && grid > split_compute_units()) grid = split_compute_units();
+  hipLaunchKernelGGL((split_gemm_kernel<S, D, EPI, Sh::W, Sh::BM, Sh::STAGES, Sh::NACC, Sh::NJ>),
                      dim3(static_cast<unsigned>(grid)), dim3(64 * Sh::W), 0, s, a);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
@@ -659,7 +707,7 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
   const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
   const SliceDims dt = slice_dims((long long)o * o, static_cast<int>(v2));
   // integral rows of the largest block: n_a*v, or its packed rows a <= b
-  const SliceDims dV = slice_dims(pl.pairsym ? pair_prefix(pl.n_a, v) : (long long)pl.n_a * v,
+  const SliceDims dV = slice_dims(pl.pairsym ? pl.npk : (long long)pl.n_a * v,
                                   static_cast<int>(v2));
   __bf16* Ls = reinterpret_cast<__bf16*>(ws + pl.off_L);
   int* Le = reinterpret_cast<int*>(ws + pl.off_Lexp);
@@ -675,8 +723,10 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
   if (!rc) rc = slice_kc<S>(t, v2, o * o, static_cast<int>(v2), dt, ts, te, s);
   tr(CC_LADDER_PHASE_PREP, 0, 1);
   if (rc) return rc;
-  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
-    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+  for (int blk = 0; blk < pl.nblocks; ++blk) {
+    int a0, na;
+    block_range(pl, blk, &a0, &na);
+    if (na <= 0) continue;
     const long long r0 = (long long)a0 * v;  // first (a,c) row of this block
     if (pl.pairsym) {
       // packed rows (a,b), b >= a: columns (b,d) from b = a0 on

@@ -41,6 +41,7 @@ constexpr int kIBK = 64;                      // K per stage: one int8 MFMA dept
 constexpr int kIRow = kIBK;                   // bytes of one digit row per K-step
 constexpr int kIChunkSteps = kI8Chunk / kIBK; // K-steps per exponent chunk and drain
 constexpr int kIBM = 128, kIBN = 128;         // workgroup tile
+constexpr int kIWaves = 8, kINJ = 2;          // waves per workgroup, 16-column blocks per wave
 
 // Exponent of a chunk whose largest magnitude is m: m < 2^e * 127/128.
 __device__ __forceinline__ int i8_exponent(double m) {
@@ -218,11 +219,11 @@ typedef __attribute__((address_space(3))) void lds_void_i8;
 // enter each MFMA with the same k order.  One int32 sum per anti-diagonal;
 // every kI8Chunk contracted indices (and at the end) the sums are scaled and
 // added to the output in float64.
-template <int S, int D, int EPI>
-__global__ __launch_bounds__(512, 1) void i8_gemm_kernel(I8Args g) {
+template <int S, int D, int EPI, int WAVES, int NJ>
+__global__ __launch_bounds__(64 * WAVES, 1) void i8_gemm_kernel(I8Args g) {
   constexpr bool CE = true;  // chunked exponents on both operands
   constexpr int NG = S + D - 1;  // anti-diagonals kept
-  constexpr int WAVES = 8, NJ = 2, WCOLS = kIBN / (16 * NJ), MI = kIBM / (16 * (WAVES / WCOLS));
+  constexpr int WCOLS = kIBN / (16 * NJ), MI = kIBM / (16 * (WAVES / WCOLS));
   constexpr int A_BYTES = S * kIBM * kIRow;
   constexpr int B_BYTES = S * kIBN * kIRow;
   constexpr int ASLABS = S * kIBM / 16, BSLABS = S * kIBN / 16;
@@ -239,31 +240,44 @@ __global__ __launch_bounds__(512, 1) void i8_gemm_kernel(I8Args g) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = (wave / WCOLS) * (16 * MI);
   const int wn = (wave % WCOLS) * (16 * NJ);
-  int tm, tn;
-  if (EPI == EPI_PACK) {
-    // compact grid over the tiles on or above the a = b diagonal
-    const int id = blockIdx.x;
-    int lo = 0, hi = g.tiles_m - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (g.row_tiles[mid] <= id) lo = mid; else hi = mid - 1;
+  // Persistent: workgroup b takes the tiles of linear ids it * G + xcd_linear(b)
+  // (G workgroups, one per compute unit), so each XCD walks contiguous runs of
+  // the tile order, and the first K-step of its next tile is loaded while the
+  // current tile drains (one workgroup fits a compute unit, so nothing else
+  // would hide that drain and the next tile's first loads).
+  const int G = gridDim.x;
+  const int ntiles = (EPI == EPI_PACK) ? g.row_tiles[g.tiles_m] : g.tiles_m * g.tiles_n;
+  const int lin0 = xcd_linear(blockIdx.x, G);
+  auto coords = [&](int lin, int& m0, int& n0) {
+    int tm, tn;
+    if (EPI == EPI_PACK) {
+      // compact grid over the tiles on or above the a = b diagonal
+      int lo = 0, hi = g.tiles_m - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.row_tiles[mid] <= lin) lo = mid; else hi = mid - 1;
+      }
+      tm = lo;
+      tn = pack_first_tile(tm, kIBM, kIBN, g.v) + (lin - g.row_tiles[tm]);
+    } else {
+      tile_from_linear(lin, ntiles, g.tiles_m, g.group_m, tm, tn);
     }
-    tm = lo;
-    tn = pack_first_tile(tm, kIBM, kIBN, g.v) + (id - g.row_tiles[tm]);
-  } else {
-    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
-  }
-  const int m0 = tm * kIBM, n0 = tn * kIBN;
+    // uniform over the workgroup: kept in scalar registers
+    m0 = __builtin_amdgcn_readfirstlane(tm * kIBM);
+    n0 = __builtin_amdgcn_readfirstlane(tn * kIBN);
+  };
+  if (lin0 >= ntiles) return;
 
   const int lrow = lane >> 2;
   const int lslot = (lane & 3) ^ ((lane >> 3) & 3);  // key (row >> 1) & 3
   const long long row_len = (long long)g.Kp * S;     // digit bytes of one row
   const long long loff = (long long)lrow * row_len + lslot * 16;
-  auto a_stage = [&](int kt) { return lds + (kt % STAGES) * A_BYTES; };
-  auto b_stage = [&](int kt) { return lds + STAGES * A_BYTES + (kt % STAGES) * B_BYTES; };
-  auto issue = [&](int kt) {
+  // stage of global step gs (steps counted over all tiles of this workgroup)
+  auto a_stage = [&](int gs) { return lds + (gs % STAGES) * A_BYTES; };
+  auto b_stage = [&](int gs) { return lds + STAGES * A_BYTES + (gs % STAGES) * B_BYTES; };
+  auto issue = [&](int m0, int n0, int kt, int gs) {
     const long long ko = (long long)kt * (S * kIBK);
-    unsigned char* sa = a_stage(kt);
+    unsigned char* sa = a_stage(gs);
 #pragma unroll
     for (int j = 0; j < NLA; ++j) {
       const int ai = wave * NLA + j, r = ai / S, s = ai % S;
@@ -271,7 +285,7 @@ __global__ __launch_bounds__(512, 1) void i8_gemm_kernel(I8Args g) {
           (const void*)(g.A + (long long)(m0 + 16 * r) * row_len + loff + ko + s * kIBK),
           (lds_void_i8*)(sa + (s * kIBM + 16 * r) * kIRow), 16, 0, 0);
     }
-    unsigned char* sb = b_stage(kt);
+    unsigned char* sb = b_stage(gs);
 #pragma unroll
     for (int j = 0; j < NLB; ++j) {
       const int bi = wave * NLB + j, r = bi / S, s = bi % S;
@@ -284,106 +298,128 @@ __global__ __launch_bounds__(512, 1) void i8_gemm_kernel(I8Args g) {
   const int frag_off = (lane & 15) * kIRow + (((lane >> 4) ^ ((lane >> 1) & 3)) * 16);
   const int nk = g.Kp / kIBK;
   const long long v = g.v;
+  if (nk <= 0) return;
 
-  if (nk > 0) issue(0);
-  for (int k0 = 0; k0 < nk; k0 += kIChunkSteps) {
-    const int k1 = (k0 + kIChunkSteps) < nk ? (k0 + kIChunkSteps) : nk;
-    i32x4 acc[NG][MI][NJ];
+  int lin = lin0, m0, n0;
+  coords(lin, m0, n0);
+  int gbase = 0;  // global step of this tile's first K-step
+  issue(m0, n0, 0, 0);
+  for (;;) {
+    const int lin_next = lin + G;
+    const bool more = lin_next < ntiles;
+    int m0n = 0, n0n = 0;
+    if (more) coords(lin_next, m0n, n0n);
+    for (int k0 = 0; k0 < nk; k0 += kIChunkSteps) {
+      const int k1 = (k0 + kIChunkSteps) < nk ? (k0 + kIChunkSteps) : nk;
+      i32x4 acc[NG][MI][NJ];
 #pragma unroll
-    for (int q = 0; q < NG; ++q)
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[q][i][j] = i32x4{0, 0, 0, 0};
-    for (int kt = k0; kt < k1; ++kt) {
-      // step kt's loads are the only ones in flight; once they land and every
-      // wave is past step kt-1, the other stage is free for step kt+1
-      i8_wait_vm0();
-      __builtin_amdgcn_s_barrier();
-      if (kt + 1 < nk) issue(kt + 1);
-      const unsigned char* sa = a_stage(kt);
-      const unsigned char* sb = b_stage(kt);
-      i32x4 fb[S][NJ];
-#pragma unroll
-      for (int q = 0; q < S; ++q)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          fb[q][j] = *reinterpret_cast<const i32x4*>(sb + (q * kIBN + wn + 16 * j) * kIRow + frag_off);
-      __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-      for (int p = 0; p < S; ++p) {
-        if (p >= NG) continue;
-        i32x4 fa[MI];
+      for (int q = 0; q < NG; ++q)
 #pragma unroll
         for (int i = 0; i < MI; ++i)
-          fa[i] = *reinterpret_cast<const i32x4*>(sa + (p * kIBM + wm + 16 * i) * kIRow + frag_off);
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-          if (p + q >= NG) continue;
+          for (int j = 0; j < NJ; ++j) acc[q][i][j] = i32x4{0, 0, 0, 0};
+      for (int kt = k0; kt < k1; ++kt) {
+        // step kt's loads are the only ones in flight; once they land and every
+        // wave is past the previous step, the other stage takes the next step
+        // (this tile's, or the next tile's first)
+        i8_wait_vm0();
+        __builtin_amdgcn_s_barrier();
+        {
+          const bool same = kt + 1 < nk;
+          if (same || more)
+            issue(same ? m0 : m0n, same ? n0 : n0n, same ? kt + 1 : 0, gbase + kt + 1);
+        }
+        const unsigned char* sa = a_stage(gbase + kt);
+        const unsigned char* sb = b_stage(gbase + kt);
+        i32x4 fb[S][NJ];
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            fb[q][j] = *reinterpret_cast<const i32x4*>(sb + (q * kIBN + wn + 16 * j) * kIRow + frag_off);
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          if (p >= NG) continue;
+          i32x4 fa[MI];
 #pragma unroll
           for (int i = 0; i < MI; ++i)
+            fa[i] = *reinterpret_cast<const i32x4*>(sa + (p * kIBM + wm + 16 * i) * kIRow + frag_off);
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-              acc[p + q][i][j] =
-                  __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[q][j], acc[p + q][i][j], 0, 0, 0);
-        }
-      }
-      __builtin_amdgcn_s_setprio(0);
-    }
-    // drain chunk c into the output: 2^(eA + eB - 14) sum_g 2^(-8g) acc_g
-    const int c = k0 / kIChunkSteps;
-    const bool first = k0 == 0;
+          for (int q = 0; q < S; ++q) {
+            if (p + q >= NG) continue;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int n = n0 + wn + 16 * j + (lane & 15);
-      if (n >= g.N) continue;
-      const int en = g.eb[(long long)c * g.eb_stride + n];
-      long long ncol = n;
-      int pa = 0, pb = 0;  // EPI_PACK: b - a0 and d; EPI_PAIR: a and b
-      if (EPI == EPI_PERM) {
-        const int y = n / g.v, d = n - y * g.v;
-        ncol = (long long)y * v * v + d;
-      } else if (EPI == EPI_PACK) {
-        pa = n / g.v;
-        pb = n - pa * g.v;
-      } else if (EPI == EPI_PAIR) {
-        const long long q = pair_prefix_d(g.a0, v) + n;
-        pa = pair_row(q, g.v);
-        pb = pa + static_cast<int>(q - pair_prefix_d(pa, v));
-      }
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-          if (m >= g.M) continue;
-          double u = 0.0;
-#pragma unroll
-          for (int q = NG - 1; q >= 0; --q)
-            u = fma(static_cast<double>(acc[q][i][j][r]), 1.0 / static_cast<double>(1ull << (8 * q)), u);
-          const double val = ldexp(u, g.ea[(long long)c * g.ea_stride + m] + en - 14);
-          double* C = g.C;
-          if (EPI == EPI_ACC) {
-            C[(long long)m * g.ldc + n] += val;
-          } else if (EPI == EPI_PERM) {
-            const int a = m / g.v, x = m - a * g.v;
-            double* dst = C + (long long)a * v * v * v + ncol + (long long)x * v;
-            *dst = first ? val : *dst + val;
-          } else if (EPI == EPI_PACK) {
-            const int al = m / g.v, cc = m - al * g.v;
-            if (pa < al) continue;
-            const long long prow = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (pa - al);
-            double* dst = C + prow * v * v + (long long)cc * v + pb;
-            *dst = first ? val : *dst + val;
-          } else {  // EPI_PAIR: R[i][j][a][b] and, for a != b, R[j][i][b][a]
-            C[(long long)m * g.ldc + (long long)pa * v + pb] += val;
-            if (pa != pb) {
-              const int ii = m / g.o, jj = m - ii * g.o;
-              C[(long long)(jj * g.o + ii) * g.ldc + (long long)pb * v + pa] += val;
-            }
+              for (int j = 0; j < NJ; ++j)
+                acc[p + q][i][j] =
+                    __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[q][j], acc[p + q][i][j], 0, 0, 0);
           }
         }
+        __builtin_amdgcn_s_setprio(0);
+      }
+      // drain chunk c into the output: 2^(eA + eB - 14) sum_g 2^(-8g) acc_g
+      const int c = k0 / kIChunkSteps;
+      const bool first = k0 == 0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        if (n >= g.N) continue;
+        const int en = g.eb[(long long)c * g.eb_stride + n];
+        long long ncol = n;
+        int pa = 0, pb = 0;  // EPI_PACK: b - a0 and d; EPI_PAIR: a and b
+        if (EPI == EPI_PERM) {
+          const int y = n / g.v, d = n - y * g.v;
+          ncol = (long long)y * v * v + d;
+        } else if (EPI == EPI_PACK) {
+          pa = n / g.v;
+          pb = n - pa * g.v;
+        } else if (EPI == EPI_PAIR) {
+          const long long q = pair_prefix_d(g.a0, v) + n;
+          pa = pair_row(q, g.v);
+          pb = pa + static_cast<int>(q - pair_prefix_d(pa, v));
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+            if (m >= g.M) continue;
+            double u = 0.0;
+#pragma unroll
+            for (int q = NG - 1; q >= 0; --q)
+              u = fma(static_cast<double>(acc[q][i][j][r]), 1.0 / static_cast<double>(1ull << (8 * q)),
+                      u);
+            const double val = ldexp(u, g.ea[(long long)c * g.ea_stride + m] + en - 14);
+            double* C = g.C;
+            if (EPI == EPI_ACC) {
+              C[(long long)m * g.ldc + n] += val;
+            } else if (EPI == EPI_PERM) {
+              const int a = m / g.v, x = m - a * g.v;
+              double* dst = C + (long long)a * v * v * v + ncol + (long long)x * v;
+              *dst = first ? val : *dst + val;
+            } else if (EPI == EPI_PACK) {
+              const int al = m / g.v, cc = m - al * g.v;
+              if (pa < al) continue;
+              const long long prow =
+                  pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (pa - al);
+              double* dst = C + prow * v * v + (long long)cc * v + pb;
+              *dst = first ? val : *dst + val;
+            } else {  // EPI_PAIR: R[i][j][a][b] and, for a != b, R[j][i][b][a]
+              C[(long long)m * g.ldc + (long long)pa * v + pb] += val;
+              if (pa != pb) {
+                const int ii = m / g.o, jj = m - ii * g.o;
+                C[(long long)(jj * g.o + ii) * g.ldc + (long long)pb * v + pa] += val;
+              }
+            }
+          }
+      }
     }
+    if (!more) break;
+    lin = lin_next;
+    m0 = m0n;
+    n0 = n0n;
+    gbase += nk;
   }
 }
 
@@ -397,6 +433,20 @@ __global__ void i8_pack_rows_kernel(int* row_tiles, int tiles_m, int tiles_n, in
     acc += first < tiles_n ? tiles_n - first : 0;
   }
   row_tiles[tiles_m] = acc;
+}
+
+// Compute units of the current device (queried once per device).
+int i8_compute_units() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
 }
 
 template <int S, int D, int EPI>
@@ -421,8 +471,10 @@ int launch_i8_gemm(const I8Args& a0, hipStream_t s) {
                        a.tiles_m, a.tiles_n, a.v);
     grid = needed;
   }
-  hipLaunchKernelGGL((i8_gemm_kernel<S, D, EPI>), dim3(static_cast<unsigned>(grid)), dim3(512), 0, s,
-                     a);
+  // one persistent workgroup per compute unit (or per tile, when fewer)
+  const long long wgs = grid < i8_compute_units() ? grid : i8_compute_units();
+  hipLaunchKernelGGL((i8_gemm_kernel<S, D, EPI, kIWaves, kINJ>), dim3(static_cast<unsigned>(wgs)),
+                     dim3(64 * kIWaves), 0, s, a);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
@@ -457,7 +509,7 @@ int i8_forward_s(const Plan& pl, const double* L, const double* t, double* R, ch
   const long long v2 = (long long)v * v;
   const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
   const SliceDims dt = slice_dims((long long)o * o, static_cast<int>(v2));
-  const SliceDims dV = slice_dims(pl.pairsym ? pair_prefix(pl.n_a, v) : (long long)pl.n_a * v,
+  const SliceDims dV = slice_dims(pl.pairsym ? pl.npk : (long long)pl.n_a * v,
                                   static_cast<int>(v2));
   signed char* Ls = reinterpret_cast<signed char*>(ws + pl.off_L);
   int* Le = reinterpret_cast<int*>(ws + pl.off_Lexp);
@@ -473,8 +525,10 @@ int i8_forward_s(const Plan& pl, const double* L, const double* t, double* R, ch
   if (!rc) rc = i8_slice_kc<S>(t, v2, o * o, static_cast<int>(v2), dt, ts, te, s);
   tr(CC_LADDER_PHASE_PREP, 0, 1);
   if (rc) return rc;
-  for (int a0 = 0, blk = 0; a0 < v; a0 += pl.n_a, ++blk) {
-    const int na = (v - a0) < pl.n_a ? (v - a0) : pl.n_a;
+  for (int blk = 0; blk < pl.nblocks; ++blk) {
+    int a0, na;
+    block_range(pl, blk, &a0, &na);
+    if (na <= 0) continue;
     const long long r0 = (long long)a0 * v;  // first (a,c) row of this block
     const long long nrows = pl.pairsym ? pair_prefix(a0 + na, v) - pair_prefix(a0, v)
                                        : (long long)na * v;

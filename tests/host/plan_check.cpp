@@ -84,7 +84,21 @@ static void workspace_checks() {
 
 static void plan_invariants(const Plan& p, int backward, size_t budget) {
   CHECK(p.n_a >= 1 && p.n_a <= p.v);
-  CHECK(p.nblocks == (p.v + p.n_a - 1) / p.n_a);
+  if (p.balanced) {
+    // pair-balanced blocks tile [0, v) and none exceeds the buffers' sizes
+    CHECK(p.pairsym && !backward && p.nblocks >= 1 && p.nblocks <= p.v);
+    int next = 0;
+    for (int k = 0; k < p.nblocks; ++k) {
+      int a0, na;
+      block_range(p, k, &a0, &na);
+      CHECK(a0 == next && na >= 0 && na <= p.n_a);
+      CHECK(pair_prefix(a0 + na, p.v) - pair_prefix(a0, p.v) <= p.npk);
+      next = a0 + na;
+    }
+    CHECK(next == p.v);
+  } else {
+    CHECK(p.nblocks == (p.v + p.n_a - 1) / p.n_a);
+  }
   CHECK(p.bytes % 256 == 0);
   CHECK(budget == 0 || p.bytes <= budget);
   const size_t offs[] = {p.off_lamP, p.off_B, p.off_check, p.off_tx, p.off_dtx, p.off_L, p.off_t,
@@ -142,8 +156,16 @@ static void planner_sweep() {
     if (rc) continue;
     ++plans;
     plan_invariants(p, backward, budget);
-    // the footprint grows with the block size (the search relies on it)
-    if (p.n_a < v) {
+    // the footprint grows with the block size (the search relies on it); for
+    // pair-balanced blocks it shrinks as their count grows
+    if (p.balanced) {
+      if (p.nblocks > 1) {
+        Plan q;
+        const int rc2 = layout_plan(o, v, P, precision, backward, 0, opts.split_slices,
+                                    opts.split_depth, opts.k_chunk, opts.flags, &q, p.nblocks - 1);
+        CHECK(rc2 == CC_LADDER_OK && q.bytes >= p.bytes);
+      }
+    } else if (p.n_a < v) {
       Plan q;
       const int rc2 = layout_plan(o, v, P, precision, backward, p.n_a + 1, opts.split_slices,
                                   opts.split_depth, opts.k_chunk, opts.flags, &q);

@@ -97,3 +97,33 @@ def test_plus_minus_rejections(gpu_lib):
     assert e.value.code == gpu_lib.CC_LADDER_EUNSUPPORTED
     torch.cuda.synchronize()
     assert float(R.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("precision,slices,pm", [(0, 0, False), (0, 0, True), (1, 0, True),
+                                                 (2, 4, False), (3, 5, False)])
+def test_pair_balanced_blocks(gpu_lib, precision, slices, pm):
+    # a budget that forces several blocks of about equal pair counts (no a_block
+    # given): the same result as one block, bit for bit in float64, and the
+    # oracle's within tolerance
+    o, v, P = 6, 53, 40
+    announce("pair-balanced-blocks", precision, slices, pm)
+    L, t, _ = random_general(o, v, P, 1400 + precision)
+    t = _pair_symmetric(t)
+    kw = dict(split_slices=slices, pair_symmetric=True, plus_minus=pm)
+    one, blk1 = gpu_lib.cc_ladder_workspace_query(o, v, P, precision, opts=gpu_lib.make_opts(**kw))
+    assert blk1 == v
+    budget = one // 3
+    nbytes, blk = gpu_lib.cc_ladder_workspace_query(o, v, P, precision, hbm_budget=budget,
+                                                    opts=gpu_lib.make_opts(**kw))
+    assert nbytes <= budget and blk < v
+    R1 = dev(np.zeros_like(t))
+    gpu_lib.cc_ladder_residual(dev(L), dev(t), R1, precision, opts=gpu_lib.make_opts(**kw))
+    Rb = dev(np.zeros_like(t))
+    gpu_lib.cc_ladder_residual(dev(L), dev(t), Rb, precision,
+                               opts=gpu_lib.make_opts(hbm_budget=budget, **kw))
+    torch.cuda.synchronize()
+    if precision == 0:
+        assert torch.equal(R1, Rb)
+    ref = oracle.ladder_forward(L, t)
+    tol = {0: TOL[0], 1: TOL[1], 2: 2e-9, 3: 1e-9}[precision]
+    assert rel_fro(host(Rb), ref) < tol
