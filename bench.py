@@ -388,10 +388,11 @@ def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
     torch.cuda.empty_cache()
     free, total = torch.cuda.mem_get_info()
     # the adjoint's dL and dt are allocated later: keep their room out of the large budget
-    extra = 2 * t.numel() * 8 + L.numel() * 8
+    extra = t.numel() * 8 + L.numel() * 8
     budgets = {"default": int(min(free // 2, 64 << 30)),
                "device": int(free - extra - (8 << 30))}
     res["device_total_bytes"] = int(total)
+    res["budgets_bytes"] = budgets
 
     def timed(call, timer, after_warmup=None):
         call()  # warm-up (also plans nothing new: the workspace is the caller's)
@@ -425,11 +426,14 @@ def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
 
             ms = timed(lambda: native.cc_ladder_residual(L, t, R, prec, opts=opts), timer, check)
             got = got[0]
-            del ws
+            phases = {k: d["ms_total"] for k, d in timer.summary().items()}
+            # release the workspace (the options hold a reference) before the next plan
+            del ws, opts, timer
+            torch.cuda.empty_cache()
             r = {"ms": ms, "tflops": fwd / (ms * 1e-3) / 1e12, "a_block": n_a,
                  "workspace_bytes": nbytes,
                  "rel_err_vs_oracle_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                 "phases_ms": {k: d["ms_total"] for k, d in timer.summary().items()}}
+                 "phases_ms": phases}
             res[f"{form}_{bname}"] = r
             log(f"large {form} budget {bname} ({budget / 2**30:.0f} GiB, a_block {n_a}): "
                 f"{ms:.0f} ms {r['tflops']:.1f} TFLOP/s phases {json.dumps(r['phases_ms'])}")
