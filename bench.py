@@ -41,7 +41,9 @@ METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 
 # *_exchange forms evaluate the exchange partner sum_cd (ad|bc) t[i,j,c,d]
 # (eq. vfunction2) with the same nominal flops.
 # The *_pm forms contract the symmetric and antisymmetric combinations t+- with
-# V+- = (ac|bd) +- (ad|bc) over i <= j, a <= b, c <= d (pair-symmetric amplitudes).
+# V+- = (ac|bd) +- (ad|bc) over i <= j, a <= b, c <= d (pair-symmetric amplitudes);
+# the *_pm_symv forms gather V+- from the whole pair-pair integral of the
+# workload's symmetric Cholesky vectors (built over its upper triangle).
 FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16": ("split_bf16", 4, False, False),
          "split_bf16_s2": ("split_bf16", 2, False, False),
@@ -49,6 +51,7 @@ FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "fp64_pairsym": ("fp64", 0, True, False), "fp32_pairsym": ("fp32", 0, True, False),
          "split_bf16_pairsym": ("split_bf16", 4, True, False),
          "fp64_pm": ("fp64", 0, "pm", False), "fp32_pm": ("fp32", 0, "pm", False),
+         "fp64_pm_symv": ("fp64", 0, "pmv", False), "fp32_pm_symv": ("fp32", 0, "pmv", False),
          "fp64_exchange": ("fp64", 0, False, True), "fp32_exchange": ("fp32", 0, False, True),
          "split_bf16_exchange": ("split_bf16", 4, False, True),
          "split_int8": ("split_int8", 5, False, False),
@@ -84,14 +87,18 @@ def executed_flops(form, o, v, P):
     """(build, contraction) flops a form executes per forward: 2 P v^4 and
     2 o^2 v^4 in general; packed rows a <= b halve both (the build's (v+1)/(2v));
     the +- combinations contract o(o+1)/2 rows with the v(v+1)/2 pairs c <= d
-    and o(o-1)/2 rows with the v(v-1)/2 pairs c < d."""
+    and o(o-1)/2 rows with the v(v-1)/2 pairs c < d; with symmetric vectors the
+    build is the upper triangle of the pair-pair integral, P n(n+1) for
+    n = v(v+1)/2 pairs."""
     v4 = float(v) ** 4
     sym = FORMS[form][2]
     if not sym:
         return 2.0 * P * v4, 2.0 * o * o * v4
     npk = v * (v + 1) / 2.0
     build = 2.0 * P * v * v * npk
-    if sym == "pm":
+    if sym == "pmv":
+        build = P * npk * (npk + 1)  # the pair-pair integral's upper triangle
+    if sym in ("pm", "pmv"):
         nm = v * (v - 1) / 2.0
         return build, 2.0 * (o * (o + 1) / 2.0 * npk * npk + o * (o - 1) / 2.0 * nm * nm)
     return build, 2.0 * o * o * v * v * npk
@@ -200,21 +207,23 @@ def sampled_pairs(v, n, seed):
     return sorted(pairs)
 
 
+def form_opts(native, form, **kw):
+    """The library options of a form (plus workspace, trace, ... in kw)."""
+    slices, sym, exchange = FORMS[form][1:]
+    return native.make_opts(split_slices=slices, pair_symmetric=bool(sym), exchange=exchange,
+                            plus_minus=sym in ("pm", "pmv"), symmetric_vectors=sym == "pmv", **kw)
+
+
 def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
     import torch
 
     prec = native.PRECISIONS[FORMS[form][0]]
-    slices, pairsym, exchange = FORMS[form][1:]
-    pm = pairsym == "pm"
     stream = torch.cuda.current_stream()
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    nbytes, n_a = native.cc_ladder_workspace_query(
-        o, v, P, prec, hbm_budget=ws_bytes,
-        opts=native.make_opts(split_slices=slices, pair_symmetric=bool(pairsym), exchange=exchange,
-                              plus_minus=pm))
+    nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, prec, hbm_budget=ws_bytes,
+                                                   opts=form_opts(native, form))
     timer = PhaseTimer(native, stream)
-    opts = native.make_opts(workspace=ws, trace=timer.fn, split_slices=slices,
-                            pair_symmetric=bool(pairsym), exchange=exchange, plus_minus=pm)
+    opts = form_opts(native, form, workspace=ws, trace=timer.fn)
 
     def step():
         native.cc_ladder_residual(L, t, R, prec, opts=opts)
@@ -248,10 +257,7 @@ def rel_err_form(native, form, L, t, ref, idx_a, idx_b, ws_bytes):
     R = torch.zeros_like(t)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     native.cc_ladder_residual(L, t, R, native.PRECISIONS[FORMS[form][0]],
-                              opts=native.make_opts(workspace=ws, split_slices=FORMS[form][1],
-                                                    pair_symmetric=bool(FORMS[form][2]),
-                                                    exchange=FORMS[form][3],
-                                                    plus_minus=FORMS[form][2] == "pm"))
+                              opts=form_opts(native, form, workspace=ws))
     torch.cuda.synchronize()
     got = R[:, :, idx_a, idx_b].permute(2, 0, 1).cpu().numpy()
     del R, ws
@@ -317,7 +323,7 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
     ref = None
     stream = torch.cuda.current_stream()
     free, _ = torch.cuda.mem_get_info()
-    budget = int(min(free // 2, 64 << 30))
+    budget = int(min(free // 2, 128 << 30))
     for form in forms:
         prec = native.PRECISIONS[form.split("_")[0]]
         sym = form.endswith("_pairsym")
@@ -358,7 +364,7 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
 def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
     """The large single-GPU workload (o=60, v=600, P=1800) under two scratch
     budgets, each a caller workspace allocated once: the default (half the free
-    memory, at most 64 GiB) and one sized to the device (the free memory left
+    memory, at most 128 GiB, as the library plans by default) and one sized to the device (the free memory left
     with every array of the call resident, less 8 GiB).  Per budget and form: a
     warm-up call, then one timed call (HIP events on the call's stream) with
     per-phase times; the float32 adjoint is timed the same way.  Errors: the
@@ -389,7 +395,7 @@ def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
     free, total = torch.cuda.mem_get_info()
     # the adjoint's dL and dt are allocated later: keep their room out of the large budget
     extra = t.numel() * 8 + L.numel() * 8
-    budgets = {"default": int(min(free // 2, 64 << 30)),
+    budgets = {"default": int(min(free // 2, 128 << 30)),
                "device": int(free - extra - (8 << 30))}
     res["device_total_bytes"] = int(total)
     res["budgets_bytes"] = budgets
@@ -539,10 +545,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_int8,split_bf16_s2,fp64_pairsym,"
-                                       "fp64_pm,fp32_pm,split_bf16_pairsym,split_int8_pairsym,"
-                                       "fp64_exchange")
+                                       "fp64_pm,fp32_pm,fp64_pm_symv,fp32_pm_symv,split_bf16_pairsym,"
+                                       "split_int8_pairsym,fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--budget-gib", type=float, default=64.0,
+    ap.add_argument("--budget-gib", type=float, default=128.0,
                     help="scratch budget of the timed forms: at most this many GiB, and at most "
                          "half the free device memory")
     ap.add_argument("--no-adjoint", action="store_true")

@@ -130,6 +130,22 @@ typedef enum {
                                         PAIR_SYMMETRIC; EUNSUPPORTED in the split forms; the
                                         adjoint ignores it. */
 
+#define CC_LADDER_SYMMETRIC_VECTORS 16u /* with PLUS_MINUS: the caller asserts L[x][a][c] ==
+                                        L[x][c][a] (real orbitals give one symmetric Cholesky
+                                        factor for both pair indices, Sec. "The CC ansatz",
+                                        eq. cholesky).  The integral is then the symmetric matrix
+                                        G[{a,c}][{b,d}] = sum_x L[x][a][c] L[x][b][d] over the
+                                        v(v+1)/2 unordered pairs, built once over its upper
+                                        triangle (the 8-fold permutational symmetry: a quarter of
+                                        the packed build's flops), and each block's V+- is
+                                        gathered from it.  G is kept whole in scratch, a square of
+                                        v(v+1)/2 (rounded up to a multiple of 4) elements of the
+                                        form's type (34 GB in float64 at v = 360); when it does
+                                        not fit the budget the flag changes nothing.  With
+                                        CHECK_SYMMETRY, L is checked as well:
+                                        EINVAL when some |L[x][a][c] - L[x][c][a]| exceeds
+                                        2^-40 max|L|.  EINVAL without PLUS_MINUS. */
+
 /* Kernel phases reported to an optional trace hook. */
 typedef enum {
   CC_LADDER_PHASE_PREP = 0,      /* operand conversion / slicing of L, t, lam; the exchange swaps
@@ -157,7 +173,7 @@ typedef struct {
                               depth in [1, 2]; 0 = 2 for S = 4 (13 products), 1 otherwise
                               (S = 2: hi*hi, hi*lo, lo*hi; S = 3: 6 products) */
   size_t hbm_budget;       /* bytes the library may use for scratch; 0 = half the free device
-                              memory, at most 64 GiB */
+                              memory, at most 128 GiB */
   void*  workspace;        /* caller scratch (device, 256-byte aligned) or NULL; the part the
                               plan uses, [workspace, workspace + planned bytes), must not
                               overlap any tensor argument (CC_LADDER_EINVAL) */
@@ -165,7 +181,8 @@ typedef struct {
   cc_ladder_trace_fn trace;  /* optional per-phase hook, NULL = none */
   void*  trace_user;       /* passed back to `trace` */
   unsigned flags;          /* CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE |
-                              CC_LADDER_CHECK_SYMMETRY | CC_LADDER_PLUS_MINUS, or 0 */
+                              CC_LADDER_CHECK_SYMMETRY | CC_LADDER_PLUS_MINUS |
+                              CC_LADDER_SYMMETRIC_VECTORS, or 0 */
   int    reserved;         /* must be 0 */
 } cc_ladder_opts;
 

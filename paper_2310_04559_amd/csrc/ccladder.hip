@@ -144,7 +144,7 @@ bool launch_rc_direct(const GemmArgs<typename Tr::T>& g0, hipStream_t stream, in
   long long grid = (long long)g.tiles_m * g.tiles_n;
   if (grid > 0x7fffffffLL) return false;
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
-  if (EPI == EPI_PACK) {
+  if (EPI == EPI_PACK || EPI == EPI_SYM) {
     if (!g.row_tiles) return false;
     long long needed = 0;
     for (int tm = 0; tm < g.tiles_m; ++tm) {
@@ -187,11 +187,13 @@ template <class Tr, int LA, int LB, int EPI>
 int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B, long long ldb,
                 void* C, long long ldc, int M, int N, int K, int v, int drain_steps,
                 hipStream_t stream, int o = 0, int a0 = 0, int* row_tiles = nullptr,
-                double alpha = 1.0, int pm = 0) {
+                double alpha = 1.0, int pm = 0, int kband = 0, int m_keep = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return CC_LADDER_OK;
   GemmArgs<typename Tr::T> g;
   g.alpha = alpha;
   g.pm = pm;
+  g.kband = kband;
+  g.m_keep = m_keep;
   g.A = A; g.lda = lda;
   g.B = B; g.ldb = ldb;
   g.C = C; g.ldc = ldc;
@@ -201,7 +203,9 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   g.a0 = a0;
   g.row_tiles = row_tiles;
   g.drain_steps = drain_steps > 0 ? drain_steps : 1;
-  if constexpr (LA == RC && LB == RC && (EPI == EPI_PERM || EPI == EPI_PACK) && Tr::kDirectRC) {
+  if constexpr (LA == RC && LB == RC &&
+                (EPI == EPI_PERM || EPI == EPI_PACK || EPI == EPI_UNPACK || EPI == EPI_SYM) &&
+                Tr::kDirectRC) {
     int rc = CC_LADDER_OK;
     if (launch_rc_direct<Tr, EPI>(g, stream, &rc)) return rc;
   }
@@ -213,7 +217,7 @@ int launch_gemm(const typename Tr::T* A, long long lda, const typename Tr::T* B,
   // both their row panels and a few column panels.
   g.group_m = g.tiles_m < 16 ? g.tiles_m : 16;
   dim3 grid(static_cast<unsigned>(tiles));
-  if (EPI == EPI_PACK) {
+  if (EPI == EPI_PACK || EPI == EPI_SYM) {
     if (!row_tiles) return CC_LADDER_EINVAL;
     // the compact grid's size is the sum over tile rows of the needed columns
     long long needed = 0;
@@ -375,21 +379,42 @@ int fill_zero(double* x, long long n, hipStream_t s) {
 
 // Pair-symmetric adjoint, per block: lamP[(ij)][q] = w lam[(ij)][(a,b)] for the
 // block's packed pairs q -> (a, b) (a in the block, b >= a), w = 1/2 when a == b,
-// row stride ldp.
+// row stride ldp; the pad columns [npairs, ldp) are zero.
 template <typename T>
 __global__ __launch_bounds__(256) void gather_pairs_kernel(const T* __restrict__ lam,
                                                            T* __restrict__ lamP, int o2, int v,
                                                            int a0, long long npairs, long long ldp) {
-  const long long n = (long long)o2 * npairs;
+  const long long n = (long long)o2 * ldp;
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long v2 = (long long)v * v;
   const long long base = pair_prefix_d(a0, v);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-    const long long row = e / npairs, q = e - row * npairs;
+    const long long row = e / ldp, q = e - row * ldp;
+    if (q >= npairs) {
+      lamP[e] = T(0);
+      continue;
+    }
     const int a = pair_row(base + q, v);
     const int b = a + static_cast<int>(base + q - pair_prefix_d(a, v));
     const T x = lam[row * v2 + (long long)a * v + b];
-    lamP[row * ldp + q] = (a == b) ? x * T(0.5) : x;
+    lamP[e] = (a == b) ? x * T(0.5) : x;
+  }
+}
+
+// Rows (a - a0, c) of a half-written adjoint block W[na][v][v][v] (only b >= a
+// stored by the packed product): zeros at b in [max(0, a - s), a), the rows next
+// to the diagonal that the K-banded products still read.
+template <typename T>
+__global__ __launch_bounds__(256) void zero_band_kernel(T* __restrict__ W, int na, int v, int a0,
+                                                        int s) {
+  const long long v2 = (long long)v * v;
+  const long long rows = (long long)na * v;
+  for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int a = a0 + static_cast<int>(r / v);
+    const int b0 = a - s > 0 ? a - s : 0;
+    T* row = W + r * v2;
+    for (long long e = (long long)b0 * v + threadIdx.x; e < (long long)a * v; e += blockDim.x)
+      row[e] = T(0);
   }
 }
 
@@ -517,6 +542,119 @@ int pm_rows(const In* X, long long nrows, int n, int a0, int v, Out* plus, long 
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
 }
 
+// Symmetric vectors: Lp[x][pair(a,c)] = L[x][a][c] for a <= c (pair(a,c) =
+// prefix_v(a) + c - a), row stride ldg, the pad columns [v(v+1)/2, ldg) zero.
+// One workgroup per (x, a): contiguous reads and writes along c.
+template <typename Out>
+__global__ __launch_bounds__(256) void pack_sym_kernel(const double* __restrict__ L,
+                                                       Out* __restrict__ Lp, int P, int v,
+                                                       long long ldg) {
+  const long long v2 = (long long)v * v;
+  const long long npv = (long long)v * (v + 1) / 2;
+  for (long long r = blockIdx.x; r < (long long)P * v; r += gridDim.x) {
+    const long long x = r / v;
+    const int a = static_cast<int>(r - x * v);
+    const double* src = L + x * v2 + (long long)a * v;
+    Out* dst = Lp + x * ldg + pair_prefix_d(a, v) - a;  // dst[c] = Lp[x][pair(a, c)]
+    for (int c = a + static_cast<int>(threadIdx.x); c < v; c += blockDim.x)
+      dst[c] = static_cast<Out>(src[c]);
+    if (a == v - 1)
+      for (long long e = npv + threadIdx.x; e < ldg; e += blockDim.x) Lp[x * ldg + e] = Out(0);
+  }
+}
+
+// The combinations of a block's integral rows, gathered from the whole
+// pair-pair integral G of symmetric vectors (G[p][q] = G[q][p], p, q unordered
+// pairs): the rows (a, b), a <= b, a from a0, of X_ab[c][d] = (ac|bd) =
+// G[{a,c}][{b,d}] go into plus/minus exactly as in pm_rows (wdiag 2, sm 1).
+// Work item w = (tile pair C <= D, row r), the row inner: workgroups that run
+// together on one XCD take consecutive rows, the same a with consecutive b.
+// Every element of the two 32 x 32 tiles is read in an orientation of G that
+// keeps 32 lanes on one contiguous run where one exists: along d in row {a,c}
+// when d >= b; along c in row {b,d} when d < b and c >= a; otherwise (c < a,
+// d < b) element by element, where neighbouring rows b share the cache lines.
+template <typename T>
+__global__ __launch_bounds__(256) void pm_gather_kernel(const T* __restrict__ G, long long ldg,
+                                                        long long nrows, int a0, int v, int tiles,
+                                                        T* __restrict__ plus, long long ldp,
+                                                        T* __restrict__ minus, long long ldm) {
+  __shared__ double xs[kSwapTile][kSwapTile + 1], ys[kSwapTile][kSwapTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const long long ntp = (long long)tiles * (tiles + 1) / 2;
+  const long long work = nrows * ntp;
+  auto pp = [&](long long x) { return pair_prefix_d(x, v); };
+  for (long long w = xcd_linear(blockIdx.x, gridDim.x); w < work; w += gridDim.x) {
+    const long long tp = w / nrows, r = w - tp * nrows;
+    const int C = pair_row(tp, tiles);
+    const int D = C + static_cast<int>(tp - pair_prefix_d(C, tiles));
+    const int c0 = C * kSwapTile, d0 = D * kSwapTile;
+    const long long q = pp(a0) + r;
+    const int a = pair_row(q, v);
+    const int b = a + static_cast<int>(q - pp(a));
+    const long long rm = a < b ? pair_prefix_d(a, v - 1) - pair_prefix_d(a0, v - 1) + (b - a - 1) : -1;
+    // S[k][l] = X_ab[r0 + k][s0 + l]
+    auto load = [&](double (*S)[kSwapTile + 1], int r0, int s0) {
+#pragma unroll
+      for (int k = ty; k < kSwapTile; k += 8) {
+        const int c = r0 + k, d = s0 + tx;
+        double x = 0.0;
+        if (c < v && d < v) {
+          if (d >= b) {
+            const long long pac = a <= c ? pp(a) + c - a : pp(c) + a - c;
+            x = static_cast<double>(G[pac * ldg + pp(b) + d - b]);
+          } else if (c < a) {
+            x = static_cast<double>(G[(pp(c) + a - c) * ldg + pp(d) + b - d]);
+          }
+        }
+        if (!(c < v && d < v) || d >= b || c < a) S[k][tx] = x;
+      }
+#pragma unroll
+      for (int l = ty; l < kSwapTile; l += 8) {
+        const int c = r0 + tx, d = s0 + l;
+        if (c < v && d < v && d < b && c >= a)
+          S[tx][l] = static_cast<double>(G[(pp(d) + b - d) * ldg + pp(a) + c - a]);
+      }
+    };
+    load(xs, c0, d0);
+    load(ys, d0, c0);
+    __syncthreads();
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      const int c = c0 + k, d = d0 + tx;
+      if (c < v && d < v && c <= d) {
+        const double xcd = xs[k][tx], xdc = ys[tx][k];
+        const long long kp = pp(c) + (d - c);
+        plus[r * ldp + kp] = static_cast<T>(c == d ? 2.0 * xcd : xcd + xdc);
+        if (rm >= 0 && c < d) {
+          const long long km = pair_prefix_d(c, v - 1) + (d - c - 1);
+          minus[rm * ldm + km] = static_cast<T>(xcd - xdc);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+int pm_gather(const T* G, long long ldg, long long nrows, int a0, int v, T* plus, long long ldp,
+              T* minus, long long ldm, hipStream_t s) {
+  if (nrows <= 0) return CC_LADDER_OK;
+  const int tiles = (v + kSwapTile - 1) / kSwapTile;
+  const long long work = nrows * ((long long)tiles * (tiles + 1) / 2);
+  const long long blocks = std::min<long long>(work, 65536);
+  hipLaunchKernelGGL((pm_gather_kernel<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, G,
+                     ldg, nrows, a0, v, tiles, plus, ldp, minus, ldm);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+template <typename Out>
+int pack_sym(const double* L, Out* Lp, int P, int v, long long ldg, hipStream_t s) {
+  const long long blocks = std::min<long long>((long long)P * v, 65536);
+  hipLaunchKernelGGL((pack_sym_kernel<Out>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     L, Lp, P, v, ldg);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
 constexpr int kRedBlocks = 1024;
 
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const double* __restrict__ x,
@@ -587,7 +725,7 @@ size_t default_budget() {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0;
   const size_t half = free_b / 2;
-  const size_t cap = static_cast<size_t>(64) << 30;
+  const size_t cap = static_cast<size_t>(128) << 30;
   return half < cap ? half : cap;
 }
 
@@ -637,22 +775,28 @@ int plan_and_scratch(int o, int v, int P, int precision, int backward, hipStream
   return take_scratch(*plan, stream, opts, ws);
 }
 
-// Pair-symmetry check: out[0] = max |x[i][j][c][d] - x[j][i][d][c]|, out[1] =
-// max |x| over the o^2 v^2 entries, as the bit patterns of non-negative doubles
-// (ordered like the values, so an integer maximum combines them).  out must be
-// zero on entry.
-__global__ __launch_bounds__(256) void pair_asym_kernel(const double* __restrict__ x, int o, int v,
-                                                        unsigned long long* out) {
+// Symmetry check of nmat v x v matrices: out[0] = max |x[m][c][d] - x[m'][d][c]|
+// with partner m' = (j, i) of m = (i, j) over o x o when o > 0 (the pair
+// symmetry of t or lam), m' = m when o == 0 (each matrix symmetric: the
+// Cholesky vectors); out[1] = max |x|; as the bit patterns of non-negative
+// doubles (ordered like the values, so an integer maximum combines them).  out
+// must be zero on entry.
+__global__ __launch_bounds__(256) void pair_asym_kernel(const double* __restrict__ x, long long nmat,
+                                                        int o, int v, unsigned long long* out) {
   const long long v2 = (long long)v * v;
-  const long long n = (long long)o * o * v2;
+  const long long n = nmat * v2;
   const long long stride = (long long)gridDim.x * blockDim.x;
   double dmax = 0.0, xmax = 0.0;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
     const long long m = e / v2, cd = e - m * v2;
-    const long long i = m / o, j = m - i * o;
+    long long partner = m;
+    if (o > 0) {
+      const long long i = m / o, j = m - i * o;
+      partner = j * o + i;
+    }
     const long long c = cd / v, d = cd - c * v;
     const double a = x[e];
-    const double b = x[(j * o + i) * v2 + d * v + c];
+    const double b = x[partner * v2 + d * v + c];
     dmax = fmax(dmax, fabs(a - b));
     xmax = fmax(xmax, fabs(a));
   }
@@ -679,12 +823,13 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 
 // CC_LADDER_CHECK_SYMMETRY: returns CC_LADDER_EINVAL when some pair of x differs
 // by more than 2^-40 max|x| (synchronises the stream to read the result).
-int check_pair_symmetric(const double* x, int o, int v, unsigned long long* buf, hipStream_t s) {
+int check_symmetric(const double* x, long long nmat, int o, int v, unsigned long long* buf,
+                    hipStream_t s) {
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, buf, 2);
-  const long long n = (long long)o * o * v * v;
+  const long long n = nmat * v * v;
   const long long blocks = std::min<long long>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(pair_asym_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x, o,
-                     v, buf);
+  hipLaunchKernelGGL(pair_asym_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x,
+                     nmat, o, v, buf);
   if (hipGetLastError() != hipSuccess) return CC_LADDER_EHIP;
   unsigned long long h[2] = {0, 0};
   CCL_HIP(hipMemcpyAsync(h, buf, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -693,6 +838,16 @@ int check_pair_symmetric(const double* x, int o, int v, unsigned long long* buf,
   std::memcpy(&d, &h[0], sizeof(double));
   std::memcpy(&m, &h[1], sizeof(double));
   return d <= std::ldexp(m, -40) ? CC_LADDER_OK : CC_LADDER_EINVAL;
+}
+
+// t or lam against its pair transpose x[j][i][d][c]
+int check_pair_symmetric(const double* x, int o, int v, unsigned long long* buf, hipStream_t s) {
+  return check_symmetric(x, (long long)o * o, o, v, buf, s);
+}
+
+// the Cholesky vectors against their transposes L[x][c][a]
+int check_vectors_symmetric(const double* L, int P, int v, unsigned long long* buf, hipStream_t s) {
+  return check_symmetric(L, P, 0, v, buf, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,13 +907,24 @@ template <class Tr>
 int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr::T* Tp,
                       const typename Tr::T* Tm, double* R, typename Tr::T* V,
                       typename Tr::T* Vp, typename Tr::T* Vm, int* row_tiles, const Tracer& tr,
-                      hipStream_t s) {
+                      hipStream_t s, const typename Tr::T* Lp = nullptr,
+                      typename Tr::T* G = nullptr) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
   const int mp = o * (o + 1) / 2, mm = o * (o - 1) / 2;
   const int kp = static_cast<int>((long long)v * (v + 1) / 2);
   const int km = static_cast<int>((long long)v * (v - 1) / 2);
+  if (pl.gsym) {
+    // symmetric vectors: G[p][q] = sum_x Lp[x][p] Lp[x][q] over the unordered
+    // pairs, the tiles on or above the diagonal (each stored with its mirror)
+    tr(CC_LADDER_PHASE_BUILD, 0, 0);
+    const int n = static_cast<int>(pl.ldg);
+    const int rc = launch_gemm<Tr, RC, RC, EPI_SYM>(Lp, pl.ldg, Lp, pl.ldg, G, pl.ldg, n, n, P, 1,
+                                                    drain, s, 0, 0, row_tiles);
+    tr(CC_LADDER_PHASE_BUILD, 0, 1);
+    if (rc) return rc;
+  }
   for (int blk = 0; blk < pl.nblocks; ++blk) {
     int a0, na;
     block_range(pl, blk, &a0, &na);
@@ -767,11 +933,17 @@ int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr
     const long long np = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
     const long long nm = np - na;
     tr(CC_LADDER_PHASE_BUILD, blk, 0);
-    int rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
-                                               static_cast<int>((long long)(v - a0) * v), P, v,
-                                               drain, s, o, a0, row_tiles);
-    if (!rc)
-      rc = pm_rows<PM_INTS>(V, np, v, a0, v, Vp, pl.ldp, Vm, pl.ldm, 2.0, 1.0, s);
+    int rc;
+    if (pl.gsym) {
+      rc = pm_gather(static_cast<const typename Tr::T*>(G), pl.ldg, np, a0, v, Vp, pl.ldp, Vm,
+                     pl.ldm, s);
+    } else {
+      rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
+                                             static_cast<int>((long long)(v - a0) * v), P, v,
+                                             drain, s, o, a0, row_tiles);
+      if (!rc)
+        rc = pm_rows<PM_INTS>(V, np, v, a0, v, Vp, pl.ldp, Vm, pl.ldm, 2.0, 1.0, s);
+    }
     tr(CC_LADDER_PHASE_BUILD, blk, 1);
     if (rc) return rc;
     tr(CC_LADDER_PHASE_CONTRACT, blk, 0);
@@ -810,10 +982,11 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     block_range(pl, blk, &a0, &na);
     if (na <= 0) continue;
     const long long off = (long long)a0 * v;
+    // pair-symmetric: the block's packed pairs (a, b), a <= b, and lamP's row stride
+    const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
+    const long long ldp = (npairs + 3) / 4 * 4;
     int rc;
     if (sym) {
-      const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
-      const long long ldp = (npairs + 3) / 4 * 4;
       tr(CC_LADDER_PHASE_BUILD, blk, 0);
       rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
                                              static_cast<int>((long long)(v - a0) * v), P, v,
@@ -848,21 +1021,49 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     }
     // W'_A[a][c][b][d] = sum_(ij) lam[(ij)][a0*v + (ab)] t[(ij)][(cd)]
     tr(CC_LADDER_PHASE_W, blk, 0);
-    rc = launch_gemm<Tr, RC, RC, EPI_PERM>(lam + off, v2, t, v2, W, 0, na * v,
-                                           static_cast<int>(v2), o * o, v, drain, s);
+    if (sym) {
+      // With pair-symmetric t and lam, W[b,d,a,c] = W[a,c,b,d]: only the half
+      // Wh over the packed pairs b >= a is formed (the diagonal a == b halved by
+      // lamP's weights), so that W = Wh + Wh^T.  The K-banded dL products read
+      // up to `band` rows b below the diagonal: those are zeroed.
+      const int band = (kDBN - 2 + v) / v + (32 - 2 + v) / v;
+      const long long rows = (long long)na * v;
+      hipLaunchKernelGGL((zero_band_kernel<T>), dim3(static_cast<unsigned>(std::min<long long>(rows, 16384))),
+                         dim3(256), 0, s, W, na, v, a0, band);
+      rc = hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+      if (!rc)
+        rc = launch_gemm<Tr, RC, RC, EPI_UNPACK>(lamP, ldp, t, v2, W, 0, static_cast<int>(ldp),
+                                                 static_cast<int>(v2), o * o, v, drain, s, 0, a0,
+                                                 nullptr, 1.0, 0, 0, static_cast<int>(npairs));
+    } else {
+      rc = launch_gemm<Tr, RC, RC, EPI_PERM>(lam + off, v2, t, v2, W, 0, na * v,
+                                             static_cast<int>(v2), o * o, v, drain, s);
+    }
     tr(CC_LADDER_PHASE_W, blk, 1);
     if (rc) return rc;
     tr(CC_LADDER_PHASE_DL, blk, 0);
-    // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]; with pair-symmetric t
-    // and lam, W[b,a,d,c] = W[a,b,c,d] and the second term equals the first:
-    // it is added twice instead
-    rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
-                                          static_cast<int>(v2), v, drain, s, 0, 0, nullptr,
-                                          sym ? 2.0 : 1.0);
-    // dL[x][(bd)] += L[x][a0*v + (ac)] . W'_A[(ac)][(bd)]
-    if (!rc && !sym)
-      rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
-                                            na * v, v, drain, s);
+    if (sym) {
+      // Each dL term of W = Wh + Wh^T is the first term of Wh plus the second
+      // of Wh, and the two terms of W are equal: dL += 2 (first + second), with
+      // the K ranges cut to Wh's non-zero half (b >= a).
+      // dL[x][a0*v + (ac)] += 2 L[x][(bd), b >= a] . Wh[(ac)][(bd)]
+      rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
+                                            static_cast<int>(v2), v, drain, s, 0, a0, nullptr,
+                                            2.0, 0, 1);
+      // dL[x][(bd), b >= a0] += 2 L[x][a0*v + (ac), a <= b] . Wh[(ac)][(bd)]
+      if (!rc)
+        rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W + off, v2, dL + off, v2, P,
+                                              static_cast<int>((long long)(v - a0) * v), na * v,
+                                              v, drain, s, 0, a0, nullptr, 2.0, 0, 2);
+    } else {
+      // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]
+      rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,
+                                            static_cast<int>(v2), v, drain, s);
+      // dL[x][(bd)] += L[x][a0*v + (ac)] . W'_A[(ac)][(bd)]
+      if (!rc)
+        rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W, v2, dL, v2, P, static_cast<int>(v2),
+                                              na * v, v, drain, s);
+    }
     tr(CC_LADDER_PHASE_DL, blk, 1);
     if (rc) return rc;
   }
@@ -1029,8 +1230,10 @@ int residual_body(const Plan& pl, const double* L, const double* t, double* R, i
   const int o = pl.o, v = pl.v, P = pl.P;
   int rc;
   if (pl.check_sym) {
-    rc = check_pair_symmetric(t, o, v, reinterpret_cast<unsigned long long*>(base + pl.off_check),
-                              stream);
+    unsigned long long* buf = reinterpret_cast<unsigned long long*>(base + pl.off_check);
+    rc = check_pair_symmetric(t, o, v, buf, stream);
+    if (!rc && opts && (opts->flags & CC_LADDER_SYMMETRIC_VECTORS))
+      rc = check_vectors_symmetric(L, P, v, buf, stream);
     if (rc) return rc;
   }
   const Tracer tr(opts, stream);
@@ -1042,26 +1245,31 @@ int residual_body(const Plan& pl, const double* L, const double* t, double* R, i
     if (precision == CC_LADDER_FP64) {
       double* Tp = reinterpret_cast<double*>(base + pl.off_Tp);
       double* Tm = reinterpret_cast<double*>(base + pl.off_Tm);
+      double* Lp = pl.gsym ? reinterpret_cast<double*>(base + pl.off_Lp) : nullptr;
       rc = pm_rows<PM_AMPS>(t, mp, o, 0, v, Tp, pl.ldp, Tm, pl.ldm, 1.0, sm, stream);
+      if (!rc && pl.gsym) rc = pack_sym(L, Lp, P, v, pl.ldg, stream);
       tr(CC_LADDER_PHASE_PREP, 0, 1);
       if (rc) return rc;
       return forward_blocks_pm<TrF64>(pl, L, Tp, Tm, R, reinterpret_cast<double*>(base + pl.off_V),
                                       reinterpret_cast<double*>(base + pl.off_Vp),
                                       reinterpret_cast<double*>(base + pl.off_Vm),
-                                      reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
+                                      reinterpret_cast<int*>(base + pl.off_tiles), tr, stream, Lp,
+                                      pl.gsym ? reinterpret_cast<double*>(base + pl.off_G) : nullptr);
     }
     if (precision != CC_LADDER_FP32) return CC_LADDER_EUNSUPPORTED;
     float* Tp = reinterpret_cast<float*>(base + pl.off_Tp);
     float* Tm = reinterpret_cast<float*>(base + pl.off_Tm);
-    float* L32 = reinterpret_cast<float*>(base + pl.off_L);
-    rc = to_f32(L, L32, (size_t)P * v * v, stream);
+    float* L32 = pl.gsym ? nullptr : reinterpret_cast<float*>(base + pl.off_L);
+    float* Lp = pl.gsym ? reinterpret_cast<float*>(base + pl.off_Lp) : nullptr;
+    rc = pl.gsym ? pack_sym(L, Lp, P, v, pl.ldg, stream) : to_f32(L, L32, (size_t)P * v * v, stream);
     if (!rc) rc = pm_rows<PM_AMPS>(t, mp, o, 0, v, Tp, pl.ldp, Tm, pl.ldm, 1.0, sm, stream);
     tr(CC_LADDER_PHASE_PREP, 0, 1);
     if (rc) return rc;
     return forward_blocks_pm<TrF32>(pl, L32, Tp, Tm, R, reinterpret_cast<float*>(base + pl.off_V),
                                     reinterpret_cast<float*>(base + pl.off_Vp),
                                     reinterpret_cast<float*>(base + pl.off_Vm),
-                                    reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
+                                    reinterpret_cast<int*>(base + pl.off_tiles), tr, stream, Lp,
+                                    pl.gsym ? reinterpret_cast<float*>(base + pl.off_G) : nullptr);
   }
   if (pl.exchange && precision != CC_LADDER_FP32) {
     // the exchange partner is the ladder of the swapped amplitudes

@@ -34,6 +34,20 @@
 //   EPI_PART: split K: workgroup s of a tile sums K-steps [s*split_steps, (s+1)*split_steps)
 //             and stores C[s*part_stride + m*ldc + n] = acc (float64 partials, summed
 //             in order of s by a separate pass)
+//   EPI_SYM:  a symmetric product (A = B): only the tiles on or above the diagonal run
+//             (the compact grid of EPI_PACK with v = 1), and each stores C[m*ldc + n] = acc
+//             and its mirror C[n*ldc + m] = acc (the same value: the products commute)
+//   EPI_UNPACK: rows are packed pairs: m = pair(a,b) - pair(a0,a0) (a <= b), n = (c, d);
+//             C[(a - a0)*v^3 + c*v^2 + b*v + d] = acc for m < m_keep (the integral-shaped
+//             block of EPI_PERM with only its b >= a half written)
+//
+// K bands (kband, any epilogue): a product whose B operand is such a half-written
+// block skips the K-steps that only meet its zero half.  kband 1: columns
+// n = (a - a0, c), K = (b, d) over every b, non-zero for b >= a: a tile's K range
+// starts at its smallest a.  kband 2: columns n = (b - a0, d), K rows (a - a0, c),
+// non-zero for a <= b: a tile's range ends after its largest b.  The ranges are
+// whole K-steps, so B must hold zeros in the few (b, a) rows next to the diagonal
+// that a rounded range still covers.
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, 128x128 workgroup tile, each
 // wave owns a 64x64 sub-tile = 4x4 MFMA 16x16 blocks.  Global tiles are read
@@ -59,7 +73,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 enum { KC = 0, RC = 1 };
-enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3, EPI_PART = 4, EPI_PM = 5 };
+enum { EPI_ACC = 0, EPI_PERM = 1, EPI_PACK = 2, EPI_PAIR = 3, EPI_PART = 4, EPI_PM = 5,
+       EPI_UNPACK = 6, EPI_SYM = 7 };
 
 // float64 operands on v_mfma_f64_16x16x4_f64.
 struct TrF64 {
@@ -121,7 +136,27 @@ struct GemmArgs {
   double alpha;          // EPI_ACC: C += alpha * acc (1, or 2 for a term counted twice)
   int m_off = 0;         // EPI_PAIR/PM: global row of this launch's row 0 (a remainder launch)
   int pm = 0;            // EPI_PM: 1 = symmetric pairs (i <= j, a <= b), 2 = antisymmetric (<)
+  int kband = 0;         // K bands of a half-written B operand (0 = the whole K range)
+  int m_keep = 0;        // EPI_UNPACK: rows stored (M may be padded to whole 16-byte chunks)
 };
+
+// K-steps [ks0, ks1) of the tile whose columns start at n0 (bn wide), steps of bk.
+template <class T>
+__device__ __forceinline__ void k_band(const GemmArgs<T>& g, int n0, int bn, int bk, int& ks0,
+                                       int& ks1) {
+  ks0 = 0;
+  ks1 = (g.K + bk - 1) / bk;
+  if (g.kband == 1) {
+    const long long k = (long long)(g.a0 + n0 / g.v) * g.v;  // first (b, d) with b = smallest a
+    ks0 = static_cast<int>(k / bk);
+  } else if (g.kband == 2) {
+    const int nl = (n0 + bn < g.N ? n0 + bn : g.N) - 1;
+    long long k = (long long)(nl / g.v + 1) * g.v;  // past the rows a - a0 <= largest b - a0
+    if (k > g.K) k = g.K;
+    const int e = static_cast<int>((k + bk - 1) / bk);
+    ks1 = e < ks1 ? e : ks1;
+  }
+}
 
 // First needed tile column of tile row tm in the packed build: columns whose
 // largest b is at least the row's smallest a.
@@ -137,13 +172,16 @@ __device__ __forceinline__ long long pair_prefix_d(long long a, long long v) {
   return a * v - a * (a - 1) / 2;
 }
 
-// Largest a with pair_prefix(a) <= q (q < v(v+1)/2).
+// Largest a with pair_prefix(a) <= q (q < v(v+1)/2): the smaller root of
+// a^2 - (2v+1) a + 2q = 0, floored.  In float64 (exact squares for v < 2^26) the
+// computed root is within far less than 1 of the true one, so one correction
+// step each way gives the floor; no loops (they keep epilogues unrolled).
 __device__ __forceinline__ int pair_row(long long q, int v) {
   const double b = 2.0 * v + 1.0;
   int a = static_cast<int>((b - sqrt(b * b - 8.0 * static_cast<double>(q))) * 0.5);
   a = a < 0 ? 0 : (a >= v ? v - 1 : a);
-  while (a + 1 < v && pair_prefix_d(a + 1, v) <= q) ++a;
-  while (a > 0 && pair_prefix_d(a, v) > q) --a;
+  if (a + 1 < v && pair_prefix_d(a + 1, v) <= q) ++a;
+  if (a > 0 && pair_prefix_d(a, v) > q) --a;
   return a;
 }
 
@@ -158,7 +196,7 @@ template <class T, int EPI>
 __device__ __forceinline__ EpiCol epi_col(const GemmArgs<T>& g, int n) {
   EpiCol c{n, 0, 0};
   const long long v = g.v;
-  if (EPI == EPI_PERM) {
+  if (EPI == EPI_PERM || EPI == EPI_UNPACK) {
     const int y = n / g.v, d = n - y * g.v;
     c.off = (long long)y * v * v + d;
   } else if (EPI == EPI_PACK) {
@@ -197,6 +235,17 @@ __device__ __forceinline__ void epi_store(const GemmArgs<T>& g, int m, int n, co
   } else if (EPI == EPI_PERM) {
     const int a = m / g.v, x = m - a * g.v;
     static_cast<T*>(g.C)[(long long)a * g.N * v + c.off + (long long)x * v] = static_cast<T>(val);
+  } else if (EPI == EPI_SYM) {
+    T* C = static_cast<T*>(g.C);
+    C[(long long)m * g.ldc + n] = static_cast<T>(val);
+    C[(long long)n * g.ldc + m] = static_cast<T>(val);
+  } else if (EPI == EPI_UNPACK) {
+    if (m >= g.m_keep) return;
+    const long long q = pair_prefix_d(g.a0, v) + m;
+    const int a = pair_row(q, g.v);
+    const int b = a + static_cast<int>(q - pair_prefix_d(a, v));
+    static_cast<T*>(g.C)[(long long)(a - g.a0) * v * v * v + c.off + (long long)b * v] =
+        static_cast<T>(val);
   } else if (EPI == EPI_PACK) {
     const int al = m / g.v, cc = m - al * g.v;
     if (c.x < al) return;
@@ -355,11 +404,21 @@ __device__ inline void tile_of(int bid, int nwg, int tiles_m, int group_m, int& 
   tile_from_linear(xcd_linear(bid, nwg), nwg, tiles_m, group_m, tm, tn);
 }
 
+// Tile of a K-banded product, whose tiles' K ranges shrink (kband 1) or grow
+// (kband 2) along the tile columns: the dispatch order itself, so that the
+// round-robin hands every XCD long and short tiles alike (contiguous runs per
+// XCD would give one XCD all the long ones), longest first.
+__device__ inline void tile_of_banded(int kband, int bid, int nwg, int tiles_m, int group_m,
+                                      int& tm, int& tn) {
+  tile_from_linear(kband == 2 ? nwg - 1 - bid : bid, nwg, tiles_m, group_m, tm, tn);
+}
+
 // K loop of one tile.  FAST: the tile lies inside M x N and its operands are
 // 16-byte aligned, so every full K-step is one vector load per chunk with no
 // test; only a ragged last K-step is masked.  Otherwise every load is masked.
 template <class Tr, int LA, int LB, bool FAST>
 __device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g, int m0, int n0,
+                                              int ks0, int ks1,
                                               typename Tr::T* sA0, typename Tr::T* sA1,
                                               typename Tr::T* sB0, typename Tr::T* sB1,
                                               typename Tr::Acc (&acc)[4][4],
@@ -374,13 +433,15 @@ __device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g,
   const int wave = tid >> 6;
   const int wm = (wave >> 1) * 64;
   const int wn = (wave & 1) * 64;
-  const int nk = (g.K + BK - 1) / BK;
+  const int nk = ks1;                   // one past the tile's last K-step
   const int nkf = FAST ? g.K / BK : 0;  // K-steps loaded without masks
 
   typename IA::Cursor ca;
   typename IB::Cursor cb;
   IA::init(ca, g.A, g.lda, m0, tid);
   IB::init(cb, g.B, g.ldb, n0, tid);
+  ca.p += ks0 * ca.kstep;
+  cb.p += ks0 * cb.kstep;
   typename IA::Chunk ra[IA::NCH];
   typename IB::Chunk rb[IB::NCH];
 
@@ -426,15 +487,15 @@ __device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g,
         }
   };
 
-  fetch(0);
+  fetch(ks0);
   IA::store(sA0, ra, tid);
   IB::store(sB0, rb, tid);
   __syncthreads();
-  int kt = 0;
+  int kt = ks0;
   for (;;) {
     const int kend = (Tr::kDrain && kt + g.drain_steps < nk) ? kt + g.drain_steps : nk;
     // Steady state, two K-steps per trip so the LDS stages stay compile-time
-    // (chunks hold an even number of steps, so kt is even here).
+    // (chunks hold an even number of steps, so kt - ks0 is even here).
     for (; kt + 2 <= kend && kt + 2 < nkf; kt += 2) {
       fetch(kt + 1);
       compute(sA0, sB0);
@@ -449,14 +510,15 @@ __device__ __forceinline__ void tile_mainloop(const GemmArgs<typename Tr::T>& g,
     }
     // Remaining steps of the chunk (masked loads where needed); stage parity follows kt.
     for (; kt < kend; ++kt) {
-      typename Tr::T* sa = (kt & 1) ? sA1 : sA0;
-      typename Tr::T* sb = (kt & 1) ? sB1 : sB0;
+      const int odd = (kt - ks0) & 1;
+      typename Tr::T* sa = odd ? sA1 : sA0;
+      typename Tr::T* sb = odd ? sB1 : sB0;
       const bool more = kt + 1 < nk;
       if (more) fetch(kt + 1);
       compute(sa, sb);
       if (more) {
-        IA::store((kt & 1) ? sA0 : sA1, ra, tid);
-        IB::store((kt & 1) ? sB0 : sB1, rb, tid);
+        IA::store(odd ? sA0 : sA1, ra, tid);
+        IB::store(odd ? sB0 : sB1, rb, tid);
       }
       __syncthreads();
     }
@@ -482,7 +544,7 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
   const int wn = (wave & 1) * 64;
 
   int tm, tn;
-  if (EPI == EPI_PACK) {
+  if (EPI == EPI_PACK || EPI == EPI_SYM) {
     // compact grid over the tiles on or above the a = b diagonal: tile row by
     // binary search over the row offsets, then columns from the row's first
     const int id = blockIdx.x;
@@ -493,12 +555,14 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
     }
     tm = lo;
     tn = pack_first_tile(tm, kBM, kBN, g.v) + (id - g.row_tiles[tm]);
+  } else if (g.kband) {
+    tile_of_banded(g.kband, blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   } else {
     tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   }
   const int m0 = tm * kBM;
   const int n0 = tn * kBN;
-  if (EPI == EPI_PACK) {
+  if (EPI == EPI_PACK || EPI == EPI_SYM) {
     // every column's b below every row's a: nothing of this tile is kept
     const int nlast = ((n0 + kBN < g.N) ? n0 + kBN : g.N) - 1;
     if (nlast / g.v < m0 / g.v) return;
@@ -514,11 +578,13 @@ __global__ __launch_bounds__(kThreads, Tr::kWaves) void gemm_kernel(GemmArgs<typ
       acc64[i][j] = f64x4{0, 0, 0, 0};
     }
 
+  int ks0, ks1;
+  k_band(g, n0, kBN, Tr::BK, ks0, ks1);
   const bool interior = (m0 + kBM <= g.M) && (n0 + kBN <= g.N);
   if (VEC && interior)
-    tile_mainloop<Tr, LA, LB, true>(g, m0, n0, sA[0], sA[1], sB[0], sB[1], acc, acc64);
+    tile_mainloop<Tr, LA, LB, true>(g, m0, n0, ks0, ks1, sA[0], sA[1], sB[0], sB[1], acc, acc64);
   else
-    tile_mainloop<Tr, LA, LB, false>(g, m0, n0, sA[0], sA[1], sB[0], sB[1], acc, acc64);
+    tile_mainloop<Tr, LA, LB, false>(g, m0, n0, ks0, ks1, sA[0], sA[1], sB[0], sB[1], acc, acc64);
 
   // Epilogue: lane holds column lane%16 of each 16x16 block, rows Tr::row_of(lane, r).
   const int col = lane & 15;

@@ -84,10 +84,13 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kc_direct_kernel(GemmArgs<t
     ks0 = split * g.split_steps;
     ks1 = ks0 + g.split_steps < nk_all ? ks0 + g.split_steps : nk_all;
     g.C = static_cast<double*>(g.C) + split * g.part_stride;
+  } else if (g.kband) {
+    tile_of_banded(g.kband, blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   } else {
     tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   }
   const int m0 = tm * BM, n0 = tn * kDBN;
+  if (EPI != EPI_PART && g.kband) k_band(g, n0, kDBN, BK, ks0, ks1);
 
   // Slabs: A rows 8*(wave + 8*j), j < JA; B rows 8*(wave + 8*j), j < 4.  The
   // swizzle of a lane depends on the slab's parity only (slab origin 8*s rows).
@@ -259,7 +262,8 @@ __device__ __forceinline__ int rc_pos(int i, int r) {
 
 template <class Tr, int EPI>
 __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<typename Tr::T> g) {
-  static_assert(EPI == EPI_PERM || EPI == EPI_PACK, "integral-block stores");
+  static_assert(EPI == EPI_PERM || EPI == EPI_PACK || EPI == EPI_UNPACK || EPI == EPI_SYM,
+                "integral-block stores");
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using Chunk = typename Tr::Chunk;
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
   const int wm = (wave >> 2) * 64;
   const int wn = (wave & 3) * 64;
   int tm, tn;
-  if (EPI == EPI_PACK) {
+  if (EPI == EPI_PACK || EPI == EPI_SYM) {
     // compact grid over the tiles on or above the a = b diagonal
     const int id = blockIdx.x;
     int lo = 0, hi = g.tiles_m - 1;
@@ -429,13 +433,22 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
   // epilogue: column groups of CH adjacent n (blocks j = CH*h .. CH*h + CH - 1).
   // EPI_PERM: m = (a, x), n = (y, d) -> C[a*N*v + y*v^2 + x*v + d];
   // EPI_PACK: m = (a - a0, c), n = (b - a0, d), kept for b >= a, at packed row
-  // pair(a, b) - pair(a0, a0): C[row*v^2 + c*v + d].
+  // pair(a, b) - pair(a0, a0): C[row*v^2 + c*v + d];
+  // EPI_UNPACK: m = pair(a, b) - pair(a0, a0) (m < m_keep), n = (c, d) ->
+  // C[(a - a0)*v^3 + c*v^2 + b*v + d].
   const long long v = g.v;
   const bool vec = (g.v % CH) == 0;
   constexpr int NG = 4 / CH;  // column groups per lane: 1 (float32) or 2 (float64)
   auto dst_of = [&](int m, int n) -> long long {  // -1: not stored
-    const int a = m / g.v, x = m - a * g.v;
     const int y = n / g.v, d = n - y * g.v;
+    if (EPI == EPI_UNPACK) {
+      if (m >= g.m_keep) return -1;
+      const long long q = pair_prefix_d(g.a0, v) + m;
+      const int a = pair_row(q, g.v);
+      const int b = a + static_cast<int>(q - pair_prefix_d(a, v));
+      return (long long)(a - g.a0) * v * v * v + (long long)y * v * v + (long long)b * v + d;
+    }
+    const int a = m / g.v, x = m - a * g.v;
     if (EPI == EPI_PERM) return (long long)a * g.N * v + (long long)y * v * v + (long long)x * v + d;
     if (y < a) return -1;
     const long long row = pair_prefix_d(g.a0 + a, v) - pair_prefix_d(g.a0, v) + (y - a);
@@ -459,6 +472,18 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_rc_direct_kernel(GemmArgs<t
           val[e] = static_cast<T>(s);
         }
         T* C = static_cast<T*>(g.C);
+        if constexpr (EPI == EPI_SYM) {
+          // the group's CH adjacent columns, and their mirrors down one column m
+          if (g.ldc % CH == 0) {
+            *reinterpret_cast<Chunk*>(C + (long long)m * g.ldc + nb) = val;
+          } else {
+#pragma unroll
+            for (int e = 0; e < CH; ++e) C[(long long)m * g.ldc + nb + e] = val[e];
+          }
+#pragma unroll
+          for (int e = 0; e < CH; ++e) C[(long long)(nb + e) * g.ldc + m] = val[e];
+          continue;
+        }
         if (vec) {
           // the group's CH columns share (y) and are adjacent in d
           const long long o0 = dst_of(m, nb);
@@ -516,8 +541,13 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kr_direct_kernel(GemmArgs<t
   const int wm = (wave >> 2) * 64;
   const int wn = (wave & 3) * 64;
   int tm, tn;
-  tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  if (g.kband)
+    tile_of_banded(g.kband, blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
+  else
+    tile_of(blockIdx.x, gridDim.x, g.tiles_m, g.group_m, tm, tn);
   const int m0 = tm * kDBM, n0 = tn * kDBN;
+  int ks0, ks1;  // this tile's K-steps
+  k_band(g, n0, kDBN, BK, ks0, ks1);
 
   // A: slabs of 8 rows, lane -> row lane/8, physical chunk lane%8 holding
   // logical chunk (lane%8) ^ ((row/2)%8)
@@ -592,7 +622,7 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kr_direct_kernel(GemmArgs<t
   const int slot = lane >> 4;
   const int r16 = lane & 15;
   const int offb = (wn + (CH == 4 ? 4 * r16 : 2 * r16)) * (int)sizeof(T);
-  const int nk = (g.K + BK - 1) / BK;
+  const int nk = ks1;
   const int nkf = g.K / BK;
   auto stage_in = [&](int kt) {
     if (kt < nkf)
@@ -600,12 +630,13 @@ __global__ __launch_bounds__(kDThreads, 1) void gemm_kr_direct_kernel(GemmArgs<t
     else
       issue_tail(kt);
   };
-  stage_in(0);
-  if (nk > 1) stage_in(1);
-  for (int k0 = 0; k0 < nk;) {
+  stage_in(ks0);
+  if (ks0 + 1 < nk) stage_in(ks0 + 1);
+  for (int k0 = ks0; k0 < nk;) {
     const int kend = (Tr::kDrain && k0 + g.drain_steps < nk) ? k0 + g.drain_steps : nk;
     for (int kt = k0; kt < kend; ++kt) {
-      d_wait_vm(kt + 1 < nkf ? LOADS : 0);
+      // step kt's direct loads have landed once only step kt+1's remain in flight
+      d_wait_vm(kt + 1 < nkf && kt + 1 < nk ? LOADS : 0);
       __builtin_amdgcn_s_barrier();
       if (kt + 2 < nk) stage_in(kt + 2);
       const unsigned char* st = lds + (kt % kDStages) * STAGE;

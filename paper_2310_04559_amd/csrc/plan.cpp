@@ -44,11 +44,14 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
   if (!opts) return CC_LADDER_OK;
   if (opts->a_block < 0 || opts->split_depth < 0 || opts->split_depth > 2) return CC_LADDER_EINVAL;
   if ((opts->flags & ~(CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE | CC_LADDER_CHECK_SYMMETRY |
-                       CC_LADDER_PLUS_MINUS)) != 0 ||
+                       CC_LADDER_PLUS_MINUS | CC_LADDER_SYMMETRIC_VECTORS)) != 0 ||
       opts->reserved != 0)
     return CC_LADDER_EINVAL;
-  // the symmetric/antisymmetric combinations rest on the pair-symmetry assertion
+  // the symmetric/antisymmetric combinations rest on the pair-symmetry assertion,
+  // the whole pair-pair integral on them
   if ((opts->flags & CC_LADDER_PLUS_MINUS) && !(opts->flags & CC_LADDER_PAIR_SYMMETRIC))
+    return CC_LADDER_EINVAL;
+  if ((opts->flags & CC_LADDER_SYMMETRIC_VECTORS) && !(opts->flags & CC_LADDER_PLUS_MINUS))
     return CC_LADDER_EINVAL;
   if (opts->split_slices != 0) {
     const int lo = precision == CC_LADDER_SPLIT_INT8 ? 4 : 2;
@@ -198,11 +201,19 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
     p.off_Tm = take(&cur, mm * p.ldm * es);
     p.off_Vp = take(&cur, np * p.ldp * es);
     p.off_Vm = take(&cur, nm * p.ldm * es);
-    if (precision == CC_LADDER_FP32) {
-      p.k_chunk = k_chunk ? k_chunk : 512;
-      p.off_L = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
+    if (precision == CC_LADDER_FP32) p.k_chunk = k_chunk ? k_chunk : 512;
+    p.gsym = (flags & CC_LADDER_SYMMETRIC_VECTORS) ? 1 : 0;
+    if (p.gsym) {
+      // symmetric vectors: packed vectors and the whole pair-pair integral (its
+      // side padded like the operand rows, pads zero) instead of a packed block
+      p.ldg = p.ldp;
+      p.off_Lp = take(&cur, static_cast<size_t>(P) * p.ldg * es);
+      p.off_G = take(&cur, static_cast<size_t>(p.ldg) * p.ldg * es);
+    } else {
+      if (precision == CC_LADDER_FP32)
+        p.off_L = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
+      p.off_V = take(&cur, blk * es);
     }
-    p.off_V = take(&cur, blk * es);
   } else {
   switch (precision) {
     case CC_LADDER_FP64:
@@ -271,9 +282,10 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   }
   if (p.pairsym || p.pairsym_adj) {
     // tile-row offsets of the packed build's compact grid (128-row tiles; 64 rows
-    // in the split form)
+    // in the split form), or of the upper-triangle grid of the pair-pair integral
     const size_t bm = precision == CC_LADDER_SPLIT_BF16 ? 64 : 128;
-    const size_t tiles_m = (static_cast<size_t>(n_a) * v + bm - 1) / bm;
+    const size_t rows_m = p.gsym ? static_cast<size_t>(p.ldg) : static_cast<size_t>(n_a) * v;
+    const size_t tiles_m = (rows_m + bm - 1) / bm;
     p.off_tiles = take(&cur, (tiles_m + 1) * sizeof(int));
   }
   p.bytes = cur;
@@ -324,15 +336,12 @@ int search_block(int n_max, size_t budget, int fixed, Layout layout, Plan* plan)
 
 }  // namespace
 
-int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
-              const cc_ladder_opts* opts, Plan* plan) {
-  int rc = check_dims(o, v, P);
-  if (rc) return rc;
-  rc = check_precision_opts(precision, opts);
-  if (rc) return rc;
+namespace {
+
+int make_plan_flags(int o, int v, int P, int precision, int backward, size_t budget,
+                    const cc_ladder_opts* opts, unsigned flags, Plan* plan) {
   const int slices = opts ? opts->split_slices : 0;
   const int depth = opts ? opts->split_depth : 0;
-  const unsigned flags = opts ? opts->flags : 0u;
   const int k_chunk = opts ? opts->k_chunk : 0;
   const int fixed = opts ? opts->a_block : 0;
   if ((flags & CC_LADDER_PAIR_SYMMETRIC) && !backward && fixed == 0) {
@@ -372,6 +381,23 @@ int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
   return search_block(v, budget, fixed, [&](int n_a, Plan* p) {
     return layout_plan(o, v, P, precision, backward, n_a, slices, depth, k_chunk, flags, p);
   }, plan);
+}
+
+}  // namespace
+
+int make_plan(int o, int v, int P, int precision, int backward, size_t budget,
+              const cc_ladder_opts* opts, Plan* plan) {
+  int rc = check_dims(o, v, P);
+  if (rc) return rc;
+  rc = check_precision_opts(precision, opts);
+  if (rc) return rc;
+  const unsigned flags = opts ? opts->flags : 0u;
+  rc = make_plan_flags(o, v, P, precision, backward, budget, opts, flags, plan);
+  // the whole pair-pair integral does not fit: the packed blocks instead
+  if (rc == CC_LADDER_ENOMEM && (flags & CC_LADDER_SYMMETRIC_VECTORS))
+    rc = make_plan_flags(o, v, P, precision, backward, budget, opts,
+                         flags & ~CC_LADDER_SYMMETRIC_VECTORS, plan);
+  return rc;
 }
 
 int choose_kc_tiling(long long M, long long N, bool tall, bool split, long long* main_rows) {

@@ -39,6 +39,10 @@ struct Plan {
   long long ldp = 0, ldm = 0;  // PLUS_MINUS: row strides of the c <= d and c < d operands
   size_t off_Tp = 0, off_Tm = 0;  // PLUS_MINUS: t+ [o(o+1)/2][ldp], t- [o(o-1)/2][ldm]
   size_t off_Vp = 0, off_Vm = 0;  // PLUS_MINUS: V+ [pairs a <= b][ldp], V- [pairs a < b][ldm]
+  int gsym = 0;         // PLUS_MINUS with symmetric vectors: whole pair-pair integral G
+  long long ldg = 0;    // its side: v(v+1)/2 rounded up to a multiple of 4
+  size_t off_Lp = 0;    // packed vectors Lp[x][pair(a,c)], a <= c ([P][ldg], pads zero)
+  size_t off_G = 0;     // G[ldg][ldg], symmetric
   int k_chunk = 0;      // float32 drain interval along the contracted index
   // operand copies made once per call (float32 / bf16 slice forms)
   size_t off_L = 0, off_t = 0, off_lam = 0;

@@ -12,7 +12,7 @@ pair-symmetric.
 
 Scratch comes from PyTorch: unless the caller's options carry a workspace,
 each call plans against a budget of half the memory PyTorch could hand out
-(at most 64 GiB) and allocates the planned bytes as a tensor, so the caching
+(at most 128 GiB) and allocates the planned bytes as a tensor, so the caching
 allocator serves repeated calls.  The backward never reuses the forward's
 workspace: it plans and allocates its own.
 """
@@ -22,7 +22,7 @@ import torch
 
 from . import native
 
-_BUDGET_CAP = 64 << 30
+_BUDGET_CAP = 128 << 30
 
 
 def _budget(device) -> int:
@@ -73,7 +73,8 @@ class LadderFn(torch.autograd.Function):
             opts = native.copy_opts(opts, workspace=None,
                                     flags=opts.flags & ~(native.CC_LADDER_PAIR_SYMMETRIC
                                                          | native.CC_LADDER_CHECK_SYMMETRY
-                                                         | native.CC_LADDER_PLUS_MINUS))
+                                                         | native.CC_LADDER_PLUS_MINUS
+                                                         | native.CC_LADDER_SYMMETRIC_VECTORS))
         P, v, _ = L.shape
         o = t.shape[0]
         run = _with_workspace(opts, o, v, P, precision, True, t.device)

@@ -57,6 +57,7 @@ CC_LADDER_PAIR_SYMMETRIC = 1
 CC_LADDER_EXCHANGE = 2
 CC_LADDER_CHECK_SYMMETRY = 4
 CC_LADDER_PLUS_MINUS = 8
+CC_LADDER_SYMMETRIC_VECTORS = 16
 CC_INTERMEDIATE_IJKL = 0
 CC_INTERMEDIATE_IJBK = 1
 CC_HOLE_LADDER = 2
@@ -121,7 +122,7 @@ def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_bud
               workspace: Optional[torch.Tensor] = None, trace=None,
               split_depth: int = 0, pair_symmetric: bool = False,
               exchange: bool = False, check_symmetry: bool = False,
-              plus_minus: bool = False) -> CcLadderOpts:
+              plus_minus: bool = False, symmetric_vectors: bool = False) -> CcLadderOpts:
     """``trace`` is a TRACE_FN.  The options keep references to the workspace
     tensor and the trace callback, so neither is freed while they are in use."""
     o = CcLadderOpts()
@@ -132,7 +133,8 @@ def make_opts(a_block: int = 0, split_slices: int = 0, k_chunk: int = 0, hbm_bud
     o.flags = ((CC_LADDER_PAIR_SYMMETRIC if pair_symmetric else 0)
                | (CC_LADDER_EXCHANGE if exchange else 0)
                | (CC_LADDER_CHECK_SYMMETRY if check_symmetry else 0)
-               | (CC_LADDER_PLUS_MINUS if plus_minus else 0))
+               | (CC_LADDER_PLUS_MINUS if plus_minus else 0)
+               | (CC_LADDER_SYMMETRIC_VECTORS if symmetric_vectors else 0))
     o.reserved = 0
     o.hbm_budget = int(hbm_budget)
     o._workspace_ref = None

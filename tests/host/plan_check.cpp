@@ -52,8 +52,12 @@ static void argument_checks() {
   cc_ladder_opts o{};
   o.flags = CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_EXCHANGE | CC_LADDER_CHECK_SYMMETRY;
   CHECK(check_precision_opts(0, &o) == CC_LADDER_OK);
-  o.flags = 16;  // no such flag
+  o.flags = 32;  // no such flag
   CHECK(check_precision_opts(0, &o) == CC_LADDER_EINVAL);
+  o.flags = CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_SYMMETRIC_VECTORS;  // needs PLUS_MINUS
+  CHECK(check_precision_opts(0, &o) == CC_LADDER_EINVAL);
+  o.flags |= CC_LADDER_PLUS_MINUS;
+  CHECK(check_precision_opts(0, &o) == CC_LADDER_OK);
   o = cc_ladder_opts{};
   o.workspace = reinterpret_cast<void*>(uintptr_t(4096 + 128));
   CHECK(check_precision_opts(0, &o) == CC_LADDER_EINVAL);  // misaligned workspace
@@ -104,7 +108,7 @@ static void plan_invariants(const Plan& p, int backward, size_t budget) {
   const size_t offs[] = {p.off_lamP, p.off_B, p.off_check, p.off_tx, p.off_dtx, p.off_L, p.off_t,
                          p.off_lam, p.off_L2, p.off_part, p.off_Lexp, p.off_texp, p.off_V, p.off_W,
                          p.off_Vs, p.off_Vexp, p.off_tiles, p.off_Tp, p.off_Tm, p.off_Vp,
-                         p.off_Vm};
+                         p.off_Vm, p.off_Lp, p.off_G};
   for (size_t off : offs) {
     CHECK(off % 256 == 0);
     CHECK(off == 0 || off < p.bytes);
@@ -115,7 +119,17 @@ static void plan_invariants(const Plan& p, int backward, size_t budget) {
     CHECK(p.ldp % 4 == 0 && p.ldm % 4 == 0);
     CHECK(p.ldp >= static_cast<long long>(p.v) * (p.v + 1) / 2);
     CHECK(p.ldm >= static_cast<long long>(p.v) * (p.v - 1) / 2);
-    CHECK(p.pairsym && !backward && p.off_Vp > p.off_Tp && p.off_V > 0);
+    CHECK(p.pairsym && !backward && p.off_Vp > p.off_Tp);
+    if (p.gsym) {
+      // the whole pair-pair integral instead of a packed block; its compact grid's
+      // tile offsets cover its ldg rows
+      CHECK(p.ldg == p.ldp && p.off_G > p.off_Lp && p.off_Lp >= p.off_Vm && p.off_V == 0);
+      CHECK(p.off_tiles > p.off_G);
+    } else {
+      CHECK(p.off_V > 0 && p.off_G == 0);
+    }
+  } else {
+    CHECK(!p.gsym);
   }
 }
 
@@ -130,7 +144,7 @@ static void planner_sweep() {
     const int backward = static_cast<int>(rng() % 2);
     const bool split = precision == CC_LADDER_SPLIT_BF16 || precision == CC_LADDER_SPLIT_INT8;
     cc_ladder_opts opts{};
-    opts.flags = static_cast<unsigned>(rng() % 16);
+    opts.flags = static_cast<unsigned>(rng() % 32);
     if (precision == CC_LADDER_SPLIT_INT8)
       opts.split_slices = (rng() % 3 == 0) ? 0 : 4 + static_cast<int>(rng() % 2);
     else
@@ -141,7 +155,8 @@ static void planner_sweep() {
     Plan p;
     const int rc = make_plan(o, v, P, precision, backward, budget, &opts, &p);
     const bool pm = (opts.flags & CC_LADDER_PLUS_MINUS) != 0;
-    if (pm && !(opts.flags & CC_LADDER_PAIR_SYMMETRIC)) {
+    if ((pm && !(opts.flags & CC_LADDER_PAIR_SYMMETRIC)) ||
+        ((opts.flags & CC_LADDER_SYMMETRIC_VECTORS) && !pm)) {
       CHECK(rc == CC_LADDER_EINVAL);
       continue;
     }
@@ -172,7 +187,7 @@ static void planner_sweep() {
       CHECK(rc2 == CC_LADDER_OK && q.bytes >= p.bytes);
     }
   }
-  CHECK(plans > 1000);
+  CHECK(plans > 600);
   // occupied-index terms
   for (int it = 0; it < 2000; ++it) {
     const int which = static_cast<int>(rng() % 3);

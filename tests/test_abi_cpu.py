@@ -383,6 +383,53 @@ def test_planner_plus_minus_footprint(native):
         assert nbytes == want, (prec, nbytes, want)
 
 
+def test_planner_symmetric_vectors_footprint(native):
+    # t+- and V+- as above, then the packed vectors [P][ldg] and the whole
+    # pair-pair integral [ldg][ldg] (ldg = v(v+1)/2 rounded to 4) in place of the
+    # packed block (and of the float32 copy of L), and the tile offsets of its
+    # upper-triangle grid
+    def r256(x):
+        return (x + 255) // 256 * 256
+
+    o, v, P, n_a = 5, 21, 30, 6
+    for prec, es in (("fp64", 8), ("fp32", 4)):
+        opts = native.make_opts(a_block=n_a, pair_symmetric=True, plus_minus=True,
+                                symmetric_vectors=True)
+        nbytes, blk = native.cc_ladder_workspace_query(o, v, P, prec, opts=opts)
+        assert blk == n_a
+        kp, km = v * (v + 1) // 2, v * (v - 1) // 2
+        ldp, ldm = (kp + 3) // 4 * 4, (km + 3) // 4 * 4
+        npk = n_a * v - n_a * (n_a - 1) // 2
+        want = (r256(o * (o + 1) // 2 * ldp * es) + r256(o * (o - 1) // 2 * ldm * es)
+                + r256(npk * ldp * es) + r256((npk - n_a) * ldm * es))
+        want += r256(P * ldp * es) + r256(ldp * ldp * es)
+        want += r256(((ldp + 127) // 128 + 1) * 4)
+        assert nbytes == want, (prec, nbytes, want)
+        # a budget that the whole integral alone fills: the packed blocks of one
+        # virtual, as without the flag
+        small = ldp * ldp * es
+        one = dict(a_block=1, pair_symmetric=True, plus_minus=True)
+        a = native.cc_ladder_workspace_query(
+            o, v, P, prec, hbm_budget=small, opts=native.make_opts(symmetric_vectors=True, **one))
+        b = native.cc_ladder_workspace_query(o, v, P, prec, hbm_budget=small,
+                                             opts=native.make_opts(**one))
+        assert a == b and a[0] <= small
+
+
+def test_symmetric_vectors_needs_plus_minus(native):
+    with pytest.raises(native.LadderError) as e:
+        native.cc_ladder_workspace_query(
+            3, 10, 5, "fp64", opts=native.make_opts(pair_symmetric=True, symmetric_vectors=True))
+    assert e.value.code == native.CC_LADDER_EINVAL
+    # the adjoint plans as with pair symmetry alone
+    a = native.cc_ladder_workspace_query(
+        3, 10, 5, "fp64", backward=True,
+        opts=native.make_opts(pair_symmetric=True, plus_minus=True, symmetric_vectors=True))
+    b = native.cc_ladder_workspace_query(3, 10, 5, "fp64", backward=True,
+                                         opts=native.make_opts(pair_symmetric=True))
+    assert a == b
+
+
 def test_plus_minus_needs_pair_symmetry(native):
     with pytest.raises(native.LadderError) as e:
         native.cc_ladder_workspace_query(3, 10, 5, "fp64", opts=native.make_opts(plus_minus=True))

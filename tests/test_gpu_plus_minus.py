@@ -84,6 +84,81 @@ def test_plus_minus_c2_workload_whole_tensor(gpu_lib):
         assert err < TOL[precision]
 
 
+def _symmetric_vectors(L):
+    return 0.5 * (L + L.transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (4, 44, 131, 13),
+                                           (3, 130, 17, 40), (2, 3, 2, 0), (16, 64, 200, 1),
+                                           (1, 33, 9, 0), (7, 1, 4, 0), (23, 65, 50, 30)])
+def test_symmetric_vectors(gpu_lib, o, v, P, a_block, precision):
+    # symmetric Cholesky vectors: V+- gathered from the whole pair-pair integral
+    # (ragged 32-wide pair tiles, pair counts that are not multiples of the
+    # 128 x 128 / 128 x 256 tiles of its upper-triangle grid, blocks of several sizes)
+    announce("forward-pm-symv", o, v, P, "a_block", a_block, "precision", precision)
+    L, t, _ = random_general(o, v, P, 1500 + o + v)
+    L, t = _symmetric_vectors(L), _pair_symmetric(t)
+    kw = dict(a_block=a_block, pair_symmetric=True, plus_minus=True)
+    with_g = gpu_lib.cc_ladder_workspace_query(o, v, P, precision,
+                                               opts=gpu_lib.make_opts(symmetric_vectors=True, **kw))
+    without = gpu_lib.cc_ladder_workspace_query(o, v, P, precision, opts=gpu_lib.make_opts(**kw))
+    if v >= 8:  # (a few virtuals: the two footprints can coincide)
+        assert with_g != without  # the whole-integral plan is the one taken
+    R0 = np.random.default_rng(11).standard_normal(t.shape)
+    inc = oracle.ladder_forward(L, t)
+    got = run(gpu_lib, L, t, R0, precision, a_block=a_block, symmetric_vectors=True)
+    err = rel_fro(got - R0, inc)
+    print(f"CASE forward-pm-symv error {err:.2e}", flush=True)
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_symmetric_vectors_integer_exact_and_exchange(gpu_lib, precision):
+    # integer symmetric vectors and pair-symmetric integer amplitudes: exact;
+    # the exchange partner from the same integral within tolerance
+    announce("forward-pm-symv-int", precision)
+    L, t = integer_inputs(4, 11, 5, 81)
+    L, t = L + L.transpose(0, 2, 1), t + t.transpose(1, 0, 3, 2)
+    got = run(gpu_lib, L, t, np.zeros_like(t), precision, a_block=4, symmetric_vectors=True)
+    assert np.array_equal(got, oracle.ladder_forward(L, t))
+    L, t, _ = random_general(9, 37, 101, 47)
+    L, t = _symmetric_vectors(L), _pair_symmetric(t)
+    got = run(gpu_lib, L, t, np.zeros_like(t), precision, a_block=7, exchange=True,
+              symmetric_vectors=True)
+    assert rel_fro(got, oracle.exchange_forward(L, t)) < TOL[precision]
+
+
+def test_symmetric_vectors_checks_and_fallback(gpu_lib):
+    announce("forward-pm-symv-checks")
+    o, v, P = 4, 29, 13
+    L, t, _ = random_general(o, v, P, 48)
+    t = _pair_symmetric(t)
+    Ls = _symmetric_vectors(L)
+    kw = dict(pair_symmetric=True, plus_minus=True, symmetric_vectors=True)
+    # the symmetry check rejects general vectors with the outputs untouched, and
+    # passes symmetric ones
+    R = torch.zeros(t.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_residual(dev(L), dev(t), R, 0,
+                                   opts=gpu_lib.make_opts(check_symmetry=True, **kw))
+    assert e.value.code == gpu_lib.CC_LADDER_EINVAL
+    torch.cuda.synchronize()
+    assert float(R.abs().max()) == 0.0
+    ref = oracle.ladder_forward(Ls, t)
+    got = run(gpu_lib, Ls, t, np.zeros_like(t), 0, check_symmetry=True, symmetric_vectors=True)
+    assert rel_fro(got, ref) < TOL[0]
+    # without PLUS_MINUS the flag is rejected
+    with pytest.raises(gpu_lib.LadderError) as e:
+        gpu_lib.cc_ladder_residual(dev(Ls), dev(t), R, 0,
+                                   opts=gpu_lib.make_opts(pair_symmetric=True, symmetric_vectors=True))
+    assert e.value.code == gpu_lib.CC_LADDER_EINVAL
+    # a budget the whole integral does not fit: the packed blocks, same result
+    ldg = (v * (v + 1) // 2 + 3) // 4 * 4
+    got = run(gpu_lib, Ls, t, np.zeros_like(t), 0, hbm_budget=ldg * ldg * 8, symmetric_vectors=True)
+    assert rel_fro(got, ref) < TOL[0]
+
+
 def test_plus_minus_rejections(gpu_lib):
     announce("forward-pm-rejections")
     L, t, _ = random_general(3, 10, 4, 46)

@@ -21,10 +21,13 @@ from tests.gpu_common import TOL, TOL_SPLIT_WORKLOAD, announce, dev, host, rel_f
 pytestmark = pytest.mark.gpu
 
 # (precision, split slices, pair-symmetric) -> tolerance over the whole tensor
-# ("pm": the symmetric/antisymmetric combinations over i <= j, a <= b, c <= d)
+# ("pm": the symmetric/antisymmetric combinations over i <= j, a <= b, c <= d;
+# "pmv": the same gathered from the whole pair-pair integral of the workload's
+# symmetric Cholesky vectors)
 FORMS = [(0, 0, False, TOL[0]), (1, 0, False, TOL[1]), (2, 4, False, TOL_SPLIT_WORKLOAD[4]),
          (2, 2, False, TOL_SPLIT_WORKLOAD[2]), (0, 0, True, TOL[0]), (1, 0, True, TOL[1]),
          (2, 4, True, TOL_SPLIT_WORKLOAD[4]), (0, 0, "pm", TOL[0]), (1, 0, "pm", TOL[1]),
+         (0, 0, "pmv", TOL[0]), (1, 0, "pmv", TOL[1]),
          (3, 5, False, TOL[2]), (3, 5, True, TOL[2])]
 
 
@@ -35,7 +38,8 @@ def _check_forms(native, name, Ld, td, ref):
         R = torch.zeros_like(td)
         native.cc_ladder_residual(Ld, td, R, precision,
                                   opts=native.make_opts(split_slices=slices, pair_symmetric=bool(sym),
-                                                        plus_minus=sym == "pm"))
+                                                        plus_minus=sym in ("pm", "pmv"),
+                                                        symmetric_vectors=sym == "pmv"))
         torch.cuda.synchronize()
         if sym:
             # entries a != b are stored twice from one computed value: exact mirrors
