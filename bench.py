@@ -42,8 +42,9 @@ METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 
 # (eq. vfunction2) with the same nominal flops.
 # The *_pm forms contract the symmetric and antisymmetric combinations t+- with
 # V+- = (ac|bd) +- (ad|bc) over i <= j, a <= b, c <= d (pair-symmetric amplitudes);
-# the *_pm_symv forms gather V+- from the whole pair-pair integral of the
-# workload's symmetric Cholesky vectors (built over its upper triangle).
+# the *_symv forms gather the packed rows (*_pairsym_symv) or V+- (*_pm_symv)
+# from the whole pair-pair integral of the workload's symmetric Cholesky vectors
+# (built over its upper triangle).
 FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16": ("split_bf16", 4, False, False),
          "split_bf16_s2": ("split_bf16", 2, False, False),
@@ -52,6 +53,7 @@ FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16_pairsym": ("split_bf16", 4, True, False),
          "fp64_pm": ("fp64", 0, "pm", False), "fp32_pm": ("fp32", 0, "pm", False),
          "fp64_pm_symv": ("fp64", 0, "pmv", False), "fp32_pm_symv": ("fp32", 0, "pmv", False),
+         "fp64_pairsym_symv": ("fp64", 0, "sv", False), "fp32_pairsym_symv": ("fp32", 0, "sv", False),
          "fp64_exchange": ("fp64", 0, False, True), "fp32_exchange": ("fp32", 0, False, True),
          "split_bf16_exchange": ("split_bf16", 4, False, True),
          "split_int8": ("split_int8", 5, False, False),
@@ -96,7 +98,7 @@ def executed_flops(form, o, v, P):
         return 2.0 * P * v4, 2.0 * o * o * v4
     npk = v * (v + 1) / 2.0
     build = 2.0 * P * v * v * npk
-    if sym == "pmv":
+    if sym in ("pmv", "sv"):
         build = P * npk * (npk + 1)  # the pair-pair integral's upper triangle
     if sym in ("pm", "pmv"):
         nm = v * (v - 1) / 2.0
@@ -211,7 +213,8 @@ def form_opts(native, form, **kw):
     """The library options of a form (plus workspace, trace, ... in kw)."""
     slices, sym, exchange = FORMS[form][1:]
     return native.make_opts(split_slices=slices, pair_symmetric=bool(sym), exchange=exchange,
-                            plus_minus=sym in ("pm", "pmv"), symmetric_vectors=sym == "pmv", **kw)
+                            plus_minus=sym in ("pm", "pmv"),
+                            symmetric_vectors=sym in ("pmv", "sv"), **kw)
 
 
 def bench_form(native, form, L, t, R, out, ws_bytes, steps, warmup, o, v, P):
@@ -303,10 +306,13 @@ def cpu_baseline(inp, target_s=15.0):
                       f"({k}/{v} of its flops, {dt:.1f} s)"}
 
 
-def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pairsym")):
+def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pairsym",
+                                        "fp64_pairsym_symv", "fp32_pairsym_symv")):
     """The adjoint on the gradient workload (o=30, v=300, P=900); its lam and t
-    are pair-symmetric, so the *_pairsym forms (one dL term added twice) apply
-    and report effective TFLOP/s on the same nominal count."""
+    are pair-symmetric, so the *_pairsym forms (the half-written W block) apply
+    and report effective TFLOP/s on the same nominal count; its vectors are
+    symmetric, so the *_symv forms gather the packed rows from the pair-pair
+    integral."""
     import numpy as np
     import torch
 
@@ -326,13 +332,16 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
     budget = int(min(free // 2, 128 << 30))
     for form in forms:
         prec = native.PRECISIONS[form.split("_")[0]]
-        sym = form.endswith("_pairsym")
+        sym = "_pairsym" in form
+        symv = form.endswith("_symv")
         timer = PhaseTimer(native, stream)
         # the caller's workspace, allocated once outside the timed calls
-        nbytes, _ = native.cc_ladder_workspace_query(o, v, P, prec, backward=True, hbm_budget=budget,
-                                                     opts=native.make_opts(pair_symmetric=sym))
+        nbytes, _ = native.cc_ladder_workspace_query(
+            o, v, P, prec, backward=True, hbm_budget=budget,
+            opts=native.make_opts(pair_symmetric=sym, symmetric_vectors=symv))
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        opts = native.make_opts(trace=timer.fn, pair_symmetric=sym, workspace=ws)
+        opts = native.make_opts(trace=timer.fn, pair_symmetric=sym, symmetric_vectors=symv,
+                                workspace=ws)
         dL = torch.zeros_like(L)
         dt = torch.zeros_like(t)
         native.cc_ladder_backward(L, t, lam, dL, dt, prec, opts=opts)  # warm-up, also the result
@@ -356,7 +365,7 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
                      "phases_ms_per_step": {k: d["ms_total"] / steps for k, d in timer.summary().items()}}
         log(f"adjoint {form}: {ms:.1f} ms {res[form]['tflops']:.1f} TFLOP/s "
             f"phases {json.dumps(res[form]['phases_ms_per_step'])}")
-        del ws
+        del ws, opts, timer
         del dL, dt
     return res
 
@@ -545,7 +554,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_int8,split_bf16_s2,fp64_pairsym,"
-                                       "fp64_pm,fp32_pm,fp64_pm_symv,fp32_pm_symv,split_bf16_pairsym,"
+                                       "fp64_pairsym_symv,fp64_pm,fp32_pm,fp64_pm_symv,fp32_pm_symv,"
+                                       "split_bf16_pairsym,"
                                        "split_int8_pairsym,fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--budget-gib", type=float, default=128.0,

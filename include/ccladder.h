@@ -130,21 +130,24 @@ typedef enum {
                                         PAIR_SYMMETRIC; EUNSUPPORTED in the split forms; the
                                         adjoint ignores it. */
 
-#define CC_LADDER_SYMMETRIC_VECTORS 16u /* with PLUS_MINUS: the caller asserts L[x][a][c] ==
+#define CC_LADDER_SYMMETRIC_VECTORS 16u /* with PAIR_SYMMETRIC: the caller asserts L[x][a][c] ==
                                         L[x][c][a] (real orbitals give one symmetric Cholesky
                                         factor for both pair indices, Sec. "The CC ansatz",
                                         eq. cholesky).  The integral is then the symmetric matrix
                                         G[{a,c}][{b,d}] = sum_x L[x][a][c] L[x][b][d] over the
-                                        v(v+1)/2 unordered pairs, built once over its upper
-                                        triangle (the 8-fold permutational symmetry: a quarter of
-                                        the packed build's flops), and each block's V+- is
-                                        gathered from it.  G is kept whole in scratch, a square of
-                                        v(v+1)/2 (rounded up to a multiple of 4) elements of the
-                                        form's type (34 GB in float64 at v = 360); when it does
-                                        not fit the budget the flag changes nothing.  With
-                                        CHECK_SYMMETRY, L is checked as well:
-                                        EINVAL when some |L[x][a][c] - L[x][c][a]| exceeds
-                                        2^-40 max|L|.  EINVAL without PLUS_MINUS. */
+                                        v(v+1)/2 unordered pairs, built once per call over its
+                                        upper triangle (the 8-fold permutational symmetry: a
+                                        quarter of the packed build's flops), and each block's
+                                        packed rows (a,b), a <= b (or, with PLUS_MINUS, its V+-)
+                                        are gathered from it.  FP64 and FP32, forward and
+                                        adjoint; the split forms ignore it.  G is kept whole in
+                                        scratch, a square of v(v+1)/2 (rounded up to a multiple
+                                        of 4) elements of the form's type (34 GB in float64 at
+                                        v = 360) plus the packed vectors; when it does not fit the
+                                        budget the flag changes nothing.  With CHECK_SYMMETRY, L
+                                        is checked as well: EINVAL when some |L[x][a][c] -
+                                        L[x][c][a]| exceeds 2^-40 max|L|.  EINVAL without
+                                        PAIR_SYMMETRIC. */
 
 /* Kernel phases reported to an optional trace hook. */
 typedef enum {

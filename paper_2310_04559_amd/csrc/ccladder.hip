@@ -563,17 +563,21 @@ __global__ __launch_bounds__(256) void pack_sym_kernel(const double* __restrict_
   }
 }
 
-// The combinations of a block's integral rows, gathered from the whole
-// pair-pair integral G of symmetric vectors (G[p][q] = G[q][p], p, q unordered
-// pairs): the rows (a, b), a <= b, a from a0, of X_ab[c][d] = (ac|bd) =
-// G[{a,c}][{b,d}] go into plus/minus exactly as in pm_rows (wdiag 2, sm 1).
+// A block's integral rows, gathered from the whole pair-pair integral G of
+// symmetric vectors (G[p][q] = G[q][p], p, q unordered pairs): the rows (a, b),
+// a <= b, a from a0, of X_ab[c][d] = (ac|bd) = G[{a,c}][{b,d}], either whole
+// (GATHER_ROWS: plus[r][c*v + d], the packed block of the pair-symmetric
+// forward and adjoint) or combined into plus/minus exactly as in pm_rows
+// (GATHER_PM: wdiag 2, sm 1).
 // Work item w = (tile pair C <= D, row r), the row inner: workgroups that run
 // together on one XCD take consecutive rows, the same a with consecutive b.
 // Every element of the two 32 x 32 tiles is read in an orientation of G that
 // keeps 32 lanes on one contiguous run where one exists: along d in row {a,c}
 // when d >= b; along c in row {b,d} when d < b and c >= a; otherwise (c < a,
 // d < b) element by element, where neighbouring rows b share the cache lines.
-template <typename T>
+enum { GATHER_PM = 0, GATHER_ROWS = 1 };
+
+template <int MODE, typename T>
 __global__ __launch_bounds__(256) void pm_gather_kernel(const T* __restrict__ G, long long ldg,
                                                         long long nrows, int a0, int v, int tiles,
                                                         T* __restrict__ plus, long long ldp,
@@ -616,18 +620,30 @@ __global__ __launch_bounds__(256) void pm_gather_kernel(const T* __restrict__ G,
       }
     };
     load(xs, c0, d0);
-    load(ys, d0, c0);
+    if (MODE == GATHER_PM || D != C) load(ys, d0, c0);
     __syncthreads();
+    if (MODE == GATHER_ROWS) {
+      // X[C][D] and X[D][C] along contiguous d
+      T* row = plus + r * ldp;
 #pragma unroll
-    for (int k = ty; k < kSwapTile; k += 8) {
-      const int c = c0 + k, d = d0 + tx;
-      if (c < v && d < v && c <= d) {
-        const double xcd = xs[k][tx], xdc = ys[tx][k];
-        const long long kp = pp(c) + (d - c);
-        plus[r * ldp + kp] = static_cast<T>(c == d ? 2.0 * xcd : xcd + xdc);
-        if (rm >= 0 && c < d) {
-          const long long km = pair_prefix_d(c, v - 1) + (d - c - 1);
-          minus[rm * ldm + km] = static_cast<T>(xcd - xdc);
+      for (int k = ty; k < kSwapTile; k += 8) {
+        if (c0 + k < v && d0 + tx < v)
+          row[(long long)(c0 + k) * v + d0 + tx] = static_cast<T>(xs[k][tx]);
+        if (D != C && d0 + k < v && c0 + tx < v)
+          row[(long long)(d0 + k) * v + c0 + tx] = static_cast<T>(ys[k][tx]);
+      }
+    } else {
+#pragma unroll
+      for (int k = ty; k < kSwapTile; k += 8) {
+        const int c = c0 + k, d = d0 + tx;
+        if (c < v && d < v && c <= d) {
+          const double xcd = xs[k][tx], xdc = ys[tx][k];
+          const long long kp = pp(c) + (d - c);
+          plus[r * ldp + kp] = static_cast<T>(c == d ? 2.0 * xcd : xcd + xdc);
+          if (rm >= 0 && c < d) {
+            const long long km = pair_prefix_d(c, v - 1) + (d - c - 1);
+            minus[rm * ldm + km] = static_cast<T>(xcd - xdc);
+          }
         }
       }
     }
@@ -635,16 +651,31 @@ __global__ __launch_bounds__(256) void pm_gather_kernel(const T* __restrict__ G,
   }
 }
 
-template <typename T>
+template <int MODE, typename T>
 int pm_gather(const T* G, long long ldg, long long nrows, int a0, int v, T* plus, long long ldp,
               T* minus, long long ldm, hipStream_t s) {
   if (nrows <= 0) return CC_LADDER_OK;
   const int tiles = (v + kSwapTile - 1) / kSwapTile;
   const long long work = nrows * ((long long)tiles * (tiles + 1) / 2);
   const long long blocks = std::min<long long>(work, 65536);
-  hipLaunchKernelGGL((pm_gather_kernel<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, G,
-                     ldg, nrows, a0, v, tiles, plus, ldp, minus, ldm);
+  hipLaunchKernelGGL((pm_gather_kernel<MODE, T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                     s, G, ldg, nrows, a0, v, tiles, plus, ldp, minus, ldm);
   return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
+// Symmetric vectors: G[p][q] = sum_x Lp[x][p] Lp[x][q] over the unordered pairs,
+// the tiles on or above the diagonal (each stored with its mirror), traced as
+// the build of block 0.
+template <class Tr>
+int build_pair_integral(const Plan& pl, const typename Tr::T* Lp, typename Tr::T* G,
+                        int* row_tiles, const Tracer& tr, hipStream_t s) {
+  const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  const int n = static_cast<int>(pl.ldg);
+  tr(CC_LADDER_PHASE_BUILD, 0, 0);
+  const int rc = launch_gemm<Tr, RC, RC, EPI_SYM>(Lp, pl.ldg, Lp, pl.ldg, G, pl.ldg, n, n, pl.P, 1,
+                                                  drain, s, 0, 0, row_tiles);
+  tr(CC_LADDER_PHASE_BUILD, 0, 1);
+  return rc;
 }
 
 template <typename Out>
@@ -856,22 +887,31 @@ int check_vectors_symmetric(const double* L, int P, int v, unsigned long long* b
 
 template <class Tr>
 int forward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t, double* R,
-                   typename Tr::T* V, int* row_tiles, const Tracer& tr, hipStream_t s) {
+                   typename Tr::T* V, int* row_tiles, const Tracer& tr, hipStream_t s,
+                   const typename Tr::T* Lp = nullptr, typename Tr::T* G = nullptr) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
   const int drain = Tr::kDrain ? pl.k_chunk / Tr::BK : 0;
+  if (pl.gsym) {
+    const int rc = build_pair_integral<Tr>(pl, Lp, G, row_tiles, tr, s);
+    if (rc) return rc;
+  }
   for (int blk = 0; blk < pl.nblocks; ++blk) {
     int a0, na;
     block_range(pl, blk, &a0, &na);
     if (na <= 0) continue;
     if (pl.pairsym) {
       // packed rows (a,b), a in the block, b >= a: columns (b,d) from b = a0 on
+      // (or, with symmetric vectors, gathered from the pair-pair integral)
       const long long off = (long long)a0 * v;
       const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
       tr(CC_LADDER_PHASE_BUILD, blk, 0);
-      int rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
-                                                 static_cast<int>((long long)(v - a0) * v), P, v,
-                                                 drain, s, o, a0, row_tiles);
+      int rc = pl.gsym ? pm_gather<GATHER_ROWS>(static_cast<const typename Tr::T*>(G), pl.ldg,
+                                                npairs, a0, v, V, v2,
+                                                static_cast<typename Tr::T*>(nullptr), 0, s)
+                       : launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
+                                                           static_cast<int>((long long)(v - a0) * v),
+                                                           P, v, drain, s, o, a0, row_tiles);
       tr(CC_LADDER_PHASE_BUILD, blk, 1);
       if (rc) return rc;
       // R[(ij)][(ab)] and R[(ji)][(ba)] += t[(ij)][(cd)] . V_A[pair(a,b)][(cd)]
@@ -916,13 +956,7 @@ int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr
   const int kp = static_cast<int>((long long)v * (v + 1) / 2);
   const int km = static_cast<int>((long long)v * (v - 1) / 2);
   if (pl.gsym) {
-    // symmetric vectors: G[p][q] = sum_x Lp[x][p] Lp[x][q] over the unordered
-    // pairs, the tiles on or above the diagonal (each stored with its mirror)
-    tr(CC_LADDER_PHASE_BUILD, 0, 0);
-    const int n = static_cast<int>(pl.ldg);
-    const int rc = launch_gemm<Tr, RC, RC, EPI_SYM>(Lp, pl.ldg, Lp, pl.ldg, G, pl.ldg, n, n, P, 1,
-                                                    drain, s, 0, 0, row_tiles);
-    tr(CC_LADDER_PHASE_BUILD, 0, 1);
+    const int rc = build_pair_integral<Tr>(pl, Lp, G, row_tiles, tr, s);
     if (rc) return rc;
   }
   for (int blk = 0; blk < pl.nblocks; ++blk) {
@@ -935,8 +969,8 @@ int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr
     tr(CC_LADDER_PHASE_BUILD, blk, 0);
     int rc;
     if (pl.gsym) {
-      rc = pm_gather(static_cast<const typename Tr::T*>(G), pl.ldg, np, a0, v, Vp, pl.ldp, Vm,
-                     pl.ldm, s);
+      rc = pm_gather<GATHER_PM>(static_cast<const typename Tr::T*>(G), pl.ldg, np, a0, v, Vp,
+                                pl.ldp, Vm, pl.ldm, s);
     } else {
       rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
                                              static_cast<int>((long long)(v - a0) * v), P, v,
@@ -961,7 +995,8 @@ int forward_blocks_pm(const Plan& pl, const typename Tr::T* L, const typename Tr
 template <class Tr>
 int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::T* t,
                     const typename Tr::T* lam, double* dL, double* dt, char* base,
-                    const Tracer& tr, hipStream_t s) {
+                    const Tracer& tr, hipStream_t s, const typename Tr::T* Lp = nullptr,
+                    typename Tr::T* G = nullptr) {
   using T = typename Tr::T;
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
@@ -974,7 +1009,8 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
   T* lamP = sym ? reinterpret_cast<T*>(base + pl.off_lamP) : nullptr;
   int* row_tiles = sym ? reinterpret_cast<int*>(base + pl.off_tiles) : nullptr;
   if (sym) {
-    const int rc = fill_zero(Bacc, (long long)o * o * v2, s);
+    int rc = fill_zero(Bacc, (long long)o * o * v2, s);
+    if (!rc && pl.gsym) rc = build_pair_integral<Tr>(pl, Lp, G, row_tiles, tr, s);
     if (rc) return rc;
   }
   for (int blk = 0; blk < pl.nblocks; ++blk) {
@@ -988,9 +1024,11 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
     int rc;
     if (sym) {
       tr(CC_LADDER_PHASE_BUILD, blk, 0);
-      rc = launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
-                                             static_cast<int>((long long)(v - a0) * v), P, v,
-                                             drain, s, o, a0, row_tiles);
+      rc = pl.gsym ? pm_gather<GATHER_ROWS>(static_cast<const T*>(G), pl.ldg, npairs, a0, v, V, v2,
+                                            static_cast<T*>(nullptr), 0, s)
+                   : launch_gemm<Tr, RC, RC, EPI_PACK>(L + off, v2, L + off, v2, V, 0, na * v,
+                                                       static_cast<int>((long long)(v - a0) * v), P,
+                                                       v, drain, s, o, a0, row_tiles);
       tr(CC_LADDER_PHASE_BUILD, blk, 1);
       if (rc) return rc;
       // B[(ij)][(cd)] += sum_(ab packed) w lam[(ij)][(ab)] V_A[pair(a,b)][(cd)]
@@ -1281,20 +1319,32 @@ int residual_body(const Plan& pl, const double* L, const double* t, double* R, i
     t = tx;
   }
   switch (precision) {
-    case CC_LADDER_FP64:
+    case CC_LADDER_FP64: {
+      double* Lp = pl.gsym ? reinterpret_cast<double*>(base + pl.off_Lp) : nullptr;
+      if (pl.gsym) {
+        tr(CC_LADDER_PHASE_PREP, 0, 0);
+        rc = pack_sym(L, Lp, P, v, pl.ldg, stream);
+        tr(CC_LADDER_PHASE_PREP, 0, 1);
+        if (rc) return rc;
+      }
       return forward_blocks<TrF64>(pl, L, t, R, reinterpret_cast<double*>(base + pl.off_V),
-                                   reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
+                                   reinterpret_cast<int*>(base + pl.off_tiles), tr, stream, Lp,
+                                   pl.gsym ? reinterpret_cast<double*>(base + pl.off_G) : nullptr);
+    }
     case CC_LADDER_FP32: {
-      float* L32 = reinterpret_cast<float*>(base + pl.off_L);
+      // (with symmetric vectors the build reads only the packed float32 vectors)
+      float* L32 = pl.gsym ? nullptr : reinterpret_cast<float*>(base + pl.off_L);
       float* t32 = reinterpret_cast<float*>(base + pl.off_t);
+      float* Lp = pl.gsym ? reinterpret_cast<float*>(base + pl.off_Lp) : nullptr;
       tr(CC_LADDER_PHASE_PREP, 0, 0);
-      rc = to_f32(L, L32, (size_t)P * v * v, stream);
+      rc = pl.gsym ? pack_sym(L, Lp, P, v, pl.ldg, stream) : to_f32(L, L32, (size_t)P * v * v, stream);
       if (!rc)
         rc = pl.exchange ? swap_cd(t, t32, o, v, stream) : to_f32(t, t32, (size_t)o * o * v * v, stream);
       tr(CC_LADDER_PHASE_PREP, 0, 1);
       if (rc) return rc;
       return forward_blocks<TrF32>(pl, L32, t32, R, reinterpret_cast<float*>(base + pl.off_V),
-                                   reinterpret_cast<int*>(base + pl.off_tiles), tr, stream);
+                                   reinterpret_cast<int*>(base + pl.off_tiles), tr, stream, Lp,
+                                   pl.gsym ? reinterpret_cast<float*>(base + pl.off_G) : nullptr);
     }
     case CC_LADDER_SPLIT_BF16:
       return split_forward(pl, L, t, R, base, tr, stream);
@@ -1405,6 +1455,8 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
     unsigned long long* buf = reinterpret_cast<unsigned long long*>(base + pl.off_check);
     rc = check_pair_symmetric(t, o, v, buf, stream);
     if (!rc) rc = check_pair_symmetric(lam, o, v, buf, stream);
+    if (!rc && opts && (opts->flags & CC_LADDER_SYMMETRIC_VECTORS))
+      rc = check_vectors_symmetric(L, P, v, buf, stream);
     if (rc) return rc;
   }
   const Tracer tr(opts, stream);
@@ -1422,19 +1474,30 @@ extern "C" int cc_ladder_backward(int o, int v, int P, const double* L, const do
     if (rc) return rc;
   }
   if (precision == CC_LADDER_FP64) {
-    rc = backward_blocks<TrF64>(pl, L, t, lam, dL, dtx, base, tr, stream);
+    double* Lp = pl.gsym ? reinterpret_cast<double*>(base + pl.off_Lp) : nullptr;
+    if (pl.gsym) {
+      tr(CC_LADDER_PHASE_PREP, 0, 0);
+      rc = pack_sym(L, Lp, P, v, pl.ldg, stream);
+      tr(CC_LADDER_PHASE_PREP, 0, 1);
+      if (rc) return rc;
+    }
+    rc = backward_blocks<TrF64>(pl, L, t, lam, dL, dtx, base, tr, stream, Lp,
+                                pl.gsym ? reinterpret_cast<double*>(base + pl.off_G) : nullptr);
   } else {
     float* L32 = reinterpret_cast<float*>(base + pl.off_L);
     float* t32 = reinterpret_cast<float*>(base + pl.off_t);
     float* lam32 = reinterpret_cast<float*>(base + pl.off_lam);
+    float* Lp = pl.gsym ? reinterpret_cast<float*>(base + pl.off_Lp) : nullptr;
     tr(CC_LADDER_PHASE_PREP, 0, 0);
     rc = to_f32(L, L32, (size_t)P * v * v, stream);
     if (!rc)
       rc = pl.exchange ? swap_cd(t, t32, o, v, stream) : to_f32(t, t32, (size_t)o * o * v * v, stream);
     if (!rc) rc = to_f32(lam, lam32, (size_t)o * o * v * v, stream);
+    if (!rc && pl.gsym) rc = pack_sym(L, Lp, P, v, pl.ldg, stream);
     tr(CC_LADDER_PHASE_PREP, 0, 1);
     if (rc) return rc;
-    rc = backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dtx, base, tr, stream);
+    rc = backward_blocks<TrF32>(pl, L32, t32, lam32, dL, dtx, base, tr, stream, Lp,
+                                pl.gsym ? reinterpret_cast<float*>(base + pl.off_G) : nullptr);
   }
   if (rc || !pl.exchange) return rc;
   tr(CC_LADDER_PHASE_PREP, 1, 0);

@@ -47,11 +47,10 @@ int check_precision_opts(int precision, const cc_ladder_opts* opts) {
                        CC_LADDER_PLUS_MINUS | CC_LADDER_SYMMETRIC_VECTORS)) != 0 ||
       opts->reserved != 0)
     return CC_LADDER_EINVAL;
-  // the symmetric/antisymmetric combinations rest on the pair-symmetry assertion,
-  // the whole pair-pair integral on them
-  if ((opts->flags & CC_LADDER_PLUS_MINUS) && !(opts->flags & CC_LADDER_PAIR_SYMMETRIC))
-    return CC_LADDER_EINVAL;
-  if ((opts->flags & CC_LADDER_SYMMETRIC_VECTORS) && !(opts->flags & CC_LADDER_PLUS_MINUS))
+  // the symmetric/antisymmetric combinations and the whole pair-pair integral
+  // serve the pair-symmetric paths
+  if ((opts->flags & (CC_LADDER_PLUS_MINUS | CC_LADDER_SYMMETRIC_VECTORS)) &&
+      !(opts->flags & CC_LADDER_PAIR_SYMMETRIC))
     return CC_LADDER_EINVAL;
   if (opts->split_slices != 0) {
     const int lo = precision == CC_LADDER_SPLIT_INT8 ? 4 : 2;
@@ -179,6 +178,13 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   size_t cur = 0;
   p.exchange = (flags & CC_LADDER_EXCHANGE) ? 1 : 0;
   p.pm = (p.pairsym && (flags & CC_LADDER_PLUS_MINUS)) ? 1 : 0;
+  // symmetric vectors: the whole pair-pair integral G [ldg][ldg] and the packed
+  // vectors [P][ldg] (side v(v+1)/2 rounded to 4, pads zero) replace the packed
+  // build in the FP64 and FP32 pair-symmetric paths
+  const size_t es_g = precision == CC_LADDER_FP64 ? sizeof(double) : sizeof(float);
+  p.gsym = ((flags & CC_LADDER_SYMMETRIC_VECTORS) && (p.pairsym || p.pairsym_adj) &&
+            (precision == CC_LADDER_FP64 || precision == CC_LADDER_FP32)) ? 1 : 0;
+  if (p.gsym) p.ldg = static_cast<long long>((static_cast<size_t>(v) * (v + 1) / 2 + 3) / 4 * 4);
   if (p.exchange) {
     // the float32 form swaps while converting into its own operand copy; the
     // combinations t+- of swapped amplitudes are t+ and -t-, made without a copy
@@ -202,11 +208,8 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
     p.off_Vp = take(&cur, np * p.ldp * es);
     p.off_Vm = take(&cur, nm * p.ldm * es);
     if (precision == CC_LADDER_FP32) p.k_chunk = k_chunk ? k_chunk : 512;
-    p.gsym = (flags & CC_LADDER_SYMMETRIC_VECTORS) ? 1 : 0;
     if (p.gsym) {
-      // symmetric vectors: packed vectors and the whole pair-pair integral (its
-      // side padded like the operand rows, pads zero) instead of a packed block
-      p.ldg = p.ldp;
+      // no packed block: V+- are gathered from G
       p.off_Lp = take(&cur, static_cast<size_t>(P) * p.ldg * es);
       p.off_G = take(&cur, static_cast<size_t>(p.ldg) * p.ldg * es);
     } else {
@@ -223,7 +226,8 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       break;
     case CC_LADDER_FP32:
       p.k_chunk = k_chunk ? k_chunk : 512;
-      p.off_L = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
+      // the forward over G needs no float32 copy of L (the adjoint's dL does)
+      if (!p.gsym || p.backward) p.off_L = take(&cur, static_cast<size_t>(P) * v2 * sizeof(float));
       p.off_t = take(&cur, o2 * v2 * sizeof(float));
       if (p.backward) p.off_lam = take(&cur, o2 * v2 * sizeof(float));
       p.off_V = take(&cur, blk * sizeof(float));
@@ -274,6 +278,10 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   if (p.pairsym_adj) {
     // the adjoint's dt accumulates B[(ij)][(cd)] over packed rows; dt += B + mirror(B)
     p.off_B = take(&cur, o2 * v2 * sizeof(double));
+  }
+  if (p.gsym && !p.pm) {
+    p.off_Lp = take(&cur, static_cast<size_t>(P) * p.ldg * es_g);
+    p.off_G = take(&cur, static_cast<size_t>(p.ldg) * p.ldg * es_g);
   }
   if ((p.pairsym || p.pairsym_adj) && (flags & CC_LADDER_CHECK_SYMMETRY)) {
     // two maxima of the pair-symmetry check (bit patterns of non-negative doubles)

@@ -54,9 +54,9 @@ static void argument_checks() {
   CHECK(check_precision_opts(0, &o) == CC_LADDER_OK);
   o.flags = 32;  // no such flag
   CHECK(check_precision_opts(0, &o) == CC_LADDER_EINVAL);
-  o.flags = CC_LADDER_PAIR_SYMMETRIC | CC_LADDER_SYMMETRIC_VECTORS;  // needs PLUS_MINUS
+  o.flags = CC_LADDER_SYMMETRIC_VECTORS;  // needs PAIR_SYMMETRIC
   CHECK(check_precision_opts(0, &o) == CC_LADDER_EINVAL);
-  o.flags |= CC_LADDER_PLUS_MINUS;
+  o.flags |= CC_LADDER_PAIR_SYMMETRIC;
   CHECK(check_precision_opts(0, &o) == CC_LADDER_OK);
   o = cc_ladder_opts{};
   o.workspace = reinterpret_cast<void*>(uintptr_t(4096 + 128));
@@ -121,15 +121,20 @@ static void plan_invariants(const Plan& p, int backward, size_t budget) {
     CHECK(p.ldm >= static_cast<long long>(p.v) * (p.v - 1) / 2);
     CHECK(p.pairsym && !backward && p.off_Vp > p.off_Tp);
     if (p.gsym) {
-      // the whole pair-pair integral instead of a packed block; its compact grid's
-      // tile offsets cover its ldg rows
+      // the whole pair-pair integral instead of a packed block
       CHECK(p.ldg == p.ldp && p.off_G > p.off_Lp && p.off_Lp >= p.off_Vm && p.off_V == 0);
-      CHECK(p.off_tiles > p.off_G);
     } else {
       CHECK(p.off_V > 0 && p.off_G == 0);
     }
+  }
+  if (p.gsym) {
+    // FP64/FP32 pair-symmetric paths; the compact grid's tile offsets come after G
+    CHECK(p.pairsym || p.pairsym_adj);
+    CHECK(p.precision == CC_LADDER_FP64 || p.precision == CC_LADDER_FP32);
+    CHECK(p.ldg % 4 == 0 && p.ldg >= static_cast<long long>(p.v) * (p.v + 1) / 2);
+    CHECK(p.off_G > p.off_Lp && p.off_tiles > p.off_G);
   } else {
-    CHECK(!p.gsym);
+    CHECK(p.off_G == 0 && p.off_Lp == 0);
   }
 }
 
@@ -155,8 +160,8 @@ static void planner_sweep() {
     Plan p;
     const int rc = make_plan(o, v, P, precision, backward, budget, &opts, &p);
     const bool pm = (opts.flags & CC_LADDER_PLUS_MINUS) != 0;
-    if ((pm && !(opts.flags & CC_LADDER_PAIR_SYMMETRIC)) ||
-        ((opts.flags & CC_LADDER_SYMMETRIC_VECTORS) && !pm)) {
+    if ((opts.flags & (CC_LADDER_PLUS_MINUS | CC_LADDER_SYMMETRIC_VECTORS)) &&
+        !(opts.flags & CC_LADDER_PAIR_SYMMETRIC)) {
       CHECK(rc == CC_LADDER_EINVAL);
       continue;
     }

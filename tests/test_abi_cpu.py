@@ -416,18 +416,41 @@ def test_planner_symmetric_vectors_footprint(native):
         assert a == b and a[0] <= small
 
 
-def test_symmetric_vectors_needs_plus_minus(native):
+def test_symmetric_vectors_footprint_packed_forward_and_adjoint(native):
+    # the packed forward and the pair-symmetric adjoint keep their buffers and add
+    # the packed vectors and the pair-pair integral (the float32 forward drops its
+    # float32 copy of L); the split forms ignore the flag
+    def r256(x):
+        return (x + 255) // 256 * 256
+
+    o, v, P, n_a = 4, 19, 11, 5
+    ldg = (v * (v + 1) // 2 + 3) // 4 * 4
+    tiles_old = r256(((n_a * v + 127) // 128 + 1) * 4)
+    tiles_new = r256(((ldg + 127) // 128 + 1) * 4)
+    for prec, es in (("fp64", 8), ("fp32", 4)):
+        for backward in (False, True):
+            kw = dict(a_block=n_a, pair_symmetric=True)
+            a, _ = native.cc_ladder_workspace_query(
+                o, v, P, prec, backward=backward, opts=native.make_opts(symmetric_vectors=True, **kw))
+            b, _ = native.cc_ladder_workspace_query(o, v, P, prec, backward=backward,
+                                                    opts=native.make_opts(**kw))
+            want = b + r256(P * ldg * es) + r256(ldg * ldg * es) - tiles_old + tiles_new
+            if prec == "fp32" and not backward:
+                want -= r256(P * v * v * 4)
+            assert a == want, (prec, backward, a, want)
+    kw = dict(a_block=n_a, pair_symmetric=True)
+    assert (native.cc_ladder_workspace_query(o, v, P, "split_bf16",
+                                             opts=native.make_opts(symmetric_vectors=True, **kw))
+            == native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(**kw)))
+
+
+def test_symmetric_vectors_needs_pair_symmetry(native):
     with pytest.raises(native.LadderError) as e:
-        native.cc_ladder_workspace_query(
-            3, 10, 5, "fp64", opts=native.make_opts(pair_symmetric=True, symmetric_vectors=True))
+        native.cc_ladder_workspace_query(3, 10, 5, "fp64",
+                                         opts=native.make_opts(symmetric_vectors=True))
     assert e.value.code == native.CC_LADDER_EINVAL
-    # the adjoint plans as with pair symmetry alone
-    a = native.cc_ladder_workspace_query(
-        3, 10, 5, "fp64", backward=True,
-        opts=native.make_opts(pair_symmetric=True, plus_minus=True, symmetric_vectors=True))
-    b = native.cc_ladder_workspace_query(3, 10, 5, "fp64", backward=True,
-                                         opts=native.make_opts(pair_symmetric=True))
-    assert a == b
+    native.cc_ladder_workspace_query(
+        3, 10, 5, "fp64", opts=native.make_opts(pair_symmetric=True, symmetric_vectors=True))
 
 
 def test_plus_minus_needs_pair_symmetry(native):

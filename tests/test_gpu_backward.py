@@ -159,29 +159,36 @@ def _pair_symmetric(x):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("exchange", [False, True])
+@pytest.mark.parametrize("exchange,symv", [(False, False), (True, False), (False, True),
+                                           (True, True)])
 @pytest.mark.parametrize("o,v,P,a_block", [(5, 23, 37, 5), (9, 37, 101, 0), (3, 130, 17, 40)])
-def test_backward_pair_symmetric(gpu_lib, o, v, P, a_block, precision, exchange):
-    # t and lam pair-symmetric: the one dL term added twice gives both terms
-    announce("backward-pairsym", o, v, P, "a_block", a_block, "precision", precision, exchange)
+def test_backward_pair_symmetric(gpu_lib, o, v, P, a_block, precision, exchange, symv):
+    # t and lam pair-symmetric: the half-written W block gives both dL terms;
+    # with symmetric vectors the packed integral rows come from the pair-pair integral
+    announce("backward-pairsym", o, v, P, "a_block", a_block, "precision", precision, exchange,
+             "symv", symv)
     L, t, lam = random_general(o, v, P, 650 + o + v)
     t, lam = _pair_symmetric(t), _pair_symmetric(lam)
+    if symv:
+        L = 0.5 * (L + L.transpose(0, 2, 1))
     dL0 = np.random.default_rng(5).standard_normal(L.shape)
     dt0 = np.random.default_rng(6).standard_normal(t.shape)
     ref = oracle.exchange_backward(L, t, lam) if exchange else oracle.ladder_backward(L, t, lam)
     dL, dt = run_backward(gpu_lib, L, t, lam, precision, dL0, dt0, a_block=a_block,
-                          pair_symmetric=True, exchange=exchange)
+                          pair_symmetric=True, exchange=exchange, symmetric_vectors=symv)
     assert rel_fro(dL - dL0, ref[0]) < TOL_BWD[precision]
     assert rel_fro(dt - dt0, ref[1]) < TOL_BWD[precision]
 
 
-@pytest.mark.parametrize("precision,a_block", [(0, 0), (0, 64), (1, 64)])
-def test_backward_pair_symmetric_gradient_workload(gpu_lib, precision, a_block):
+@pytest.mark.parametrize("precision,a_block,symv", [(0, 0, False), (0, 64, False), (1, 64, False),
+                                                    (0, 0, True), (1, 0, True)])
+def test_backward_pair_symmetric_gradient_workload(gpu_lib, precision, a_block, symv):
     # the gradient workload's lam and t are pair-symmetric: the symmetric adjoint
     # against the general one over the whole tensors (one block, or five blocks of
     # 64 virtuals whose half-written W blocks start past the first virtual)
     o, v, P = CONFIGS["o30_v300_P900"]
-    announce("backward-pairsym-o30-v300-P900", "precision", precision, "a_block", a_block)
+    announce("backward-pairsym-o30-v300-P900", "precision", precision, "a_block", a_block,
+             "symv", symv)
     inp = make_inputs(o, v, P, seed_for("o30_v300_P900"), with_lambda=True, device="cuda")
     Ld, td, lamd = dev(inp.L_vv), dev(inp.t), dev(inp.lam)
     out = {}
@@ -189,7 +196,8 @@ def test_backward_pair_symmetric_gradient_workload(gpu_lib, precision, a_block):
         dL = torch.zeros_like(Ld)
         dt = torch.zeros_like(td)
         gpu_lib.cc_ladder_backward(Ld, td, lamd, dL, dt, precision,
-                                   opts=gpu_lib.make_opts(pair_symmetric=sym, a_block=a_block))
+                                   opts=gpu_lib.make_opts(pair_symmetric=sym, a_block=a_block,
+                                                          symmetric_vectors=sym and symv))
         torch.cuda.synchronize()
         out[sym] = (dL, dt)
     for k in (0, 1):

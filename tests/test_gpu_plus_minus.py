@@ -148,15 +148,37 @@ def test_symmetric_vectors_checks_and_fallback(gpu_lib):
     ref = oracle.ladder_forward(Ls, t)
     got = run(gpu_lib, Ls, t, np.zeros_like(t), 0, check_symmetry=True, symmetric_vectors=True)
     assert rel_fro(got, ref) < TOL[0]
-    # without PLUS_MINUS the flag is rejected
+    # without PAIR_SYMMETRIC the flag is rejected
     with pytest.raises(gpu_lib.LadderError) as e:
         gpu_lib.cc_ladder_residual(dev(Ls), dev(t), R, 0,
-                                   opts=gpu_lib.make_opts(pair_symmetric=True, symmetric_vectors=True))
+                                   opts=gpu_lib.make_opts(symmetric_vectors=True))
     assert e.value.code == gpu_lib.CC_LADDER_EINVAL
     # a budget the whole integral does not fit: the packed blocks, same result
     ldg = (v * (v + 1) // 2 + 3) // 4 * 4
     got = run(gpu_lib, Ls, t, np.zeros_like(t), 0, hbm_budget=ldg * ldg * 8, symmetric_vectors=True)
     assert rel_fro(got, ref) < TOL[0]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("exchange", [False, True])
+@pytest.mark.parametrize("o,v,P,a_block", [(5, 20, 75, 0), (9, 37, 101, 7), (3, 130, 17, 40),
+                                           (2, 3, 2, 0), (7, 1, 4, 0), (23, 65, 50, 30)])
+def test_symmetric_vectors_packed_rows(gpu_lib, o, v, P, a_block, precision, exchange):
+    # the pair-symmetric forward without the combinations: packed rows (a,b),
+    # a <= b, gathered whole from the pair-pair integral, then the mirrored contraction
+    announce("forward-pairsym-symv", o, v, P, "a_block", a_block, "precision", precision, exchange)
+    L, t, _ = random_general(o, v, P, 1600 + o + v)
+    L, t = _symmetric_vectors(L), _pair_symmetric(t)
+    R0 = np.random.default_rng(12).standard_normal(t.shape)
+    inc = oracle.exchange_forward(L, t) if exchange else oracle.ladder_forward(L, t)
+    R = dev(R0)
+    gpu_lib.cc_ladder_residual(dev(L), dev(t), R, precision,
+                               opts=gpu_lib.make_opts(a_block=a_block, pair_symmetric=True,
+                                                      symmetric_vectors=True, exchange=exchange))
+    torch.cuda.synchronize()
+    err = rel_fro(host(R) - R0, inc)
+    print(f"CASE forward-pairsym-symv error {err:.2e}", flush=True)
+    assert err < TOL[precision]
 
 
 def test_plus_minus_rejections(gpu_lib):

@@ -23,11 +23,11 @@ pytestmark = pytest.mark.gpu
 # (precision, split slices, pair-symmetric) -> tolerance over the whole tensor
 # ("pm": the symmetric/antisymmetric combinations over i <= j, a <= b, c <= d;
 # "pmv": the same gathered from the whole pair-pair integral of the workload's
-# symmetric Cholesky vectors)
+# symmetric Cholesky vectors; "sv": the packed rows gathered from it)
 FORMS = [(0, 0, False, TOL[0]), (1, 0, False, TOL[1]), (2, 4, False, TOL_SPLIT_WORKLOAD[4]),
          (2, 2, False, TOL_SPLIT_WORKLOAD[2]), (0, 0, True, TOL[0]), (1, 0, True, TOL[1]),
          (2, 4, True, TOL_SPLIT_WORKLOAD[4]), (0, 0, "pm", TOL[0]), (1, 0, "pm", TOL[1]),
-         (0, 0, "pmv", TOL[0]), (1, 0, "pmv", TOL[1]),
+         (0, 0, "pmv", TOL[0]), (1, 0, "pmv", TOL[1]), (0, 0, "sv", TOL[0]), (1, 0, "sv", TOL[1]),
          (3, 5, False, TOL[2]), (3, 5, True, TOL[2])]
 
 
@@ -39,7 +39,7 @@ def _check_forms(native, name, Ld, td, ref):
         native.cc_ladder_residual(Ld, td, R, precision,
                                   opts=native.make_opts(split_slices=slices, pair_symmetric=bool(sym),
                                                         plus_minus=sym in ("pm", "pmv"),
-                                                        symmetric_vectors=sym == "pmv"))
+                                                        symmetric_vectors=sym in ("pmv", "sv")))
         torch.cuda.synchronize()
         if sym:
             # entries a != b are stored twice from one computed value: exact mirrors
