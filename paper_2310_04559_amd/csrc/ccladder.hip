@@ -452,6 +452,47 @@ __global__ __launch_bounds__(256) void mirror_add_kernel(const double* __restric
   }
 }
 
+// In place W <- W + W^T for a square n x n matrix (row stride n): one workgroup
+// per pair of 32 x 32 tiles P <= Q reads both tiles through LDS and writes both
+// sums, so every element is read and written once and no two workgroups touch
+// the same element.
+template <typename T>
+__global__ __launch_bounds__(256) void sym_add_kernel(T* __restrict__ W, long long n, int tiles) {
+  __shared__ double a[kSwapTile][kSwapTile + 1], b[kSwapTile][kSwapTile + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const long long npairs = (long long)tiles * (tiles + 1) / 2;
+  for (long long w = blockIdx.x; w < npairs; w += gridDim.x) {
+    const int P = pair_row(w, tiles);
+    const int Q = P + static_cast<int>(w - pair_prefix_d(P, tiles));
+    const long long p0 = (long long)P * kSwapTile, q0 = (long long)Q * kSwapTile;
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      // a[k][tx] = W[p0+k][q0+tx], b[k][tx] = W[q0+k][p0+tx]
+      a[k][tx] = (p0 + k < n && q0 + tx < n) ? static_cast<double>(W[(p0 + k) * n + q0 + tx]) : 0.0;
+      b[k][tx] = (q0 + k < n && p0 + tx < n) ? static_cast<double>(W[(q0 + k) * n + p0 + tx]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = ty; k < kSwapTile; k += 8) {
+      // W[p0+k][q0+tx] = a[k][tx] + b[tx][k]; W[q0+k][p0+tx] = b[k][tx] + a[tx][k]
+      if (p0 + k < n && q0 + tx < n) W[(p0 + k) * n + q0 + tx] = static_cast<T>(a[k][tx] + b[tx][k]);
+      if (P != Q && q0 + k < n && p0 + tx < n)
+        W[(q0 + k) * n + p0 + tx] = static_cast<T>(b[k][tx] + a[tx][k]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+int sym_add(T* W, long long n, hipStream_t s) {
+  const int tiles = static_cast<int>((n + kSwapTile - 1) / kSwapTile);
+  const long long work = (long long)tiles * (tiles + 1) / 2;
+  const long long blocks = std::min<long long>(work, 65536);
+  hipLaunchKernelGGL((sym_add_kernel<T>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, W, n,
+                     tiles);
+  return hipGetLastError() == hipSuccess ? CC_LADDER_OK : CC_LADDER_EHIP;
+}
+
 int mirror_add(const double* B, double* dt, int o, int v, hipStream_t s) {
   const int tiles = (v + kSwapTile - 1) / kSwapTile;
   const long long work = (long long)o * o * tiles * tiles;
@@ -1093,6 +1134,13 @@ int backward_blocks(const Plan& pl, const typename Tr::T* L, const typename Tr::
         rc = launch_gemm<Tr, KC, RC, EPI_ACC>(L + off, v2, W + off, v2, dL + off, v2, P,
                                               static_cast<int>((long long)(v - a0) * v), na * v,
                                               v, drain, s, 0, a0, nullptr, 2.0, 0, 2);
+    } else if (na == v) {
+      // one block holds all of W' = [(ac)][(bd)]: the two terms are one product
+      // with its symmetric part, dL[x][p] += sum_q L[x][q] (W'[p][q] + W'[q][p])
+      rc = sym_add(W, v2, s);
+      if (!rc)
+        rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL, v2, P, static_cast<int>(v2),
+                                              static_cast<int>(v2), v, drain, s);
     } else {
       // dL[x][a0*v + (ac)] += L[x][(bd)] . W'_A[(ac)][(bd)]
       rc = launch_gemm<Tr, KC, KC, EPI_ACC>(L, v2, W, v2, dL + off, v2, P, na * v,

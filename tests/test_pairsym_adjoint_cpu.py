@@ -128,3 +128,17 @@ def test_pair_row_decode():
             assert pair_row(start - 1, v) == a - 1
         if a + 1 < v:
             assert pair_row(start + (v - a) - 1, v) == a
+
+
+def test_general_adjoint_one_block_symmetric_part():
+    # general t, lam, L: with W'[(a,c)][(b,d)] = sum_ij lam[i,j,a,b] t[i,j,c,d] held
+    # whole, both dL terms are one product with its symmetric part,
+    # dL[x][p] = sum_q L[x][q] (W'[p][q] + W'[q][p])
+    from paper_2310_04559_amd.inputs import random_general
+
+    L, t, lam = random_general(3, 7, 5, 61)
+    P, v, _ = L.shape
+    W = np.einsum("ijab,ijcd->acbd", lam, t).reshape(v * v, v * v)
+    dL = (L.reshape(P, v * v) @ (W + W.T).T).reshape(P, v, v)
+    ref, _ = oracle.ladder_backward(L, t, lam)
+    assert np.max(np.abs(dL - ref)) < 1e-13 * np.max(np.abs(ref))
