@@ -306,6 +306,22 @@ def cpu_baseline(inp, target_s=15.0):
                       f"({k}/{v} of its flops, {dt:.1f} s)"}
 
 
+def adjoint_executed_flops(o, v, P, sym, symv, n_a):
+    """Flops the adjoint executes: build 2 P v^4, dt and W 2 o^2 v^4 each, and the
+    two dL terms 2 P v^4 each, or one product of 2 P v^4 when one block holds
+    all of W (its symmetric part gives both terms).  Pair-symmetric: every
+    product over the packed pairs, n = v(v+1)/2 rows instead of v^2 (the dL
+    terms over the half-written W, K ranges b >= a); with symmetric vectors the
+    build is the pair-pair integral's upper triangle, P n(n+1)."""
+    v4 = float(v) ** 4
+    if not sym:
+        dl = 2.0 if n_a == v else 4.0
+        return (2.0 * P + 4.0 * o * o + dl * P) * v4
+    n = v * (v + 1) / 2.0
+    build = P * n * (n + 1) if symv else 2.0 * P * v * v * n
+    return build + (4.0 * o * o + 4.0 * P) * v * v * n
+
+
 def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pairsym",
                                         "fp64_pairsym_symv", "fp32_pairsym_symv")):
     """The adjoint on the gradient workload (o=30, v=300, P=900); its lam and t
@@ -336,7 +352,7 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
         symv = form.endswith("_symv")
         timer = PhaseTimer(native, stream)
         # the caller's workspace, allocated once outside the timed calls
-        nbytes, _ = native.cc_ladder_workspace_query(
+        nbytes, n_a = native.cc_ladder_workspace_query(
             o, v, P, prec, backward=True, hbm_budget=budget,
             opts=native.make_opts(pair_symmetric=sym, symmetric_vectors=symv))
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -360,10 +376,13 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        executed = adjoint_executed_flops(o, v, P, sym, symv, n_a)
         res[form] = {"ms_per_step": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                     "tflops_executed": executed / (ms * 1e-3) / 1e12, "a_block": n_a,
                      "rel_err_vs_fp64_gpu": err,
                      "phases_ms_per_step": {k: d["ms_total"] / steps for k, d in timer.summary().items()}}
         log(f"adjoint {form}: {ms:.1f} ms {res[form]['tflops']:.1f} TFLOP/s "
+            f"({res[form]['tflops_executed']:.1f} executed) "
             f"phases {json.dumps(res[form]['phases_ms_per_step'])}")
         del ws, opts, timer
         del dL, dt
