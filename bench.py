@@ -389,7 +389,8 @@ def bench_adjoint(native, steps, forms=("fp64", "fp32", "fp64_pairsym", "fp32_pa
     return res
 
 
-def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
+def bench_large(native, forms=("fp64", "split_int8", "split_bf16"), budget_names=("default", "device"),
+                adjoint=True):
     """The large single-GPU workload (o=60, v=600, P=1800) under two scratch
     budgets, each a caller workspace allocated once: the default (half the free
     memory, at most 128 GiB, as the library plans by default) and one sized to the device (the free memory left
@@ -442,6 +443,8 @@ def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
         return e0.elapsed_time(e1)
 
     for bname, budget in budgets.items():
+        if bname not in budget_names:
+            continue
         for form in forms:
             prec, slices = native.PRECISIONS[FORMS[form][0]], FORMS[form][1]
             nbytes, n_a = native.cc_ladder_workspace_query(
@@ -473,6 +476,8 @@ def bench_large(native, forms=("fp64", "split_int8", "split_bf16")):
                 f"{ms:.0f} ms {r['tflops']:.1f} TFLOP/s phases {json.dumps(r['phases_ms'])}")
     del R
     torch.cuda.empty_cache()
+    if not adjoint:
+        return res
     dL = torch.zeros_like(L)
     dt = torch.zeros_like(t)
     nbytes, n_a = native.cc_ladder_workspace_query(o, v, P, native.CC_LADDER_FP32, backward=True,
@@ -586,6 +591,11 @@ def main():
                     help="also run the o=60, v=600, P=1800 workload (about five minutes)")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the o=60, v=600, P=1800 workload and print its JSON")
+    ap.add_argument("--large-forms", default="fp64,split_int8,split_bf16",
+                    help="forms of the large workload")
+    ap.add_argument("--large-budgets", default="default,device",
+                    help="scratch budgets of the large workload: default and/or device")
+    ap.add_argument("--no-large-adjoint", action="store_true")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the adjoint on the o=30, v=300, P=900 workload and print its JSON")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -622,7 +632,9 @@ def main():
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
         del src, dst
     if args.only_large:
-        print(json.dumps({"large": bench_large(native)}), flush=True)
+        print(json.dumps({"large": bench_large(native, tuple(args.large_forms.split(",")),
+                                               tuple(args.large_budgets.split(",")),
+                                               not args.no_large_adjoint)}), flush=True)
         return
     if args.only_adjoint:
         print(json.dumps({"adjoint": bench_adjoint(native, max(1, min(args.steps, 2)))}), flush=True)
