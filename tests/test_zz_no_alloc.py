@@ -54,6 +54,24 @@ def test_noalloc_matches_allocating_entry_point(gpu_lib, precision, slices, flag
         assert err < tol, (k, err)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("symv", [False, True])
+def test_noalloc_plus_minus_paths(gpu_lib, precision, symv):
+    # the +- combinations, with the packed build or gathered from the whole
+    # pair-pair integral of the workload's symmetric vectors (it fits the static array)
+    for k, (o, v, P) in enumerate(SHAPES):
+        announce("noalloc-pm", "call", k, "o", o, "v", v, "P", P, "precision", precision,
+                 "symv", symv)
+        inp = make_inputs(o, v, P, seed=720 + k)
+        Ld, td = dev(inp.L_vv), dev(inp.t)
+        R1, R2 = _pair(gpu_lib, Ld, td, precision, a_block=16 if k == 0 else 7,
+                       pair_symmetric=True, plus_minus=True, symmetric_vectors=symv)
+        assert torch.equal(R1, R2), (k, precision, symv)
+        err = rel_fro(host(R2), oracle.ladder_forward(inp.L_vv, inp.t))
+        print(f"CASE noalloc-pm call {k} rel. error vs oracle {err:.2e}", flush=True)
+        assert err < TOL[precision], (k, err)
+
+
 def test_noalloc_own_plan_and_accumulation(gpu_lib):
     # blocks sized by the library to the static array; R accumulates (+=)
     for k, (o, v, P) in enumerate([(20, 180, 600), (6, 50, 64)]):
