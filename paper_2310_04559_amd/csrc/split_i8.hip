@@ -358,14 +358,33 @@ __global__ __launch_bounds__(64 * WAVES, 1) void i8_gemm_kernel(I8Args g) {
         }
         __builtin_amdgcn_s_setprio(0);
       }
-      // drain chunk c into the output: 2^(eA + eB - 14) sum_g 2^(-8g) acc_g
+      // drain chunk c into the output: 2^(eA + eB - 14) sum_g 2^(-8g) acc_g.
+      // The exponents of this lane's 16 rows and NJ columns are loaded together
+      // first, from one base each with constant offsets (rows past M and columns
+      // past N read the zero-based padding of the exponent tables, which every
+      // operand buffer carries past its last tile), so the drain waits on memory
+      // once rather than once per element.
       const int c = k0 / kIChunkSteps;
       const bool first = k0 == 0;
+      // this lane's first row; opaque to the optimiser, so the row arithmetic of
+      // the stores stays here instead of being hoisted into registers held (and
+      // spilled) across the K loop
+      int mb = m0 + wm + 4 * (lane >> 4);
+      asm volatile("" : "+v"(mb));
+      const int* ep = g.ea + (long long)c * g.ea_stride + mb;
+      const int* fp = g.eb + (long long)c * g.eb_stride + n0 + wn + (lane & 15);
+      int erow[MI][4], ecol[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) erow[i][r] = ep[16 * i + r];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) ecol[j] = fp[16 * j];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int n = n0 + wn + 16 * j + (lane & 15);
         if (n >= g.N) continue;
-        const int en = g.eb[(long long)c * g.eb_stride + n];
+        const int en = ecol[j];
         long long ncol = n;
         int pa = 0, pb = 0;  // EPI_PACK: b - a0 and d; EPI_PAIR: a and b
         if (EPI == EPI_PERM) {
@@ -383,14 +402,14 @@ __global__ __launch_bounds__(64 * WAVES, 1) void i8_gemm_kernel(I8Args g) {
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+            const int m = mb + 16 * i + r;
             if (m >= g.M) continue;
             double u = 0.0;
 #pragma unroll
             for (int q = NG - 1; q >= 0; --q)
               u = fma(static_cast<double>(acc[q][i][j][r]), 1.0 / static_cast<double>(1ull << (8 * q)),
                       u);
-            const double val = ldexp(u, g.ea[(long long)c * g.ea_stride + m] + en - 14);
+            const double val = ldexp(u, erow[i][r] + en - 14);
             double* C = g.C;
             if (EPI == EPI_ACC) {
               C[(long long)m * g.ldc + n] += val;
