@@ -515,11 +515,26 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     }
   }
 
+  // this lane's first row, opaque to the optimiser (the row arithmetic of the
+  // stores stays here instead of registers held across the K loop); the builds'
+  // per-row exponents of its 16 rows and NJ columns are loaded together first,
+  // rows past M and columns past N reading the exponent tables' padding
+  int mb = m0 + wm + 4 * (lane >> 4);
+  asm volatile("" : "+v"(mb));
+  int erow[MI][4] = {}, ecol[NJ] = {};
+  if constexpr (!CE && S != 2) {
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) erow[i][r] = g.ea[mb + 16 * i + r];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) ecol[j] = g.eb[n0 + wn + 16 * j + (lane & 15)];
+  }
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int n = n0 + wn + 16 * j + (lane & 15);
     if (n >= g.N) continue;
-    const int en = CE ? 0 : (S == 2 ? kHiLoExp : g.eb[n]);
+    const int en = CE ? 0 : (S == 2 ? kHiLoExp : ecol[j]);
     long long ncol = n;
     int pa = 0, pb = 0;  // EPI_PACK: b - a0 and d; EPI_PAIR: a and b
     if (EPI == EPI_PERM) {
@@ -537,10 +552,10 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
     for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int m = mb + 16 * i + r;
         if (m >= g.M) continue;
         const double val =
-            CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], (S == 2 ? kHiLoExp : g.ea[m]) + en);
+            CE ? acc64[i][j][r] : ldexp(acc64[i][j][r], (S == 2 ? kHiLoExp : erow[i][r]) + en);
         double* C = static_cast<double*>(g.C);
         const int mo = m + g.m_off;  // output row
         if (EPI == EPI_ACC) {
