@@ -9,6 +9,7 @@ with V+- = (ac|bd) +- (ad|bc) (2(ac|bc) on c = d) and t+- = t_ijcd +- t_ijdc
 (t_ijcc on c = d), over rows i <= j (i < j for R-) and columns a <= b (a < b),
 scattered to the four (i,j)/(a,b) mirrors with half weight."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_2310_04559_amd.inputs import make_inputs, random_general
@@ -138,3 +139,124 @@ def test_symmetric_vector_gather_needs_symmetric_vectors():
     plus, _ = gathered_block(L, 0, v)
     want = np.array([V[a, b, cu, du] + V[a, b, du, cu] for a in range(v) for b in range(a, v)])
     assert np.max(np.abs(plus - want)) > 1e-3 * np.max(np.abs(want))
+
+
+# ---- the gather kernel's work decomposition and tile passes, replayed on the CPU
+
+_KT = 32  # tile edge of the gather
+
+
+def _xcd_linear(bid, nwg):
+    per, extra = nwg // 8, nwg % 8
+    xcd, local = bid % 8, bid // 8
+    return xcd * per + min(xcd, extra) + local
+
+
+def _pair_row_exact(q, n):
+    a = 0
+    while a + 1 < n and _pp(a + 1, n) <= q:
+        a += 1
+    return a
+
+
+def gather_tiles_model(G, v, a0, nrows, grid, rows_mode):
+    """Replays the gather kernel: its XCD-ordered grid-stride walk over
+    (tile pair, row) items, the two passes of every 32 x 32 tile (lanes along
+    d, then lanes along c), the LDS tiles (stale contents NaN) and the stores
+    of V+ / V- (or of the whole rows).  Unwritten outputs stay NaN."""
+    npv = v * (v + 1) // 2
+    tiles = -(-v // _KT)
+    work = nrows * (tiles * (tiles + 1) // 2)
+    pp = lambda x: _pp(x, v)  # noqa: E731
+    if rows_mode:
+        plus, minus = np.full((nrows, v * v), np.nan), None
+    else:
+        plus = np.full((nrows, npv), np.nan)
+        minus = np.full((nrows, v * (v - 1) // 2), np.nan)
+    q0 = pp(a0)
+    k_, t_ = np.meshgrid(np.arange(_KT), np.arange(_KT), indexing="ij")  # [k or l][tx]
+    for bid in range(grid):
+        w = _xcd_linear(bid, grid)
+        while w < work:
+            tp, r = divmod(w, nrows)
+            C = _pair_row_exact(tp, tiles)
+            D = C + tp - _pp(C, tiles)
+            c0, d0 = C * _KT, D * _KT
+            q = q0 + r
+            a = _pair_row_exact(q, v)
+            ppa = pp(a)
+            b = a + (q - ppa)
+            ppb = pp(b)
+
+            def tile(r0, s0):
+                S = np.full((_KT, _KT), np.nan)
+                # pass 1: element (c, d) = (r0 + k, s0 + tx)
+                c, d = r0 + k_, s0 + t_
+                inside = (c < v) & (d < v)
+                take1 = inside & ((d >= b) | (c < a))
+                for k, tx in zip(*np.nonzero(take1)):
+                    ck, dk = int(c[k, tx]), int(d[k, tx])
+                    row = (ppa + ck - a) if ck >= a else (pp(ck) + a - ck)
+                    col = (ppb + dk - b) if dk >= b else (pp(dk) + b - dk)
+                    S[k, tx] = G[row, col]
+                S[~inside] = 0.0
+                # pass 2: element (c, d) = (r0 + tx, s0 + l), stored at S[tx][l]
+                c, d = r0 + t_, s0 + k_
+                take2 = (c < v) & (d < v) & (c >= a) & (d < b)
+                for l, tx in zip(*np.nonzero(take2)):
+                    cl, dl = int(c[l, tx]), int(d[l, tx])
+                    S[tx, l] = G[pp(dl) + b - dl, ppa + cl - a]
+                return S
+
+            xs = tile(c0, d0)
+            ys = tile(d0, c0) if (not rows_mode or D != C) else None
+            for k in range(_KT):
+                for tx in range(_KT):
+                    if rows_mode:
+                        if c0 + k < v and d0 + tx < v:
+                            plus[r, (c0 + k) * v + d0 + tx] = xs[k, tx]
+                        if D != C and d0 + k < v and c0 + tx < v:
+                            plus[r, (d0 + k) * v + c0 + tx] = ys[k, tx]
+                        continue
+                    c, d = c0 + k, d0 + tx
+                    if c < v and d < v and c <= d:
+                        xcd, xdc = xs[k, tx], ys[tx, k]
+                        kp = pp(c) + d - c
+                        plus[r, kp] = 2.0 * xcd if c == d else xcd + xdc
+                        if a < b and c < d:
+                            rm = _pp(a, v - 1) - _pp(a0, v - 1) + (b - a - 1)
+                            minus[rm, _pp(c, v - 1) + d - c - 1] = xcd - xdc
+            w += grid
+    return plus, minus
+
+
+@pytest.mark.parametrize("v,a0,na,grid", [
+    (9, 0, 9, 5), (9, 2, 4, 64), (40, 0, 40, 7), (40, 13, 9, 1000), (70, 31, 6, 13),
+])
+def test_gather_kernel_walk(v, a0, na, grid):
+    # the kernel's indexing, replayed: every V+, V- and whole-row element of the
+    # block is written once, with (ac|bd) +- (ad|bc) of the definition
+    inp = make_inputs(1, v, 5, 40 + v)
+    L = inp.L_vv
+    iu = np.triu_indices(v)
+    Lp = L[:, iu[0], iu[1]]
+    G = Lp.T @ Lp
+    nrows = _pp(a0 + na, v) - _pp(a0, v)
+    V = np.einsum("xac,xbd->abcd", L, L)
+    rows = [(a, b) for a in range(a0, a0 + na) for b in range(a, v)]
+    assert len(rows) == nrows
+    cu, du = np.triu_indices(v)
+    cs, ds = np.triu_indices(v, 1)
+    want_p = np.array([V[a, b, cu, du] + V[a, b, du, cu] for a, b in rows])
+    want_m = np.array([V[a, b, cs, ds] - V[a, b, ds, cs] for a, b in rows if a < b])
+    want_rows = np.array([V[a, b].reshape(-1) for a, b in rows])
+    scale = np.max(np.abs(want_p))
+    plus, minus = gather_tiles_model(G, v, a0, nrows, grid, rows_mode=False)
+    nm = len(want_m)
+    assert not np.isnan(plus).any() and not np.isnan(minus[:nm]).any()
+    assert np.isnan(minus[nm:]).all()
+    assert np.max(np.abs(plus - want_p)) < 1e-14 * scale
+    assert np.max(np.abs(minus[:nm] - want_m)) < 1e-14 * scale
+    whole, _ = gather_tiles_model(G, v, a0, nrows, grid, rows_mode=True)
+    assert not np.isnan(whole).any()
+    assert np.max(np.abs(whole - want_rows)) < 1e-14 * scale
