@@ -44,7 +44,7 @@ METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 
 # V+- = (ac|bd) +- (ad|bc) over i <= j, a <= b, c <= d (pair-symmetric amplitudes);
 # the *_symv forms gather the packed rows (*_pairsym_symv) or V+- (*_pm_symv)
 # from the whole pair-pair integral of the workload's symmetric Cholesky vectors
-# (built over its upper triangle).
+# (built over its upper triangle; in split_int8_pairsym_symv from int8 digits).
 FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16": ("split_bf16", 4, False, False),
          "split_bf16_s2": ("split_bf16", 2, False, False),
@@ -57,7 +57,8 @@ FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "fp64_exchange": ("fp64", 0, False, True), "fp32_exchange": ("fp32", 0, False, True),
          "split_bf16_exchange": ("split_bf16", 4, False, True),
          "split_int8": ("split_int8", 5, False, False),
-         "split_int8_pairsym": ("split_int8", 5, True, False)}
+         "split_int8_pairsym": ("split_int8", 5, True, False),
+         "split_int8_pairsym_symv": ("split_int8", 5, "sv", False)}
 _PEAK = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0,
          "split_int8": 5000.0}  # dense MFMA, TFLOP/s (int8: TOP/s)
 _DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split_int8": "i8"}
@@ -580,7 +581,7 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_int8,split_bf16_s2,fp64_pairsym,"
                                        "fp64_pairsym_symv,fp64_pm,fp32_pm,fp64_pm_symv,fp32_pm_symv,"
                                        "split_bf16_pairsym,"
-                                       "split_int8_pairsym,fp64_exchange")
+                                       "split_int8_pairsym,split_int8_pairsym_symv,fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--budget-gib", type=float, default=128.0,
                     help="scratch budget of the timed forms: at most this many GiB, and at most "

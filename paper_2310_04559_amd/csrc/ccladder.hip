@@ -1405,6 +1405,16 @@ int residual_body(const Plan& pl, const double* L, const double* t, double* R, i
 
 }  // namespace
 
+int pack_pair_vectors(const double* L, double* Lp, int P, int v, long long ldg, hipStream_t s) {
+  return pack_sym(L, Lp, P, v, ldg, s);
+}
+
+int gather_pair_rows(const double* G, long long ldg, long long nrows, int a0, int v, double* rows,
+                     hipStream_t s) {
+  return pm_gather<GATHER_ROWS>(G, ldg, nrows, a0, v, rows, (long long)v * v,
+                                static_cast<double*>(nullptr), 0, s);
+}
+
 int ladder_forward_planned(const Plan& pl, const double* L, const double* t, double* R,
                            int precision, char* base, const cc_ladder_opts* opts,
                            hipStream_t stream) {

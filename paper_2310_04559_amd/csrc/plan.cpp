@@ -180,10 +180,14 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   p.pm = (p.pairsym && (flags & CC_LADDER_PLUS_MINUS)) ? 1 : 0;
   // symmetric vectors: the whole pair-pair integral G [ldg][ldg] and the packed
   // vectors [P][ldg] (side v(v+1)/2 rounded to 4, pads zero) replace the packed
-  // build in the FP64 and FP32 pair-symmetric paths
-  const size_t es_g = precision == CC_LADDER_FP64 ? sizeof(double) : sizeof(float);
-  p.gsym = ((flags & CC_LADDER_SYMMETRIC_VECTORS) && (p.pairsym || p.pairsym_adj) &&
-            (precision == CC_LADDER_FP64 || precision == CC_LADDER_FP32)) ? 1 : 0;
+  // build in the FP64 and FP32 pair-symmetric paths and in the split-int8
+  // pair-symmetric forward (there G is float64, built from int8 digits of the
+  // packed vectors)
+  const size_t es_g = precision == CC_LADDER_FP32 ? sizeof(float) : sizeof(double);
+  p.gsym = ((flags & CC_LADDER_SYMMETRIC_VECTORS) &&
+            (((p.pairsym || p.pairsym_adj) &&
+              (precision == CC_LADDER_FP64 || precision == CC_LADDER_FP32)) ||
+             (p.pairsym && !p.backward && precision == CC_LADDER_SPLIT_INT8))) ? 1 : 0;
   if (p.gsym) p.ldg = static_cast<long long>((static_cast<size_t>(v) * (v + 1) / 2 + 3) / 4 * 4);
   if (p.exchange) {
     // the float32 form swaps while converting into its own operand copy; the
@@ -259,7 +263,9 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       // the kernels hold S + depth - 1 int32 sums per output: 5 at most
       if (p.slices + p.split_depth - 1 > 5) return CC_LADDER_EUNSUPPORTED;
       const size_t s = static_cast<size_t>(p.slices);  // one byte per digit
-      const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
+      // digits of the vectors' columns (a,c), or with symmetric vectors of the
+      // packed vectors' columns {a,c}, a <= c
+      const SliceDims dL = slice_dims(p.gsym ? p.ldg : static_cast<long long>(v2), P);
       const SliceDims dt = slice_dims(static_cast<long long>(o2), static_cast<int>(v2));
       const SliceDims dV = slice_dims(static_cast<long long>(rows), static_cast<int>(v2));
       p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad);

@@ -40,6 +40,14 @@ inline SliceDims slice_dims(long long rows, int K) {
   return d;
 }
 
+// Symmetric vectors (defined with the float64 path): Lp[x][pair(a,c)] =
+// L[x][a][c] for a <= c (row stride ldg, pads zero), and the block's packed
+// rows X_ab[c][d] = G[{a,c}][{b,d}] (a <= b, a from a0; row stride v^2)
+// gathered from the whole pair-pair integral G (row stride ldg).
+int pack_pair_vectors(const double* L, double* Lp, int P, int v, long long ldg, hipStream_t s);
+int gather_pair_rows(const double* G, long long ldg, long long nrows, int a0, int v, double* rows,
+                     hipStream_t s);
+
 int split_forward(const Plan& pl, const double* L, const double* t, double* R, char* ws,
                   const Tracer& tr, hipStream_t stream);
 int split_i8_forward(const Plan& pl, const double* L, const double* t, double* R, char* ws,

@@ -128,9 +128,11 @@ static void plan_invariants(const Plan& p, int backward, size_t budget) {
     }
   }
   if (p.gsym) {
-    // FP64/FP32 pair-symmetric paths; the compact grid's tile offsets come after G
+    // FP64/FP32 pair-symmetric paths and the split-int8 pair-symmetric forward;
+    // the compact grid's tile offsets come after G
     CHECK(p.pairsym || p.pairsym_adj);
-    CHECK(p.precision == CC_LADDER_FP64 || p.precision == CC_LADDER_FP32);
+    CHECK(p.precision == CC_LADDER_FP64 || p.precision == CC_LADDER_FP32 ||
+          (p.precision == CC_LADDER_SPLIT_INT8 && p.pairsym && !backward));
     CHECK(p.ldg % 4 == 0 && p.ldg >= static_cast<long long>(p.v) * (p.v + 1) / 2);
     CHECK(p.off_G > p.off_Lp && p.off_tiles > p.off_G);
   } else {

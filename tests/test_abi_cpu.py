@@ -419,7 +419,9 @@ def test_planner_symmetric_vectors_footprint(native):
 def test_symmetric_vectors_footprint_packed_forward_and_adjoint(native):
     # the packed forward and the pair-symmetric adjoint keep their buffers and add
     # the packed vectors and the pair-pair integral (the float32 forward drops its
-    # float32 copy of L); the split forms ignore the flag
+    # float32 copy of L); the split-int8 forward adds both in float64 and cuts its
+    # digits from the packed vectors' v(v+1)/2 columns instead of L's v^2; the
+    # split-bf16 form ignores the flag
     def r256(x):
         return (x + 255) // 256 * 256
 
@@ -439,6 +441,17 @@ def test_symmetric_vectors_footprint_packed_forward_and_adjoint(native):
                 want -= r256(P * v * v * 4)
             assert a == want, (prec, backward, a, want)
     kw = dict(a_block=n_a, pair_symmetric=True)
+    a, _ = native.cc_ladder_workspace_query(o, v, P, "split_int8",
+                                            opts=native.make_opts(symmetric_vectors=True, **kw))
+    b, _ = native.cc_ladder_workspace_query(o, v, P, "split_int8", opts=native.make_opts(**kw))
+
+    def digits(rows):  # five digit bytes per entry, rows padded past the last tile, K to 64
+        rows_pad = (rows + 127) // 128 * 128 + 128
+        return r256(5 * rows_pad * ((P + 63) // 64 * 64)) + r256(rows_pad * 4)
+
+    want = (b - digits(v * v) + digits(ldg) + r256(P * ldg * 8) + r256(ldg * ldg * 8)
+            - tiles_old + tiles_new)
+    assert a == want, ("split_int8", a, want)
     assert (native.cc_ladder_workspace_query(o, v, P, "split_bf16",
                                              opts=native.make_opts(symmetric_vectors=True, **kw))
             == native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(**kw)))

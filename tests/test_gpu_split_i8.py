@@ -96,6 +96,50 @@ def test_i8_pair_symmetric_and_exchange(gpu_lib, o, v, P, a_block):
     assert rel_fro(got, ref_x) < TOL[(5, 1)]
 
 
+@pytest.mark.parametrize("o,v,P,a_block,exchange", [
+    (5, 20, 75, 0, False), (9, 37, 101, 7, False), (4, 44, 131, 13, True), (3, 130, 17, 40, False),
+    (2, 3, 2, 0, False), (1, 1, 3, 0, False), (2, 12, 16500, 5, False)])
+def test_i8_symmetric_vectors(gpu_lib, o, v, P, a_block, exchange):
+    # symmetric vectors: the pair-pair integral G from the packed vectors' digits,
+    # then the block's packed rows gathered from it.  A column {a,c} of the packed
+    # vectors carries the digits and exponent of column (a,c) of L, so every
+    # element of G is the packed build's element bit for bit, and so is R;
+    # (2, 12, 16500): two exponent chunks of G's product (stored, then added)
+    announce("i8-symv", o, v, P, "a_block", a_block, "exchange", exchange)
+    L, t, _ = random_general(o, v, P, 650 + o + v)
+    L = 0.5 * (L + L.transpose(0, 2, 1))
+    t = 0.5 * (t + t.transpose(1, 0, 3, 2))
+    R0 = np.random.default_rng(13).standard_normal(t.shape)
+    kw = dict(a_block=a_block, pair_symmetric=True, exchange=exchange)
+    packed = run_i8(gpu_lib, L, t, R0, **kw)
+    got = run_i8(gpu_lib, L, t, R0, symmetric_vectors=True, **kw)
+    assert np.array_equal(got, packed)
+    ref = oracle.exchange_forward(L, t) if exchange else oracle.ladder_forward(L, t)
+    err = rel_fro(got - R0, ref)
+    print(f"CASE i8-symv error {err:.2e}", flush=True)
+    assert err < TOL[(5, 1)]
+
+
+def test_i8_symmetric_vectors_footprint(gpu_lib):
+    # G replaces the per-block packed build: the plan holds G and the packed
+    # vectors, and falls back to the packed build when they do not fit
+    o, v, P = 4, 60, 50
+    q = lambda **kw: gpu_lib.cc_ladder_workspace_query(  # noqa: E731
+        o, v, P, I8, opts=gpu_lib.make_opts(pair_symmetric=True, **kw))
+    plain, _ = q()
+    symv, _ = q(symmetric_vectors=True)
+    npv = v * (v + 1) // 2
+    assert symv >= plain + npv * npv * 8 - 3 * npv * 128 * 8
+    L, t, _ = random_general(o, v, P, 660)
+    L = 0.5 * (L + L.transpose(0, 2, 1))
+    t = 0.5 * (t + t.transpose(1, 0, 3, 2))
+    packed = run_i8(gpu_lib, L, t, np.zeros_like(t), pair_symmetric=True)
+    # a budget of G's own size: the symmetric-vector plan cannot fit, the packed one does
+    small = run_i8(gpu_lib, L, t, np.zeros_like(t), pair_symmetric=True, symmetric_vectors=True,
+                   hbm_budget=npv * npv * 8)
+    assert np.array_equal(small, packed)
+
+
 def test_i8_c1_workload(gpu_lib):
     o, v, P = CONFIGS["o5_v20_P75"]
     announce("i8-o5-v20-P75")
