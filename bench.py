@@ -44,13 +44,14 @@ METRIC = "ladder-residual TFLOP/s at o=40,v=360,P=1200: FP64 vs FP32/split-BF16 
 # V+- = (ac|bd) +- (ad|bc) over i <= j, a <= b, c <= d (pair-symmetric amplitudes);
 # the *_symv forms gather the packed rows (*_pairsym_symv) or V+- (*_pm_symv)
 # from the whole pair-pair integral of the workload's symmetric Cholesky vectors
-# (built over its upper triangle; in split_int8_pairsym_symv from int8 digits).
+# (built over its upper triangle; in the split forms from the packed vectors' digits).
 FORMS = {"fp64": ("fp64", 0, False, False), "fp32": ("fp32", 0, False, False),
          "split_bf16": ("split_bf16", 4, False, False),
          "split_bf16_s2": ("split_bf16", 2, False, False),
          "split_bf16_s3": ("split_bf16", 3, False, False),
          "fp64_pairsym": ("fp64", 0, True, False), "fp32_pairsym": ("fp32", 0, True, False),
          "split_bf16_pairsym": ("split_bf16", 4, True, False),
+         "split_bf16_pairsym_symv": ("split_bf16", 4, "sv", False),
          "fp64_pm": ("fp64", 0, "pm", False), "fp32_pm": ("fp32", 0, "pm", False),
          "fp64_pm_symv": ("fp64", 0, "pmv", False), "fp32_pm_symv": ("fp32", 0, "pmv", False),
          "fp64_pairsym_symv": ("fp64", 0, "sv", False), "fp32_pairsym_symv": ("fp32", 0, "sv", False),
@@ -580,7 +581,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(FORMS))
     ap.add_argument("--forms", default="fp64,fp32,split_bf16,split_int8,split_bf16_s2,fp64_pairsym,"
                                        "fp64_pairsym_symv,fp64_pm,fp32_pm,fp64_pm_symv,fp32_pm_symv,"
-                                       "split_bf16_pairsym,"
+                                       "split_bf16_pairsym,split_bf16_pairsym_symv,"
                                        "split_int8_pairsym,split_int8_pairsym_symv,fp64_exchange")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--budget-gib", type=float, default=128.0,

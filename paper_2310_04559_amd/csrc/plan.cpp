@@ -180,14 +180,15 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
   p.pm = (p.pairsym && (flags & CC_LADDER_PLUS_MINUS)) ? 1 : 0;
   // symmetric vectors: the whole pair-pair integral G [ldg][ldg] and the packed
   // vectors [P][ldg] (side v(v+1)/2 rounded to 4, pads zero) replace the packed
-  // build in the FP64 and FP32 pair-symmetric paths and in the split-int8
-  // pair-symmetric forward (there G is float64, built from int8 digits of the
-  // packed vectors)
+  // build in the FP64 and FP32 pair-symmetric paths and in the split
+  // pair-symmetric forwards (there G is float64, built from digits of the packed
+  // vectors)
   const size_t es_g = precision == CC_LADDER_FP32 ? sizeof(float) : sizeof(double);
   p.gsym = ((flags & CC_LADDER_SYMMETRIC_VECTORS) &&
             (((p.pairsym || p.pairsym_adj) &&
               (precision == CC_LADDER_FP64 || precision == CC_LADDER_FP32)) ||
-             (p.pairsym && !p.backward && precision == CC_LADDER_SPLIT_INT8))) ? 1 : 0;
+             (p.pairsym && !p.backward &&
+              (precision == CC_LADDER_SPLIT_INT8 || precision == CC_LADDER_SPLIT_BF16)))) ? 1 : 0;
   if (p.gsym) p.ldg = static_cast<long long>((static_cast<size_t>(v) * (v + 1) / 2 + 3) / 4 * 4);
   if (p.exchange) {
     // the float32 form swaps while converting into its own operand copy; the
@@ -244,7 +245,8 @@ int layout_plan(int o, int v, int P, int precision, int backward, int n_a,
       // automatic depth: the 4-slice form keeps the triangle's next anti-diagonal
       p.split_depth = depth ? depth : (p.slices == 4 ? 2 : 1);
       const size_t s = static_cast<size_t>(p.slices);
-      const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
+      // digits of L's columns (a,c), or of the packed vectors' columns {a,c}
+      const SliceDims dL = slice_dims(p.gsym ? p.ldg : static_cast<long long>(v2), P);
       const SliceDims dt = slice_dims(static_cast<long long>(o2), static_cast<int>(v2));
       const SliceDims dV = slice_dims(static_cast<long long>(rows), static_cast<int>(v2));
       p.off_L = take(&cur, s * dL.rows_pad * dL.k_pad * 2);

@@ -246,12 +246,13 @@ struct SplitArgs {
   int ea_stride, eb_stride;
   int M, N, Kp;
   void* C;           // EPI_ACC: float64 C[m*ldc + n] +=; EPI_PERM: float64 integral block;
-                     // EPI_PACK: packed rows a <= b of the block; EPI_PAIR: R (both mirrors)
+                     // EPI_PACK: packed rows a <= b of the block; EPI_PAIR: R (both mirrors);
+                     // EPI_SYM: float64 symmetric product C[m*ldc + n] of one operand with itself
   long long ldc;
   int v;
   int o;             // EPI_PAIR: occupied count (rows are (i,j))
   int a0;            // EPI_PACK/PAIR: first virtual of the integral block
-  const int* row_tiles;  // EPI_PACK compact grid: first linear tile of each tile row
+  const int* row_tiles;  // EPI_PACK/EPI_SYM compact grid: first linear tile of each tile row
   int tiles_m, tiles_n, group_m;
   int m_off;             // EPI_ACC/PAIR: output row of this product's row 0 (a remainder launch)
 };
@@ -332,12 +333,14 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
   // K-step of its next tile while the current tile drains; otherwise G covers
   // every tile once.
   const int G = gridDim.x;
-  const int ntiles = (EPI == EPI_PACK) ? g.row_tiles[g.tiles_m] : g.tiles_m * g.tiles_n;
+  constexpr bool kCompact = EPI == EPI_PACK || EPI == EPI_SYM;
+  const int ntiles = kCompact ? g.row_tiles[g.tiles_m] : g.tiles_m * g.tiles_n;
   const int lin0 = xcd_linear(blockIdx.x, G);
   auto coords = [&](int lin, int& m0, int& n0) {
     int tm, tn;
-    if (EPI == EPI_PACK) {
-      // compact grid over the tiles on or above the a = b diagonal
+    if (kCompact) {
+      // compact grid over the tiles on or above the a = b diagonal (EPI_SYM:
+      // v = 1, the tiles on or above the matrix diagonal)
       int lo = 0, hi = g.tiles_m - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -569,6 +572,13 @@ __global__ __launch_bounds__(64 * WAVES, 1) void split_gemm_kernel(SplitArgs g) 
           if (pa < al) continue;
           const long long row = pair_prefix_d(g.a0 + al, v) - pair_prefix_d(g.a0, v) + (pa - al);
           C[row * v * v + (long long)c * v + pb] = val;
+        } else if (EPI == EPI_SYM) {
+          // C[m][n] and its mirror C[n][m], from the element on or above the
+          // diagonal (A and B are one operand: the element below it in a
+          // diagonal tile holds the same value)
+          if (m > n) continue;
+          C[(long long)m * g.ldc + n] = val;
+          if (m < n) C[(long long)n * g.ldc + m] = val;
         } else {  // EPI_PAIR: R[i][j][a][b] and, for a != b, R[j][i][b][a]
           C[(long long)mo * g.ldc + (long long)pa * v + pb] += val;
           if (pa != pb) {
@@ -675,7 +685,7 @@ int launch_split_gemm(const SplitArgs& a0, hipStream_t s) {
   if (tiles > 0x7fffffffLL) return CC_LADDER_EINVAL;
   a.group_m = a.tiles_m < 16 ? a.tiles_m : 16;
   long long grid = tiles;
-  if (EPI == EPI_PACK) {
+  if (EPI == EPI_PACK || EPI == EPI_SYM) {
     if (!a.row_tiles) return CC_LADDER_EINVAL;
     long long needed = 0;
     for (int tm = 0; tm < a.tiles_m; ++tm) {
@@ -719,7 +729,10 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
                     const Tracer& tr, hipStream_t s) {
   const int o = pl.o, v = pl.v, P = pl.P;
   const long long v2 = (long long)v * v;
-  const SliceDims dL = slice_dims(static_cast<long long>(v2), P);
+  // with symmetric vectors the digit rows are the packed vectors' columns {a,c}
+  const bool gsym = pl.gsym != 0;
+  const long long npv = (long long)v * (v + 1) / 2;
+  const SliceDims dL = slice_dims(gsym ? pl.ldg : v2, P);
   const SliceDims dt = slice_dims((long long)o * o, static_cast<int>(v2));
   // integral rows of the largest block: n_a*v, or its packed rows a <= b
   const SliceDims dV = slice_dims(pl.pairsym ? pl.npk : (long long)pl.n_a * v,
@@ -733,11 +746,35 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
   int* Ve = reinterpret_cast<int*>(ws + pl.off_Vexp);
   const long long Lrow = (long long)dL.k_pad * S;  // digits per row of L's buffer
 
+  double* G = gsym ? reinterpret_cast<double*>(ws + pl.off_G) : nullptr;
   tr(CC_LADDER_PHASE_PREP, 0, 0);
-  int rc = slice_rc<S>(L, v2, static_cast<int>(v2), P, dL, Ls, Le, s);
+  int rc;
+  if (gsym) {
+    double* Lp = reinterpret_cast<double*>(ws + pl.off_Lp);
+    rc = pack_pair_vectors(L, Lp, P, v, pl.ldg, s);
+    if (!rc) rc = slice_rc<S>(Lp, pl.ldg, static_cast<int>(npv), P, dL, Ls, Le, s);
+  } else {
+    rc = slice_rc<S>(L, v2, static_cast<int>(v2), P, dL, Ls, Le, s);
+  }
   if (!rc) rc = slice_kc<S>(t, v2, o * o, static_cast<int>(v2), dt, ts, te, s);
   tr(CC_LADDER_PHASE_PREP, 0, 1);
   if (rc) return rc;
+  if (gsym) {
+    // the whole pair-pair integral G[p][q] = sum_x Lp[x][p] Lp[x][q] from the
+    // packed vectors' digits, the tiles on or above the diagonal (each result
+    // stored with its mirror); traced as the build of block 0
+    SplitArgs gg{};
+    gg.A = Ls; gg.ea = Le;
+    gg.B = Ls; gg.eb = Le;
+    gg.ea_stride = gg.eb_stride = 0;  // one exponent per row
+    gg.M = static_cast<int>(npv); gg.N = static_cast<int>(npv); gg.Kp = dL.k_pad;
+    gg.C = G; gg.ldc = pl.ldg; gg.v = 1; gg.a0 = 0;
+    gg.row_tiles = reinterpret_cast<const int*>(ws + pl.off_tiles);
+    tr(CC_LADDER_PHASE_BUILD, 0, 0);
+    rc = launch_split_gemm<S, D, EPI_SYM>(gg, s);
+    tr(CC_LADDER_PHASE_BUILD, 0, 1);
+    if (rc) return rc;
+  }
   for (int blk = 0; blk < pl.nblocks; ++blk) {
     int a0, na;
     block_range(pl, blk, &a0, &na);
@@ -746,15 +783,20 @@ int split_forward_s(const Plan& pl, const double* L, const double* t, double* R,
     if (pl.pairsym) {
       // packed rows (a,b), b >= a: columns (b,d) from b = a0 on
       const long long npairs = pair_prefix(a0 + na, v) - pair_prefix(a0, v);
-      SplitArgs b{};
-      b.A = Ls + r0 * Lrow; b.ea = Le + r0;
-      b.B = Ls + r0 * Lrow; b.eb = Le + r0;
-      b.ea_stride = b.eb_stride = 0;
-      b.M = na * v; b.N = static_cast<int>((long long)(v - a0) * v); b.Kp = dL.k_pad;
-      b.C = V; b.ldc = 0; b.v = v; b.a0 = a0;
-      b.row_tiles = reinterpret_cast<const int*>(ws + pl.off_tiles);
       tr(CC_LADDER_PHASE_BUILD, blk, 0);
-      rc = launch_split_gemm<S, D, EPI_PACK>(b, s);
+      if (gsym) {
+        // the block's packed rows gathered from G
+        rc = gather_pair_rows(G, pl.ldg, npairs, a0, v, V, s);
+      } else {
+        SplitArgs b{};
+        b.A = Ls + r0 * Lrow; b.ea = Le + r0;
+        b.B = Ls + r0 * Lrow; b.eb = Le + r0;
+        b.ea_stride = b.eb_stride = 0;
+        b.M = na * v; b.N = static_cast<int>((long long)(v - a0) * v); b.Kp = dL.k_pad;
+        b.C = V; b.ldc = 0; b.v = v; b.a0 = a0;
+        b.row_tiles = reinterpret_cast<const int*>(ws + pl.off_tiles);
+        rc = launch_split_gemm<S, D, EPI_PACK>(b, s);
+      }
       tr(CC_LADDER_PHASE_BUILD, blk, 1);
       if (rc) return rc;
       tr(CC_LADDER_PHASE_SLICE, blk, 0);

@@ -128,11 +128,12 @@ static void plan_invariants(const Plan& p, int backward, size_t budget) {
     }
   }
   if (p.gsym) {
-    // FP64/FP32 pair-symmetric paths and the split-int8 pair-symmetric forward;
+    // FP64/FP32 pair-symmetric paths and the split pair-symmetric forwards;
     // the compact grid's tile offsets come after G
     CHECK(p.pairsym || p.pairsym_adj);
     CHECK(p.precision == CC_LADDER_FP64 || p.precision == CC_LADDER_FP32 ||
-          (p.precision == CC_LADDER_SPLIT_INT8 && p.pairsym && !backward));
+          ((p.precision == CC_LADDER_SPLIT_INT8 || p.precision == CC_LADDER_SPLIT_BF16) &&
+           p.pairsym && !backward));
     CHECK(p.ldg % 4 == 0 && p.ldg >= static_cast<long long>(p.v) * (p.v + 1) / 2);
     CHECK(p.off_G > p.off_Lp && p.off_tiles > p.off_G);
   } else {

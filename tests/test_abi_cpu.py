@@ -419,9 +419,8 @@ def test_planner_symmetric_vectors_footprint(native):
 def test_symmetric_vectors_footprint_packed_forward_and_adjoint(native):
     # the packed forward and the pair-symmetric adjoint keep their buffers and add
     # the packed vectors and the pair-pair integral (the float32 forward drops its
-    # float32 copy of L); the split-int8 forward adds both in float64 and cuts its
-    # digits from the packed vectors' v(v+1)/2 columns instead of L's v^2; the
-    # split-bf16 form ignores the flag
+    # float32 copy of L); the split forwards add both in float64 and cut their
+    # digits from the packed vectors' v(v+1)/2 columns instead of L's v^2
     def r256(x):
         return (x + 255) // 256 * 256
 
@@ -445,16 +444,22 @@ def test_symmetric_vectors_footprint_packed_forward_and_adjoint(native):
                                             opts=native.make_opts(symmetric_vectors=True, **kw))
     b, _ = native.cc_ladder_workspace_query(o, v, P, "split_int8", opts=native.make_opts(**kw))
 
-    def digits(rows):  # five digit bytes per entry, rows padded past the last tile, K to 64
+    def digits(rows, nbytes):  # digit bytes per entry; rows padded past the last tile, K to 64
         rows_pad = (rows + 127) // 128 * 128 + 128
-        return r256(5 * rows_pad * ((P + 63) // 64 * 64)) + r256(rows_pad * 4)
+        return r256(nbytes * rows_pad * ((P + 63) // 64 * 64)) + r256(rows_pad * 4)
 
-    want = (b - digits(v * v) + digits(ldg) + r256(P * ldg * 8) + r256(ldg * ldg * 8)
+    want = (b - digits(v * v, 5) + digits(ldg, 5) + r256(P * ldg * 8) + r256(ldg * ldg * 8)
             - tiles_old + tiles_new)
     assert a == want, ("split_int8", a, want)
-    assert (native.cc_ladder_workspace_query(o, v, P, "split_bf16",
-                                             opts=native.make_opts(symmetric_vectors=True, **kw))
-            == native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(**kw)))
+    # split-bf16: four bf16 digits, one exponent per row; its compact grid's rows are 64 high
+    a, _ = native.cc_ladder_workspace_query(o, v, P, "split_bf16",
+                                            opts=native.make_opts(symmetric_vectors=True, **kw))
+    b, _ = native.cc_ladder_workspace_query(o, v, P, "split_bf16", opts=native.make_opts(**kw))
+    tiles64_old = r256(((n_a * v + 63) // 64 + 1) * 4)
+    tiles64_new = r256(((ldg + 63) // 64 + 1) * 4)
+    want = (b - digits(v * v, 8) + digits(ldg, 8) + r256(P * ldg * 8) + r256(ldg * ldg * 8)
+            - tiles64_old + tiles64_new)
+    assert a == want, ("split_bf16", a, want)
 
 
 def test_symmetric_vectors_needs_pair_symmetry(native):

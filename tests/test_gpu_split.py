@@ -133,6 +133,36 @@ def test_split_pair_symmetric_path(gpu_lib, o, v, P, a_block):
     assert rel_fro(got, oracle.ladder_forward(L, t)) < TOL_SPLIT[4]
 
 
+@pytest.mark.parametrize("o,v,P,a_block,slices,exchange", [
+    (5, 20, 75, 0, 4, False), (9, 37, 101, 7, 4, True), (4, 44, 131, 13, 3, False),
+    (3, 130, 17, 40, 4, False), (2, 3, 2, 0, 2, False), (1, 1, 3, 0, 4, False),
+    (2, 12, 700, 5, 4, False)])
+def test_split_symmetric_vectors(gpu_lib, o, v, P, a_block, slices, exchange):
+    # symmetric vectors: the pair-pair integral G from the packed vectors' digits,
+    # then the block's packed rows gathered from it.  A column {a,c} of the packed
+    # vectors carries the digits and exponent of column (a,c) of L, so G holds the
+    # packed build's digit products; the elements below the diagonal come from
+    # their mirrors, computed with the operands swapped, which adds the products
+    # (p, q) of the rounded shared accumulator (anti-diagonals g >= 2, scales
+    # <= 2^-16 of the leading one) in another order: the two results differ by
+    # that rounding only (4e-11 of R at o=5, v=20), held to a tenth of the
+    # scheme's tolerance
+    announce("split-symv", o, v, P, "a_block", a_block, "slices", slices, "exchange", exchange)
+    L, t, _ = random_general(o, v, P, 720 + o + v)
+    L = 0.5 * (L + L.transpose(0, 2, 1))
+    t = _pair_symmetric(t)
+    R0 = np.random.default_rng(15).standard_normal(t.shape)
+    kw = dict(a_block=a_block, pair_symmetric=True, exchange=exchange)
+    packed = run_split(gpu_lib, L, t, R0, slices, **kw)
+    got = run_split(gpu_lib, L, t, R0, slices, symmetric_vectors=True, **kw)
+    ref = oracle.exchange_forward(L, t) if exchange else oracle.ladder_forward(L, t)
+    diff = float(np.linalg.norm(got - packed) / np.linalg.norm(ref))
+    err = rel_fro(got - R0, ref)
+    print(f"CASE split-symv vs packed {diff:.2e} error {err:.2e}", flush=True)
+    assert diff < 0.1 * TOL_SPLIT[slices]
+    assert err < TOL_SPLIT[slices]
+
+
 def test_split_pair_symmetric_integer_exact(gpu_lib):
     announce("split-pairsym-int")
     L, t = integer_inputs(3, 10, 5, 77)

@@ -28,7 +28,8 @@ FORMS = [(0, 0, False, TOL[0]), (1, 0, False, TOL[1]), (2, 4, False, TOL_SPLIT_W
          (2, 2, False, TOL_SPLIT_WORKLOAD[2]), (0, 0, True, TOL[0]), (1, 0, True, TOL[1]),
          (2, 4, True, TOL_SPLIT_WORKLOAD[4]), (0, 0, "pm", TOL[0]), (1, 0, "pm", TOL[1]),
          (0, 0, "pmv", TOL[0]), (1, 0, "pmv", TOL[1]), (0, 0, "sv", TOL[0]), (1, 0, "sv", TOL[1]),
-         (3, 5, False, TOL[2]), (3, 5, True, TOL[2]), (3, 5, "sv", TOL[2])]
+         (3, 5, False, TOL[2]), (3, 5, True, TOL[2]), (3, 5, "sv", TOL[2]),
+         (2, 4, "sv", TOL_SPLIT_WORKLOAD[4])]
 
 
 def _check_forms(native, name, Ld, td, ref):
