@@ -140,12 +140,13 @@ typedef enum {
                                         quarter of the packed build's flops), and each block's
                                         packed rows (a,b), a <= b (or, with PLUS_MINUS, its V+-)
                                         are gathered from it.  FP64 and FP32, forward and
-                                        adjoint, and the split-int8 forward (G in float64 from
-                                        int8 digits of the packed vectors, equal bit for bit to
-                                        the packed build's integrals); split-bf16 ignores it.  G
-                                        is kept whole in scratch, a square of v(v+1)/2 (rounded
-                                        up to a multiple of 4) elements of the form's type
-                                        (float64 for split-int8; 34 GB in float64 at v = 360)
+                                        adjoint, and the split forwards (G in float64 from the
+                                        digits of the packed vectors: split-int8 equal bit for
+                                        bit to the packed build, split-bf16 up to the order of
+                                        its rounded low-order sums).  G is kept whole in
+                                        scratch, a square of v(v+1)/2 (rounded up to a multiple
+                                        of 4) elements of the form's type (float64 for the split
+                                        forms; 34 GB in float64 at v = 360)
                                         plus the packed vectors; when it does not fit the
                                         budget the flag changes nothing.  With CHECK_SYMMETRY, L
                                         is checked as well: EINVAL when some |L[x][a][c] -
